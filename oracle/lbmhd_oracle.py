@@ -1,0 +1,424 @@
+"""Plain FP64 NumPy oracle of the filtered LB-MHD timestep.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): never imported by the
+product path.
+
+Paper: Flint & Vahala, arXiv 1705.09807.  Citations name the paper's section
+and the LaTeX label of the equation (``feq``, ``FluidTMatrix``, ...).
+
+State and conventions
+---------------------
+* Periodic grid of ``nx`` x ``ny`` nodes at x = i, y = j (lattice units,
+  dx = dt = 1).  Arrays are indexed ``[..., y, x]``.
+* ``f[9, ny, nx]``: D2Q9 scalar distribution (filtered density, momentum).
+* ``g[5, 2, ny, nx]``: vector distribution on the D2Q5 subset of the same
+  velocities, ``g[i, alpha]`` = component alpha of g_i (filtered B).
+* The stored state at time t is post-streaming (what the next collision
+  consumes).  Two arrays, no in-place tricks.
+
+Readings of the paper used here (each is also listed in the design notes):
+* The magnetic distribution uses D2Q5 with weights (1/3, 1/6 x 4), the only
+  D2Q5 weights with c_s^2 = 1/3, which the resistivity formula of Sec. 2
+  (eta = 1/(3 s_m) - 1/6) requires.  The paper itself writes D2Q9 for g.
+* The magnetic equilibrium moments use u = rho u / rho (as in the g
+  equilibrium ``geq`` and the induction term of ``FinalMagnetic``), not the
+  momentum written in the ``MagMomentEq`` table.
+* The subgrid terms follow ``FilterExampleSmall`` applied to every nonlinear
+  equilibrium moment with filtered-density gradients dropped, as Sec. 3 does
+  for M3; the closure strength is Delta^2/12 times ``closure_scale`` (1 =
+  as printed in Sec. 3).
+* Gradients are synchronous (taken from the current post-streaming moments)
+  with a 3x3 isotropic stencil by default; diagnostics use central
+  differences.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Lattice constants (Sec. 2)
+# ---------------------------------------------------------------------------
+
+#: D2Q9 velocities, Sec. 2 (the lattice-vector equation after ``MagTMatrix``).
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=np.int64)
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=np.int64)
+
+#: D2Q9 weights.  Sec. 2 only says "appropriate lattice weights"; these are the
+#: weights for which T f^eq reproduces the ``KinMomentEq`` table (pinned by test).
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+#: D2Q5 weights for the vector distribution (first five D2Q9 velocities).
+W5 = np.array([1 / 3] + [1 / 6] * 4)
+
+
+def moment_matrix() -> np.ndarray:
+    """The 9x9 moment transform T built from its symbolic rows, Sec. 2
+    ``FluidTMatrix``: 1, c_x, c_y, c_x c_y, c_x^2 - c_y^2, 3 c_x c_y^2 - 2 c_x,
+    3 c_y c_x^2 - 2 c_y, 4 - 9 (c_x^2 + c_y^2 - 2 c_x^2 c_y^2),
+    4 - 4 (c_x^2 + c_y^2) + 3 c_x^2 c_y^2."""
+    cx = CX.astype(np.float64)
+    cy = CY.astype(np.float64)
+    one = np.ones(9)
+    rows = [
+        one,
+        cx,
+        cy,
+        cx * cy,
+        cx ** 2 - cy ** 2,
+        3 * cx * cy ** 2 - 2 * cx,
+        3 * cy * cx ** 2 - 2 * cy,
+        4 * one - 9 * (cx ** 2 + cy ** 2 - 2 * cx ** 2 * cy ** 2),
+        4 * one - 4 * (cx ** 2 + cy ** 2) + 3 * cx ** 2 * cy ** 2,
+    ]
+    return np.array(rows)
+
+
+T = moment_matrix()
+T_INV = np.linalg.inv(T)
+
+
+def relaxation_rates(nu: float, s5=None, s6=None, s7=None, s8=None) -> np.ndarray:
+    """Diagonal of the MRT rate matrix in moment space.
+
+    s3 = s4 from nu = 1/(3 s) - 1/6 (Sec. 2, viscosity formula).  The
+    conserved moments M0..M2 get rate 0.  Ghost rates s5..s8 default to s3,
+    i.e. the single-relaxation-time collision the runs of Sec. 3 use."""
+    s = 2.0 / (6.0 * nu + 1.0)
+    ghost = [s if v is None or v <= 0 else float(v) for v in (s5, s6, s7, s8)]
+    return np.array([0.0, 0.0, 0.0, s, s] + ghost)
+
+
+def magnetic_rate(eta: float) -> float:
+    """s_m from eta = 1/(3 s_m) - 1/6 (Sec. 2, resistivity formula)."""
+    return 2.0 / (6.0 * eta + 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Equilibria
+# ---------------------------------------------------------------------------
+
+
+def f_equilibrium(rho, mx, my, Bx, By) -> np.ndarray:
+    """f_i^(eq) of Sec. 2 ``feq``, population form, with u = rho u / rho."""
+    ux = mx / rho
+    uy = my / rho
+    usq = ux * ux + uy * uy
+    bsq = Bx * Bx + By * By
+    out = np.empty((9,) + np.shape(rho))
+    for i in range(9):
+        cu = CX[i] * ux + CY[i] * uy
+        cb = CX[i] * Bx + CY[i] * By
+        c2 = CX[i] ** 2 + CY[i] ** 2
+        out[i] = W9[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) \
+            + 4.5 * W9[i] * (0.5 * bsq * c2 - cb * cb)
+    return out
+
+
+def g_equilibrium(rho, mx, my, Bx, By) -> np.ndarray:
+    """Vector g_i^(eq) of Sec. 2 ``geq`` on D2Q5, with u = rho u / rho:
+    g_i = w'_i [B + 3 ((c_i.u) B - (c_i.B) u)]."""
+    ux = mx / rho
+    uy = my / rho
+    out = np.empty((5, 2) + np.shape(rho))
+    for i in range(5):
+        cu = CX[i] * ux + CY[i] * uy
+        cb = CX[i] * Bx + CY[i] * By
+        out[i, 0] = W5[i] * (Bx + 3.0 * (cu * Bx - cb * ux))
+        out[i, 1] = W5[i] * (By + 3.0 * (cu * By - cb * uy))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Periodic finite differences
+# ---------------------------------------------------------------------------
+
+
+def shifted(a, dx: int, dy: int):
+    """a(x + dx, y + dy) on the periodic grid."""
+    return np.roll(a, (-dy, -dx), axis=(-2, -1))
+
+
+def grad_iso9(a):
+    """3x3 isotropic gradient: D_x a = (a_E - a_W)/3 + (a_NE + a_SE - a_NW - a_SW)/12,
+    D_y likewise.  This is 3 sum_i w_i c_i a(x + c_i) with the D2Q9 weights; the
+    paper leaves the stencil open (Sec. 3, remark on derivatives)."""
+    e, w = shifted(a, 1, 0), shifted(a, -1, 0)
+    n, s = shifted(a, 0, 1), shifted(a, 0, -1)
+    ne, nw = shifted(a, 1, 1), shifted(a, -1, 1)
+    se, sw = shifted(a, 1, -1), shifted(a, -1, -1)
+    dx = (e - w) / 3.0 + (ne + se - nw - sw) / 12.0
+    dy = (n - s) / 3.0 + (ne + nw - se - sw) / 12.0
+    return dx, dy
+
+
+def grad_central(a):
+    """Central differences (a_E - a_W)/2, (a_N - a_S)/2."""
+    dx = (shifted(a, 1, 0) - shifted(a, -1, 0)) / 2.0
+    dy = (shifted(a, 0, 1) - shifted(a, 0, -1)) / 2.0
+    return dx, dy
+
+
+GRADIENTS = {"iso9": grad_iso9, "central5": grad_central}
+
+
+# ---------------------------------------------------------------------------
+# Filtered equilibria with the subgrid closure (Sec. 2.1 and Sec. 3)
+# ---------------------------------------------------------------------------
+
+
+def closure_terms(rho, mx, my, Bx, By, k2: float, stencil: str = "iso9"):
+    """Delta^2 corrections of the nonlinear equilibrium products.
+
+    ``FilterExampleSmall`` gives  bar(XY) = bar X bar Y + Delta^2/12 (d_b bar X)(d_b bar Y).
+    Applied with density gradients dropped (Sec. 3) to
+
+    * the Reynolds product  m_a m_c / rho  ->  + k2/rho (d_b m_a)(d_b m_c),
+    * the Maxwell product   B_a B_c        ->  + k2 (d_b B_a)(d_b B_c),
+    * the induction product m_a B_c / rho  ->  + k2/rho (d_b m_a)(d_b B_c),
+
+    with k2 = closure_scale * Delta^2 / 12.  Returns the dictionaries
+    ``P[a,c]`` = k2/rho (d_b m_a)(d_b m_c), ``Q[a,c]`` = k2 (d_b B_a)(d_b B_c) and
+    ``R[a,c]`` = k2/rho (d_b m_a)(d_b B_c) for a, c in {0 (x), 1 (y)}."""
+    grad = GRADIENTS[stencil]
+    gm = [grad(mx), grad(my)]       # gm[a][b] = D_b m_a
+    gb = [grad(Bx), grad(By)]       # gb[a][b] = D_b B_a
+    P, Q, R = {}, {}, {}
+    for a in range(2):
+        for c in range(2):
+            P[a, c] = k2 / rho * (gm[a][0] * gm[c][0] + gm[a][1] * gm[c][1])
+            Q[a, c] = k2 * (gb[a][0] * gb[c][0] + gb[a][1] * gb[c][1])
+            R[a, c] = k2 / rho * (gm[a][0] * gb[c][0] + gm[a][1] * gb[c][1])
+    return P, Q, R
+
+
+def filtered_equilibrium_moments(rho, mx, my, Bx, By, P, Q) -> np.ndarray:
+    """Filtered M_i^(eq), i = 0..8: the ``KinMomentEq`` table evaluated on the
+    filtered invariants (Sec. 2.1, filtered equilibrium moments) plus the
+    Delta^2 term of every nonlinear entry ("similarly for the other filtered
+    equilibrium moments", with the density-gradient terms dropped as in the
+    simplified M3 of Sec. 3).  M5, M6 are linear and get no correction."""
+    meq = np.empty((9,) + np.shape(rho))
+    meq[0] = rho
+    meq[1] = mx
+    meq[2] = my
+    # M3: rho u_x rho u_y / rho - B_x B_y  (Sec. 3, simplified M3)
+    meq[3] = mx * my / rho - Bx * By + P[0, 1] - Q[0, 1]
+    # M4: ((rho u_x)^2 - (rho u_y)^2)/rho - B_x^2 + B_y^2
+    meq[4] = (mx * mx - my * my) / rho - Bx * Bx + By * By \
+        + P[0, 0] - P[1, 1] - Q[0, 0] + Q[1, 1]
+    meq[5] = -mx
+    meq[6] = -my
+    # M7: -3 ((rho u_x)^2 + (rho u_y)^2)/rho
+    meq[7] = -3.0 * (mx * mx + my * my) / rho - 3.0 * (P[0, 0] + P[1, 1])
+    # M8: 5 rho/3 - 3 ((rho u_x)^2 + (rho u_y)^2)/rho
+    meq[8] = 5.0 * rho / 3.0 - 3.0 * (mx * mx + my * my) / rho - 3.0 * (P[0, 0] + P[1, 1])
+    return meq
+
+
+def filtered_induction(rho, mx, my, Bx, By, R) -> np.ndarray:
+    """Filtered first moments of g^(eq):  Lam[b, a] = sum_i c_ib g_ia^(eq)
+    = bar(u_b B_a - B_b u_a)  (``MagMomentEq`` N_a1, N_a2 with u in place of
+    rho u), each product filtered by ``FilterExampleSmall`` with density
+    gradients dropped: + R[b, a] - R[a, b]."""
+    m = (mx, my)
+    B = (Bx, By)
+    lam = np.empty((2, 2) + np.shape(rho))
+    for b in range(2):
+        for a in range(2):
+            lam[b, a] = (m[b] * B[a] - B[b] * m[a]) / rho + R[b, a] - R[a, b]
+    return lam
+
+
+def g_equilibrium_from_moments(Bx, By, lam) -> np.ndarray:
+    """Vector g^(eq) rebuilt from its zeroth moment B and first moments Lam on
+    D2Q5: g_ia = w'_i (B_a + 3 sum_b c_ib Lam[b, a])  (reproduces ``geq`` when
+    Lam is unfiltered, since sum_i w'_i c_ib c_ic = delta_bc / 3)."""
+    B = (Bx, By)
+    out = np.empty((5, 2) + np.shape(Bx))
+    for i in range(5):
+        for a in range(2):
+            out[i, a] = W5[i] * (B[a] + 3.0 * (CX[i] * lam[0, a] + CY[i] * lam[1, a]))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), counter form
+# ---------------------------------------------------------------------------
+
+_GOLDEN_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_MIX1 = np.uint64(0xBF58476D1CE4E5B9)
+_MIX2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, counter: np.ndarray) -> np.ndarray:
+    """Output number ``counter + 1`` of the SplitMix64 sequence started at
+    state ``seed``: z = seed + (counter + 1) * gamma, then the 64-bit finaliser
+    with shifts 30, 27, 31 and the two published multipliers."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (counter.astype(np.uint64) + np.uint64(1)) * _GOLDEN_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _MIX1
+        z = (z ^ (z >> np.uint64(27))) * _MIX2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_pm1(seed: int, counter: np.ndarray) -> np.ndarray:
+    """Uniform on [-1, 1): 2 * (top 53 bits * 2^-53) - 1."""
+    z = splitmix64(seed, counter)
+    u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return 2.0 * u - 1.0
+
+
+# ---------------------------------------------------------------------------
+# The oracle
+# ---------------------------------------------------------------------------
+
+
+class Oracle:
+    """Filtered LB-MHD on an nx x ny periodic grid, FP64, two-array state.
+
+    Parameters mirror the C ABI: nu, eta (transport coefficients), optional
+    MRT ghost rates s5..s8 (<= 0 or None: equal to s3), delta (filter width;
+    0 = DNS), closure_scale (multiplies Delta^2/12), grad_stencil ('iso9' or
+    'central5')."""
+
+    def __init__(self, nx: int, ny: int, nu: float, eta: float, delta: float = 0.0,
+                 closure_scale: float = 1.0, s5=None, s6=None, s7=None, s8=None,
+                 grad_stencil: str = "iso9"):
+        if nx < 4 or ny < 4:
+            raise ValueError("grid must be at least 4 x 4")
+        self.nx, self.ny = int(nx), int(ny)
+        self.nu, self.eta = float(nu), float(eta)
+        self.delta = float(delta)
+        self.closure_scale = float(closure_scale)
+        self.k2 = self.closure_scale * self.delta ** 2 / 12.0
+        self.rates = relaxation_rates(nu, s5, s6, s7, s8)
+        self.s_m = magnetic_rate(eta)
+        if not all(0.0 < r < 2.0 for r in list(self.rates[3:]) + [self.s_m]):
+            raise ValueError("relaxation rates must lie in (0, 2)")
+        self.grad_stencil = grad_stencil
+        self.f = np.zeros((9, self.ny, self.nx))
+        self.g = np.zeros((5, 2, self.ny, self.nx))
+        self.t = 0
+
+    # -- initial and injected states ------------------------------------
+    def init_kh_jet(self, U0=0.05, delta_over_L=0.05, B0=0.01, rho0=1.0,
+                    pert_amp_over_U0=1e-3, noise_amp=1e-5, seed=0):
+        """Double shear layer: u_x = U0 [tanh((y - L/4)/d) - tanh((y - 3L/4)/d) - 1]
+        with L = ny, d = delta_over_L * ny; u_y = pert * U0 sin(2 pi x / nx)
+        + noise_amp * xi with xi uniform on [-1, 1) from SplitMix64 on cell
+        index y * nx + x; B = (B0, 0); rho = rho0.  Populations start at the
+        unfiltered equilibria ``feq`` and ``geq`` (Sec. 2)."""
+        x = np.arange(self.nx, dtype=np.float64)[None, :]
+        y = np.arange(self.ny, dtype=np.float64)[:, None]
+        L = float(self.ny)
+        d = delta_over_L * L
+        ux = U0 * (np.tanh((y - L / 4.0) / d) - np.tanh((y - 3.0 * L / 4.0) / d) - 1.0)
+        ux = np.broadcast_to(ux, (self.ny, self.nx))
+        idx = (np.arange(self.ny, dtype=np.int64)[:, None] * self.nx
+               + np.arange(self.nx, dtype=np.int64)[None, :])
+        uy = pert_amp_over_U0 * U0 * np.sin(2.0 * math.pi * x / self.nx) \
+            + noise_amp * uniform_pm1(seed, idx)
+        rho = np.full((self.ny, self.nx), float(rho0))
+        Bx = np.full((self.ny, self.nx), float(B0))
+        By = np.zeros((self.ny, self.nx))
+        self.f = f_equilibrium(rho, rho * ux, rho * uy, Bx, By)
+        self.g = g_equilibrium(rho, rho * ux, rho * uy, Bx, By)
+        self.t = 0
+
+    def set_state(self, f, g, t: int = 0):
+        self.f = np.array(f, dtype=np.float64).reshape(9, self.ny, self.nx)
+        self.g = np.array(g, dtype=np.float64).reshape(5, 2, self.ny, self.nx)
+        self.t = int(t)
+
+    def state(self):
+        """(f, g, t): copies of the post-streaming populations at time t."""
+        return self.f.copy(), self.g.copy(), self.t
+
+    # -- the method ------------------------------------------------------
+    @staticmethod
+    def _moments(f, g):
+        """rho = sum f_i, rho u = sum c_i f_i, B = sum g_i (Sec. 2, after ``LBMagEqn``)."""
+        rho = f.sum(axis=0)
+        mx = np.tensordot(CX.astype(np.float64), f, axes=(0, 0))
+        my = np.tensordot(CY.astype(np.float64), f, axes=(0, 0))
+        Bx = g[:, 0].sum(axis=0)
+        By = g[:, 1].sum(axis=0)
+        return rho, mx, my, Bx, By
+
+    def moments(self):
+        """(rho, m_x, m_y, B_x, B_y) at the current time, each [ny, nx]."""
+        return self._moments(self.f, self.g)
+
+    def collide(self, f, g):
+        """One collision (Sec. 2 ``LBKinEqn``/``LBMagEqn``, Sec. 3): moments,
+        synchronous gradients, filtered equilibria, MRT relaxation of f in
+        moment space (``Transformation``), SRT relaxation of g.  Returns the
+        post-collision (f*, g*)."""
+        rho, mx, my, Bx, By = self._moments(f, g)
+        P, Q, R = closure_terms(rho, mx, my, Bx, By, self.k2, self.grad_stencil)
+        meq = filtered_equilibrium_moments(rho, mx, my, Bx, By, P, Q)
+        M = np.tensordot(T, f, axes=(1, 0))
+        mstar = M - self.rates[:, None, None] * (M - meq)
+        fstar = np.tensordot(T_INV, mstar, axes=(1, 0))
+        lam = filtered_induction(rho, mx, my, Bx, By, R)
+        geq = g_equilibrium_from_moments(Bx, By, lam)
+        gstar = g - self.s_m * (g - geq)
+        return fstar, gstar
+
+    @staticmethod
+    def stream(fstar, gstar):
+        """Streaming in population space: f_i(x + c_i, t + 1) = f*_i(x, t)."""
+        f = np.empty_like(fstar)
+        g = np.empty_like(gstar)
+        for i in range(9):
+            f[i] = np.roll(fstar[i], (CY[i], CX[i]), axis=(0, 1))
+        for i in range(5):
+            g[i] = np.roll(gstar[i], (CY[i], CX[i]), axis=(-2, -1))
+        return f, g
+
+    def step(self, n: int = 1):
+        for _ in range(int(n)):
+            fstar, gstar = self.collide(self.f, self.g)
+            self.f, self.g = self.stream(fstar, gstar)
+            self.t += 1
+
+    # -- diagnostics -------------------------------------------------------
+    def diagnostics(self) -> dict:
+        """Scalar diagnostics of the current state, FP64 with exact summation
+        (math.fsum).  Domain means: kinetic energy 1/2 |m|^2/rho, magnetic
+        energy 1/2 |B|^2, enstrophy 1/2 w^2 (w = D_x u_y - D_y u_x), current
+        J_z^2 (J_z = D_x B_y - D_y B_x); divergence D_x B_x + D_y B_y as max and
+        rms; raw sums of rho, m, B; count of non-finite cells.  D = central
+        differences."""
+        rho, mx, my, Bx, By = self.moments()
+        n = float(self.nx * self.ny)
+        ux, uy = mx / rho, my / rho
+        dux, duy = grad_central(ux), grad_central(uy)
+        dbx, dby = grad_central(Bx), grad_central(By)
+        omega = duy[0] - dux[1]
+        jz = dby[0] - dbx[1]
+        divb = dbx[0] + dby[1]
+        finite = np.isfinite(self.f).all(axis=0) & np.isfinite(self.g).all(axis=(0, 1))
+
+        def fs(a):
+            return math.fsum(np.ravel(a).tolist())
+
+        return {
+            "t": self.t,
+            "mass": fs(rho),
+            "mom_x": fs(mx),
+            "mom_y": fs(my),
+            "bsum_x": fs(Bx),
+            "bsum_y": fs(By),
+            "e_kin": fs(0.5 * (mx * mx + my * my) / rho) / n,
+            "e_mag": fs(0.5 * (Bx * Bx + By * By)) / n,
+            "enstrophy": fs(0.5 * omega * omega) / n,
+            "j2": fs(jz * jz) / n,
+            "divb_max": float(np.max(np.abs(divb))),
+            "divb_rms": math.sqrt(fs(divb * divb) / n),
+            "nonfinite": int(np.count_nonzero(~finite)),
+        }

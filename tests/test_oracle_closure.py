@@ -1,0 +1,110 @@
+"""Pins of the oracle's subgrid closure against brute-force filtering.
+
+``FilterExampleSmall`` (Sec. 2.1) states bar(XY) = bar X bar Y + Delta^2/12
+(d bar X)(d bar Y) + O(Delta^4).  A Gaussian filter of variance Delta^2/12 has
+exactly that second moment.  Filtering the unfiltered equilibrium moments of
+smooth fields by brute force (spectral convolution) and comparing with the
+oracle's closed-form filtered moments checks the constant 1/12, the sign of
+every Reynolds and Maxwell term and which moment each one enters.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import lbmhd_oracle as O
+from seeded_inputs import smooth_field, perturbed, offset_noise
+
+N = 256
+RHO = 1.3
+
+
+def _fields():
+    return [smooth_field(N, N, s, kmax=3, amp=a)
+            for s, a in ((1, 0.08), (2, 0.06), (3, 0.05), (4, 0.04))]
+
+
+def _gauss(a, delta):
+    k = 2 * np.pi * np.fft.fftfreq(N)
+    k2 = k[None, :] ** 2 + k[:, None] ** 2
+    return np.real(np.fft.ifft2(np.fft.fft2(a) * np.exp(-k2 * delta * delta / 24.0)))
+
+
+def _errors(delta):
+    rho = np.full((N, N), RHO)
+    mx, my, bx, by = _fields()
+    # brute force: filter the unfiltered equilibrium moments (population route)
+    exact = np.tensordot(O.T, O.f_equilibrium(rho, mx, my, bx, by), axes=(1, 0))
+    exact = np.array([_gauss(exact[k], delta) for k in range(9)])
+    u = (mx / rho, my / rho)
+    b = (bx, by)
+    lam_exact = np.array([[_gauss(u[p] * b[a] - b[p] * u[a], delta) for a in range(2)]
+                          for p in range(2)])
+    fm = [_gauss(a, delta) for a in (mx, my, bx, by)]
+    P, Q, R = O.closure_terms(rho, *fm, delta * delta / 12.0)
+    zero = {(a, c): 0.0 * rho for a in range(2) for c in range(2)}
+    with_c = O.filtered_equilibrium_moments(rho, *fm, P, Q)
+    without = O.filtered_equilibrium_moments(rho, *fm, zero, zero)
+    lam_c = O.filtered_induction(rho, *fm, R)
+    lam_0 = O.filtered_induction(rho, *fm, zero)
+    ratios = {}
+    for k in (3, 4, 7, 8):
+        ratios[k] = np.abs(with_c[k] - exact[k]).max() / np.abs(without[k] - exact[k]).max()
+    ratios["lam_xy"] = np.abs(lam_c[0, 1] - lam_exact[0, 1]).max() / np.abs(lam_0[0, 1] - lam_exact[0, 1]).max()
+    ratios["lam_yx"] = np.abs(lam_c[1, 0] - lam_exact[1, 0]).max() / np.abs(lam_0[1, 0] - lam_exact[1, 0]).max()
+    # linear moments are untouched by filtering
+    for k in (0, 1, 2, 5, 6):
+        assert np.allclose(with_c[k], exact[k], atol=1e-13, rtol=0)
+    return ratios
+
+
+def test_closure_matches_bruteforce_gaussian_filter():
+    small = _errors(4.0)
+    for key, r in small.items():
+        assert r < 0.01, (key, r)
+    r8, r16 = _errors(8.0), _errors(16.0)
+    for key in r8:
+        # the remaining error is O(Delta^4): relative to O(Delta^2) it grows ~4x per doubling
+        assert 3.0 < r16[key] / r8[key] < 5.0, (key, r8[key], r16[key])
+
+
+def test_closure_is_exactly_linear_in_delta_squared():
+    """One step from the same state: (f(Delta) - f(0)) is linear in Delta^2 up
+    to rounding, and Delta = 0 reproduces the unfiltered step bit for bit."""
+    nx, ny = 16, 12
+    f = perturbed(O.W9, (9, ny, nx), 5, 0.15)
+    g = offset_noise(np.zeros(10), (10, ny, nx), 6, 0.01).reshape(5, 2, ny, nx)
+    out = {}
+    for d in (0.0, 1.0, 2.0):
+        o = O.Oracle(nx, ny, 0.02, 0.02, delta=d)
+        o.set_state(f, g)
+        o.step(1)
+        out[d] = o.state()
+    d1 = out[1.0][0] - out[0.0][0]
+    d2 = out[2.0][0] - out[0.0][0]
+    assert np.abs(d1).max() > 1e-6
+    assert np.allclose(d2, 4 * d1, atol=1e-15, rtol=1e-9)
+    g1 = out[1.0][1] - out[0.0][1]
+    g2 = out[2.0][1] - out[0.0][1]
+    assert np.abs(g1).max() > 1e-9
+    assert np.allclose(g2, 4 * g1, atol=1e-16, rtol=1e-9)
+    # closure_scale multiplies Delta^2
+    o = O.Oracle(nx, ny, 0.02, 0.02, delta=1.0, closure_scale=4.0)
+    o.set_state(f, g)
+    o.step(1)
+    assert np.allclose(o.state()[0], out[2.0][0], atol=1e-16, rtol=0)
+
+
+def test_iso9_gradient_symbol():
+    """The 3x3 stencil acting on exp(i k.x) multiplies it by
+    i sin(k_x) (2 + cos k_y) / 3 (x component); central by i sin(k_x)."""
+    n = 32
+    x = np.arange(n)[None, :]
+    y = np.arange(n)[:, None]
+    kx, ky = 2 * np.pi * 3 / n, 2 * np.pi * 5 / n
+    a = np.exp(1j * (kx * x + ky * y))
+    dx, dy = O.grad_iso9(a)
+    assert np.allclose(dx, 1j * np.sin(kx) * (2 + np.cos(ky)) / 3 * a, atol=1e-14)
+    assert np.allclose(dy, 1j * np.sin(ky) * (2 + np.cos(kx)) / 3 * a, atol=1e-14)
+    cx, cy = O.grad_central(a)
+    assert np.allclose(cx, 1j * np.sin(kx) * a, atol=1e-14)
+    assert np.allclose(cy, 1j * np.sin(ky) * a, atol=1e-14)
