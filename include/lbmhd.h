@@ -1,0 +1,162 @@
+/*
+ * lbmhd.h -- C ABI of the MI355X (gfx950) filtered lattice-Boltzmann MHD engine.
+ *
+ * Method: Flint & Vahala, "A large eddy lattice Boltzmann simulation of
+ * magnetohydrodynamic turbulence" (arXiv 1705.09807).  One timestep is the
+ * collide-stream operator split of Sec. 2 (kinetic equations LBKinEqn and
+ * LBMagEqn): moments, filtered equilibrium moments with the Delta^2/12
+ * subgrid closure of Sec. 2.1 / Sec. 3 (density gradients dropped),
+ * collision of the D2Q9 scalar f in moment space (FluidTMatrix, MRT rates),
+ * SRT collision of the vector distribution g (D2Q5 here), streaming in
+ * population space.  Periodic nx x ny lattice, lattice units.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: 0 (LBM_OK) or a negative LBM_E* code.  Nothing throws
+ *    across the ABI.  On error, lbm_last_error() returns a message (thread
+ *    local) and the context is left unchanged unless stated otherwise.
+ *  - Ownership: the caller allocates and frees every device buffer (state,
+ *    work, outputs).  The library never allocates or frees device memory.
+ *    lbm_ctx is a host object owned by the library, released by lbm_destroy.
+ *  - Streams: every call runs on the hipStream_t given to lbm_create and is
+ *    asynchronous with respect to the host, except lbm_diagnostics, which
+ *    synchronises that stream.
+ *  - Device pointers must be 256-byte aligned.
+ *  - Natural layout: a field array is [plane][y][x], x fastest, dense
+ *    (row pitch nx, plane stride nx*ny).  Populations are ordered
+ *    f_0..f_8, g_x0..g_x4, g_y0..g_y4 (19 planes), with the D2Q9
+ *    velocities c_x = {0,1,0,-1,0,1,-1,-1,1}, c_y = {0,0,1,0,-1,1,1,-1,-1}
+ *    of Sec. 2 (g uses the first five).  "State at time t" means the
+ *    post-streaming populations the next collision consumes.
+ *  - Threading: a context is used by one host thread at a time.
+ */
+#ifndef LBMHD_H
+#define LBMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)      /* bad parameter, null / misaligned pointer, size */
+#define LBM_ESTATE (-2)      /* call out of order (e.g. step before init)      */
+#define LBM_EHIP (-3)        /* HIP runtime error; message in lbm_last_error   */
+#define LBM_ENONFINITE (-4)  /* diagnostics found NaN/Inf populations          */
+
+/* Storage precision of the populations (arithmetic: FP64 for LBM_FP64, FP32
+ * otherwise).  LBM_FP32 stores f as the deviation f_i - w_i rho0 from the
+ * rest equilibrium; LBM_FP64 stores f_i itself (exact state round trips);
+ * g is stored as is. */
+#define LBM_FP64 0
+#define LBM_FP32 1
+
+/* Discrete gradient used by the closure. */
+#define LBM_STENCIL_ISO9 0      /* (a_E-a_W)/3 + (a_NE+a_SE-a_NW-a_SW)/12 */
+#define LBM_STENCIL_CENTRAL5 1  /* (a_E-a_W)/2                             */
+
+/* Memory schedule of the timestep. */
+#define LBM_SCHED_FUSED 0  /* two population buffers, one fused sweep per step */
+#define LBM_SCHED_AA 1     /* one buffer updated in place (AA pattern); with the
+                              closure on, a moment sweep precedes the collide sweep */
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Run parameters, lattice units.  Rates follow Sec. 2: s3 = s4 = 2/(6 nu + 1)
+ * (from nu = 1/(3 s) - 1/6), s_m = 2/(6 eta + 1); s0..s2 = 0 (conserved). */
+typedef struct {
+  int32_t nx, ny;          /* periodic grid, each >= 4 and <= 65536           */
+  double nu, eta;          /* > 0, giving rates in (0, 2)                     */
+  double s5, s6, s7, s8;   /* MRT ghost rates in (0, 2); <= 0 means "= s3",
+                              i.e. the single-relaxation-time runs of Sec. 3 */
+  double delta;            /* filter width Delta >= 0; 0 = unfiltered (DNS)   */
+  double closure_scale;    /* multiplies Delta^2/12; 1 = as printed in Sec. 3 */
+  int32_t grad_stencil;    /* LBM_STENCIL_*                                   */
+  int32_t dtype;           /* LBM_FP64 or LBM_FP32                            */
+  int32_t schedule;        /* LBM_SCHED_*                                     */
+  int32_t reserved;        /* must be 0                                       */
+  double rho0;             /* reference density of the FP32 deviations, > 0   */
+} lbm_params;
+
+/* Double-shear-layer Kelvin-Helmholtz jet: u_x = U0 [tanh((y - L/4)/d)
+ * - tanh((y - 3L/4)/d) - 1] with L = ny, d = delta_over_L * ny;
+ * u_y = pert_amp_over_U0 * U0 * sin(2 pi x / nx) + noise_amp * xi(x, y);
+ * B = (B0, 0); rho = rho0.  xi is uniform on [-1, 1): output number
+ * (y*nx + x + 1) of SplitMix64 (Steele, Lea & Flood 2014) started at `seed`,
+ * top 53 bits scaled by 2^-53, mapped by 2u - 1.  Populations start at the
+ * unfiltered equilibria feq / geq of Sec. 2. */
+typedef struct {
+  double U0, delta_over_L, B0, rho0, pert_amp_over_U0, noise_amp;
+  uint64_t seed;
+} lbm_kh_params;
+
+/* Scalar diagnostics, FP64 on the device.  Domain means: e_kin = <|m|^2/(2 rho)>,
+ * e_mag = <|B|^2/2>, enstrophy = <w^2/2> with w = D_x u_y - D_y u_x,
+ * j2 = <J_z^2> with J_z = D_x B_y - D_y B_x; D = central differences.
+ * divb = D_x B_x + D_y B_y as max |.| and rms.  Raw sums of rho, m, B. */
+typedef struct {
+  int64_t t;
+  double mass, mom_x, mom_y, bsum_x, bsum_y;
+  double e_kin, e_mag, enstrophy, j2, divb_max, divb_rms;
+  int64_t nonfinite;       /* cells with a non-finite population */
+} lbm_diag;
+
+/* Bytes of the caller-owned device buffers for these parameters (0 if the
+ * parameters are invalid).  The state holds the populations in the storage
+ * precision, one buffer (AA) or two (fused); the work buffer holds moment
+ * planes and reduction partials. */
+size_t lbm_state_bytes(const lbm_params* p);
+size_t lbm_work_bytes(const lbm_params* p);
+
+/* Validate p, derive the rates and bind the buffers and stream.  No device
+ * work is enqueued.  state_dev / work_dev: >= lbm_*_bytes(p) bytes, 256-byte
+ * aligned, caller owned, alive until lbm_destroy.  hip_stream: a
+ * hipStream_t (NULL = the null stream).  The state is uninitialised until
+ * lbm_init_kh_jet or lbm_set_state. */
+int lbm_create(lbm_ctx** out, const lbm_params* p, void* state_dev, void* work_dev,
+               void* hip_stream);
+
+/* Write the Kelvin-Helmholtz initial state (see lbm_kh_params); t = 0. */
+int lbm_init_kh_jet(lbm_ctx* ctx, const lbm_kh_params* kh);
+
+/* Advance n >= 0 timesteps of Sec. 2 / Sec. 3 (collide in moment space,
+ * stream).  Gradients of the closure are taken from the moments of the state
+ * at the start of each step (synchronous). */
+int lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Current time t. */
+int lbm_get_time(const lbm_ctx* ctx, int64_t* t_out);
+
+/* Macroscopic fields of the state at time t into out_dev: 5 FP64 planes
+ * rho, m_x = rho u_x, m_y, B_x, B_y (natural layout, 5*nx*ny doubles,
+ * caller owned).  Sec. 2: rho = sum f_i, rho u = sum c_i f_i, B = sum g_i. */
+int lbm_moments(lbm_ctx* ctx, double* out_dev);
+
+/* Copy the populations of the state at time t to out_dev as 19 FP64 planes
+ * in natural layout (19*nx*ny doubles, caller owned). */
+int lbm_get_state(lbm_ctx* ctx, double* out_dev);
+
+/* Replace the state by 19 FP64 planes in natural layout (rounded to the
+ * storage precision) and set the time to t >= 0. */
+int lbm_set_state(lbm_ctx* ctx, const double* in_dev, int64_t t);
+
+/* Compute the diagnostics of the state at time t into *out_host (host
+ * memory); synchronises the stream.  Returns LBM_ENONFINITE, with *out_host
+ * filled, when a population is NaN or infinite. */
+int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out_host);
+
+/* Release the context (not the caller's buffers).  NULL is accepted. */
+int lbm_destroy(lbm_ctx* ctx);
+
+/* Static description of an error code; the calling thread's last error. */
+const char* lbm_strerror(int code);
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMHD_H */

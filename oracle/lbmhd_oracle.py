@@ -273,6 +273,35 @@ def uniform_pm1(seed: int, counter: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Kelvin-Helmholtz initial state
+# ---------------------------------------------------------------------------
+
+
+def kh_jet_populations(x, y, nx, ny, U0=0.05, delta_over_L=0.05, B0=0.01, rho0=1.0,
+                       pert_amp_over_U0=1e-3, noise_amp=1e-5, seed=0):
+    """Initial populations at integer nodes (x, y) (arrays of equal shape) of
+    an nx x ny grid.  Double shear layer u_x = U0 [tanh((y - L/4)/d) -
+    tanh((y - 3L/4)/d) - 1] with L = ny, d = delta_over_L * ny;
+    u_y = pert * U0 sin(2 pi x / nx) + noise_amp * xi, xi uniform on [-1, 1)
+    from SplitMix64 on the cell index y * nx + x; B = (B0, 0); rho = rho0.
+    Populations are the unfiltered equilibria ``feq`` and ``geq`` (Sec. 2).
+    Returns (f[9, ...], g[5, 2, ...])."""
+    x = np.asarray(x, dtype=np.int64)
+    y = np.asarray(y, dtype=np.int64)
+    L = float(ny)
+    d = delta_over_L * L
+    yf = y.astype(np.float64)
+    ux = U0 * (np.tanh((yf - L / 4.0) / d) - np.tanh((yf - 3.0 * L / 4.0) / d) - 1.0)
+    uy = pert_amp_over_U0 * U0 * np.sin(2.0 * math.pi * x.astype(np.float64) / nx) \
+        + noise_amp * uniform_pm1(seed, y * nx + x)
+    rho = np.full(x.shape, float(rho0))
+    bx = np.full(x.shape, float(B0))
+    by = np.zeros(x.shape)
+    return (f_equilibrium(rho, rho * ux, rho * uy, bx, by),
+            g_equilibrium(rho, rho * ux, rho * uy, bx, by))
+
+
+# ---------------------------------------------------------------------------
 # The oracle
 # ---------------------------------------------------------------------------
 
@@ -307,26 +336,12 @@ class Oracle:
     # -- initial and injected states ------------------------------------
     def init_kh_jet(self, U0=0.05, delta_over_L=0.05, B0=0.01, rho0=1.0,
                     pert_amp_over_U0=1e-3, noise_amp=1e-5, seed=0):
-        """Double shear layer: u_x = U0 [tanh((y - L/4)/d) - tanh((y - 3L/4)/d) - 1]
-        with L = ny, d = delta_over_L * ny; u_y = pert * U0 sin(2 pi x / nx)
-        + noise_amp * xi with xi uniform on [-1, 1) from SplitMix64 on cell
-        index y * nx + x; B = (B0, 0); rho = rho0.  Populations start at the
-        unfiltered equilibria ``feq`` and ``geq`` (Sec. 2)."""
-        x = np.arange(self.nx, dtype=np.float64)[None, :]
-        y = np.arange(self.ny, dtype=np.float64)[:, None]
-        L = float(self.ny)
-        d = delta_over_L * L
-        ux = U0 * (np.tanh((y - L / 4.0) / d) - np.tanh((y - 3.0 * L / 4.0) / d) - 1.0)
-        ux = np.broadcast_to(ux, (self.ny, self.nx))
-        idx = (np.arange(self.ny, dtype=np.int64)[:, None] * self.nx
-               + np.arange(self.nx, dtype=np.int64)[None, :])
-        uy = pert_amp_over_U0 * U0 * np.sin(2.0 * math.pi * x / self.nx) \
-            + noise_amp * uniform_pm1(seed, idx)
-        rho = np.full((self.ny, self.nx), float(rho0))
-        Bx = np.full((self.ny, self.nx), float(B0))
-        By = np.zeros((self.ny, self.nx))
-        self.f = f_equilibrium(rho, rho * ux, rho * uy, Bx, By)
-        self.g = g_equilibrium(rho, rho * ux, rho * uy, Bx, By)
+        """Kelvin-Helmholtz double shear layer on the whole grid at t = 0
+        (see ``kh_jet_populations``)."""
+        x = np.arange(self.nx, dtype=np.int64)[None, :] * np.ones((self.ny, 1), dtype=np.int64)
+        y = np.arange(self.ny, dtype=np.int64)[:, None] * np.ones((1, self.nx), dtype=np.int64)
+        self.f, self.g = kh_jet_populations(x, y, self.nx, self.ny, U0, delta_over_L, B0, rho0,
+                                            pert_amp_over_U0, noise_amp, seed)
         self.t = 0
 
     def set_state(self, f, g, t: int = 0):
@@ -357,13 +372,17 @@ class Oracle:
         """One collision (Sec. 2 ``LBKinEqn``/``LBMagEqn``, Sec. 3): moments,
         synchronous gradients, filtered equilibria, MRT relaxation of f in
         moment space (``Transformation``), SRT relaxation of g.  Returns the
-        post-collision (f*, g*)."""
+        post-collision (f*, g*).
+
+        The f collision is the right-hand side of ``LBKinEqn`` with the rate
+        tensor s' = T^-1 S T:  f* = f + s' (f^eq - f) = f - T^-1 S (M - M^eq),
+        M = T f.  Relaxation acts on the moments; conserved moments (rate 0)
+        contribute nothing."""
         rho, mx, my, Bx, By = self._moments(f, g)
         P, Q, R = closure_terms(rho, mx, my, Bx, By, self.k2, self.grad_stencil)
         meq = filtered_equilibrium_moments(rho, mx, my, Bx, By, P, Q)
         M = np.tensordot(T, f, axes=(1, 0))
-        mstar = M - self.rates[:, None, None] * (M - meq)
-        fstar = np.tensordot(T_INV, mstar, axes=(1, 0))
+        fstar = f - np.tensordot(T_INV, self.rates[:, None, None] * (M - meq), axes=(1, 0))
         lam = filtered_induction(rho, mx, my, Bx, By, R)
         geq = g_equilibrium_from_moments(Bx, By, lam)
         gstar = g - self.s_m * (g - geq)

@@ -1,0 +1,233 @@
+// C ABI of the filtered LB-MHD engine: parameter validation, rates, buffer
+// binding, time/parity bookkeeping and error reporting.  The per-cell
+// arithmetic and all device work live in lbmhd_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbmhd.h"
+#include "lbmhd_internal.h"
+
+struct lbm_ctx {
+  lbm_params p;
+  lbm::Launch L;
+  int64_t t = 0;
+  bool initialized = false;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(LBM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Validate and derive rates.  Returns LBM_OK or LBM_EINVAL with a message.
+int check_params(const lbm_params* p, lbm::Launch* L) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->nx < 4 || p->ny < 4 || p->nx > 65536 || p->ny > 65536)
+    return fail(LBM_EINVAL, "nx and ny must lie in [4, 65536]");
+  if ((int64_t)p->nx * (int64_t)p->ny > (int64_t)1 << 31)
+    return fail(LBM_EINVAL, "nx*ny must not exceed 2^31 cells");
+  if (!finite_pos(p->nu) || !finite_pos(p->eta)) return fail(LBM_EINVAL, "nu and eta must be finite and > 0");
+  const double ghost[4] = {p->s5, p->s6, p->s7, p->s8};
+  for (double g : ghost) {
+    if (!std::isfinite(g)) return fail(LBM_EINVAL, "ghost rates must be finite");
+    if (g > 0.0 && g >= 2.0) return fail(LBM_EINVAL, "ghost rates must lie in (0, 2) (or <= 0 for s3)");
+  }
+  if (!std::isfinite(p->delta) || p->delta < 0.0) return fail(LBM_EINVAL, "delta must be finite and >= 0");
+  if (!std::isfinite(p->closure_scale)) return fail(LBM_EINVAL, "closure_scale must be finite");
+  if (p->grad_stencil != LBM_STENCIL_ISO9 && p->grad_stencil != LBM_STENCIL_CENTRAL5)
+    return fail(LBM_EINVAL, "grad_stencil must be LBM_STENCIL_ISO9 or LBM_STENCIL_CENTRAL5");
+  if (p->dtype != LBM_FP64 && p->dtype != LBM_FP32) return fail(LBM_EINVAL, "dtype must be LBM_FP64 or LBM_FP32");
+  if (p->schedule != LBM_SCHED_FUSED && p->schedule != LBM_SCHED_AA)
+    return fail(LBM_EINVAL, "schedule must be LBM_SCHED_FUSED or LBM_SCHED_AA");
+  if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+  if (!finite_pos(p->rho0)) return fail(LBM_EINVAL, "rho0 must be finite and > 0");
+  if (L) {
+    // nu = 1/(3 s) - 1/6, eta = 1/(3 s_m) - 1/6 (Sec. 2); nu, eta > 0 put s in (0, 2).
+    const double s = 2.0 / (6.0 * p->nu + 1.0);
+    L->nx = p->nx;
+    L->ny = p->ny;
+    L->plane = lbm::plane_elems(p->nx, p->ny);
+    L->dtype = p->dtype;
+    L->schedule = p->schedule;
+    L->stencil = p->grad_stencil;
+    for (double& r : L->rate) r = 0.0;
+    L->rate[3] = s;
+    L->rate[4] = s;
+    for (int k = 0; k < 4; ++k) L->rate[5 + k] = ghost[k] > 0.0 ? ghost[k] : s;
+    L->sm = 2.0 / (6.0 * p->eta + 1.0);
+    L->k2 = p->closure_scale * p->delta * p->delta / 12.0;
+    // FP32 stores f_i - w_i rho0 (the small dynamic part keeps its digits);
+    // FP64 stores f_i itself, so natural-layout state IO round-trips exactly.
+    L->rho0 = p->dtype == LBM_FP64 ? 0.0 : p->rho0;
+  }
+  return LBM_OK;
+}
+
+bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 255u) == 0; }
+
+int check_ctx(const lbm_ctx* ctx, bool need_state) {
+  if (!ctx) return fail(LBM_EINVAL, "context is NULL");
+  if (need_state && !ctx->initialized)
+    return fail(LBM_ESTATE, "state not initialised: call lbm_init_kh_jet or lbm_set_state first");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_state_bytes(const lbm_params* p) {
+  if (check_params(p, nullptr) != LBM_OK) return 0;
+  return lbm::state_bytes(p->nx, p->ny, p->dtype, p->schedule);
+}
+
+size_t lbm_work_bytes(const lbm_params* p) {
+  lbm::Launch L;
+  if (check_params(p, &L) != LBM_OK) return 0;
+  return lbm::work_layout(L);
+}
+
+int lbm_create(lbm_ctx** out, const lbm_params* p, void* state_dev, void* work_dev, void* hip_stream) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm::Launch L;
+  int rc = check_params(p, &L);
+  if (rc != LBM_OK) return rc;
+  if (!state_dev || !work_dev) return fail(LBM_EINVAL, "state and work buffers must not be NULL");
+  if (!aligned(state_dev) || !aligned(work_dev)) return fail(LBM_EINVAL, "device buffers must be 256-byte aligned");
+  lbm::work_layout(L);
+  L.state = state_dev;
+  L.work = work_dev;
+  L.stream = static_cast<hipStream_t>(hip_stream);
+  lbm_ctx* ctx = new (std::nothrow) lbm_ctx;
+  if (!ctx) return fail(LBM_EINVAL, "out of host memory");
+  ctx->p = *p;
+  ctx->L = L;
+  *out = ctx;
+  return LBM_OK;
+}
+
+int lbm_init_kh_jet(lbm_ctx* ctx, const lbm_kh_params* kh) {
+  int rc = check_ctx(ctx, false);
+  if (rc != LBM_OK) return rc;
+  if (!kh) return fail(LBM_EINVAL, "kh params are NULL");
+  const double vals[6] = {kh->U0, kh->delta_over_L, kh->B0, kh->rho0, kh->pert_amp_over_U0, kh->noise_amp};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(LBM_EINVAL, "kh params must be finite");
+  if (!(kh->delta_over_L > 0.0) || !(kh->rho0 > 0.0))
+    return fail(LBM_EINVAL, "delta_over_L and rho0 must be > 0");
+  hipError_t e = lbm::launch_init_kh(ctx->L, *kh);
+  if (e != hipSuccess) return hip_fail(e, "lbm_init_kh_jet");
+  ctx->t = 0;
+  ctx->initialized = true;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* ctx, int64_t n) {
+  int rc = check_ctx(ctx, true);
+  if (rc != LBM_OK) return rc;
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  for (int64_t k = 0; k < n; ++k) {
+    hipError_t e = lbm::launch_step(ctx->L, ctx->t);
+    if (e != hipSuccess) return hip_fail(e, "lbm_step");
+    ++ctx->t;
+  }
+  return LBM_OK;
+}
+
+int lbm_get_time(const lbm_ctx* ctx, int64_t* t_out) {
+  int rc = check_ctx(ctx, false);
+  if (rc != LBM_OK) return rc;
+  if (!t_out) return fail(LBM_EINVAL, "t_out is NULL");
+  *t_out = ctx->t;
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* ctx, double* out_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc != LBM_OK) return rc;
+  if (!out_dev || !aligned(out_dev)) return fail(LBM_EINVAL, "out_dev must be a non-NULL 256-byte aligned pointer");
+  hipError_t e = lbm::launch_moments(ctx->L, ctx->t, out_dev, false);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments");
+}
+
+int lbm_get_state(lbm_ctx* ctx, double* out_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc != LBM_OK) return rc;
+  if (!out_dev || !aligned(out_dev)) return fail(LBM_EINVAL, "out_dev must be a non-NULL 256-byte aligned pointer");
+  hipError_t e = lbm::launch_get_state(ctx->L, ctx->t, out_dev);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_get_state");
+}
+
+int lbm_set_state(lbm_ctx* ctx, const double* in_dev, int64_t t) {
+  int rc = check_ctx(ctx, false);
+  if (rc != LBM_OK) return rc;
+  if (!in_dev || !aligned(in_dev)) return fail(LBM_EINVAL, "in_dev must be a non-NULL 256-byte aligned pointer");
+  if (t < 0) return fail(LBM_EINVAL, "t must be >= 0");
+  hipError_t e = lbm::launch_set_state(ctx->L, t, in_dev);
+  if (e != hipSuccess) return hip_fail(e, "lbm_set_state");
+  ctx->t = t;
+  ctx->initialized = true;
+  return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out_host) {
+  int rc = check_ctx(ctx, true);
+  if (rc != LBM_OK) return rc;
+  if (!out_host) return fail(LBM_EINVAL, "out_host is NULL");
+  double v[lbm::kDiagVals];
+  hipError_t e = lbm::launch_diagnostics(ctx->L, ctx->t, v);
+  if (e != hipSuccess) return hip_fail(e, "lbm_diagnostics");
+  const double n = double(ctx->L.nx) * double(ctx->L.ny);
+  out_host->t = ctx->t;
+  out_host->mass = v[0];
+  out_host->mom_x = v[1];
+  out_host->mom_y = v[2];
+  out_host->bsum_x = v[3];
+  out_host->bsum_y = v[4];
+  out_host->e_kin = v[5] / n;
+  out_host->e_mag = v[6] / n;
+  out_host->enstrophy = v[7] / n;
+  out_host->j2 = v[8] / n;
+  out_host->divb_rms = std::sqrt(v[9] / n);
+  out_host->divb_max = v[10];
+  out_host->nonfinite = (int64_t)v[11];
+  if (out_host->nonfinite > 0) return fail(LBM_ENONFINITE, "state holds non-finite populations");
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* ctx) {
+  delete ctx;
+  return LBM_OK;
+}
+
+const char* lbm_strerror(int code) {
+  switch (code) {
+    case LBM_OK: return "success";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ESTATE: return "invalid call order";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_ENONFINITE: return "non-finite state";
+    default: return "unknown error";
+  }
+}
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

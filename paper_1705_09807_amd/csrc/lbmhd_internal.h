@@ -1,0 +1,54 @@
+// Internal interface between the C ABI (lbmhd_api.cpp) and the kernel
+// launchers (lbmhd_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbmhd.h"
+
+namespace lbm {
+
+constexpr int kQ = 19;            // 9 (f) + 5 (g_x) + 5 (g_y) populations per cell
+constexpr int kDiagVals = 12;     // accumulators of the diagnostics reduction
+constexpr int kDiagBlocksMax = 2048;
+
+// Everything a launcher needs; filled once by lbm_create.
+struct Launch {
+  int nx = 0, ny = 0;
+  int64_t plane = 0;              // elements per population plane (>= nx*ny, padded)
+  int dtype = LBM_FP64;
+  int schedule = LBM_SCHED_FUSED;
+  int stencil = LBM_STENCIL_ISO9;
+  double rate[9] = {0};           // MRT rates s0..s8 (s0..s2 = 0)
+  double sm = 0;                  // magnetic SRT rate
+  double k2 = 0;                  // closure_scale * Delta^2 / 12
+  double rho0 = 1;                // rest density subtracted from stored f (0 for FP64)
+  void* state = nullptr;          // caller-owned population storage
+  void* work = nullptr;           // caller-owned work buffer
+  size_t off_mb = 0;              // moment planes for the in-place closure sweep
+  size_t off_diag = 0;            // 5 FP64 moment planes for the diagnostics
+  size_t off_part = 0;            // per-block reduction partials
+  size_t off_final = 0;           // final reduction values
+  int diag_blocks = 0;
+  hipStream_t stream = nullptr;
+};
+
+// Layout helpers (host).
+size_t storage_bytes(int dtype);
+int64_t plane_elems(int nx, int ny);
+size_t state_bytes(int nx, int ny, int dtype, int schedule);
+// Work layout for the given geometry; returns total bytes and fills offsets.
+size_t work_layout(Launch& L);
+
+// Launchers: enqueue on L.stream, return the first HIP error.
+hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh);
+hipError_t launch_step(const Launch& L, int64_t t);  // state at time t -> t + 1
+hipError_t launch_get_state(const Launch& L, int64_t t, double* out);
+hipError_t launch_set_state(const Launch& L, int64_t t, const double* in);
+hipError_t launch_moments(const Launch& L, int64_t t, double* out, bool mark_nonfinite);
+// Diagnostics: enqueue, copy kDiagVals doubles to host, synchronise the stream.
+hipError_t launch_diagnostics(const Launch& L, int64_t t, double* vals_host);
+
+}  // namespace lbm

@@ -1,0 +1,814 @@
+// HIP kernels (gfx950) of the filtered lattice-Boltzmann MHD timestep.
+//
+// Method: Flint & Vahala, arXiv 1705.09807.  Sec. 2: kinetic equations
+// (LBKinEqn, LBMagEqn), equilibria (feq, geq), moment transform
+// (FluidTMatrix), equilibrium moments (KinMomentEq, MagMomentEq), transport
+// coefficients; Sec. 2.1: filtered equilibrium moments built from the
+// Delta-expansion FilterExampleSmall; Sec. 3: SRT runs, density gradients
+// dropped (simplified M3).
+//
+// Storage: 19 structure-of-arrays planes (f_0..f_8, g_x0..g_x4, g_y0..g_y4),
+// x fastest, plane stride padded.  f is stored as the deviation
+// f_i - w_i rho0 from the rest equilibrium, so that FP32 keeps the small
+// dynamic part accurately; g is stored as is.
+//
+// Two schedules:
+//  * fused (two buffers): the state at time t is read with aligned loads,
+//    collided and pushed to x + c_i of the other buffer.  With the closure on,
+//    one workgroup marches up a column strip and keeps a 4-row ring of
+//    moments in LDS, so the 3x3 gradient stencil costs no extra HBM pass.
+//  * AA (one buffer, in place): even steps read and write the cell's own
+//    slots (reversed), odd steps read from and write to the neighbours; the
+//    read set of a cell equals its write set, so cells never race.  With the
+//    closure on, a moment sweep writes m and B to four planes first.
+//
+// All arithmetic that defines the method (moments, closure, collision,
+// equilibria) lives in the __device__ functions below and is shared by every
+// kernel, so both schedules compute identical values.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbmhd_internal.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Lattice (Sec. 2): D2Q9 velocities; the vector distribution uses the first
+// five (D2Q5).  Population q: f_q (q < 9), g_x,q-9 (9..13), g_y,q-14 (14..18).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int cx9(int i) {
+  return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int cy9(int i) {
+  return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp9(int i) {
+  return i == 0 ? 0 : (i < 5 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
+}
+__host__ __device__ constexpr int qbase(int q) { return q < 9 ? q : (q < 14 ? q - 9 : q - 14); }
+__host__ __device__ constexpr int qcx(int q) { return cx9(qbase(q)); }
+__host__ __device__ constexpr int qcy(int q) { return cy9(qbase(q)); }
+__host__ __device__ constexpr int qopp(int q) {
+  return q < 9 ? opp9(q) : (q < 14 ? 9 + opp9(q - 9) : 14 + opp9(q - 14));
+}
+// D2Q9 weights (rest deviation of f) and D2Q5 weights of the vector distribution.
+__host__ __device__ constexpr double w9(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+__host__ __device__ constexpr double w5(int i) { return i == 0 ? 1.0 / 3.0 : 1.0 / 6.0; }
+
+static_assert(opp9(1) == 3 && opp9(2) == 4 && opp9(3) == 1 && opp9(4) == 2, "opposites");
+static_assert(opp9(5) == 7 && opp9(6) == 8 && opp9(7) == 5 && opp9(8) == 6, "opposites");
+static_assert(qcx(10) == 1 && qcy(16) == 1 && qopp(15) == 17, "vector planes");
+
+template <typename S> struct ComputeOf { using type = float; };
+template <> struct ComputeOf<double> { using type = double; };
+
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Rates in the compute type, with the 1/|row|^2 of T^-1 = T^T diag(1/|row|^2)
+// folded in: |row|^2 = 9, 6, 6, 4, 4, 12, 12, 180, 20 for M0..M8.
+template <typename C>
+struct Rates {
+  C s3q, s4q, s5q, s6q, s7q, s8q;
+  C sm, k2, rho0;
+};
+
+template <typename C>
+static Rates<C> make_rates(const Launch& L) {
+  Rates<C> r;
+  r.s3q = C(L.rate[3] / 4.0);
+  r.s4q = C(L.rate[4] / 4.0);
+  r.s5q = C(L.rate[5] / 12.0);
+  r.s6q = C(L.rate[6] / 12.0);
+  r.s7q = C(L.rate[7] / 180.0);
+  r.s8q = C(L.rate[8] / 20.0);
+  r.sm = C(L.sm);
+  r.k2 = C(L.k2);
+  r.rho0 = C(L.rho0);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell arithmetic of the method
+// ---------------------------------------------------------------------------
+template <typename C>
+struct Mom {
+  C drho, mx, my, bx, by;  // rho - rho0, rho u, B
+};
+
+// rho = sum f_i, rho u = sum c_i f_i, B = sum g_i (Sec. 2), from the stored
+// deviations (sum_i w_i = 1, sum_i w_i c_i = 0).  Fixed summation order: every
+// kernel gets bit-identical moments for a cell.
+template <typename C>
+__device__ __forceinline__ Mom<C> moments19(const C v[kQ]) {
+  Mom<C> m;
+  m.drho = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
+  m.mx = ((v[1] - v[3]) + (v[5] - v[6])) + (v[8] - v[7]);
+  m.my = ((v[2] - v[4]) + (v[5] - v[7])) + (v[6] - v[8]);
+  m.bx = ((v[9] + v[10]) + (v[11] + v[12])) + v[13];
+  m.by = ((v[14] + v[15]) + (v[16] + v[17])) + v[18];
+  return m;
+}
+
+// Subgrid terms of the filtered equilibria (Sec. 2.1 FilterExampleSmall with
+// density gradients dropped, Sec. 3).  g*_ab = D_b m_a, h*_ab = D_b B_a; with
+// k2 = closure_scale Delta^2 / 12:
+//   P_ac = k2/rho sum_b D_b m_a D_b m_c   (Reynolds products m_a m_c / rho)
+//   Q_ac = k2     sum_b D_b B_a D_b B_c   (Maxwell products B_a B_c)
+//   R_ac = k2/rho sum_b D_b m_a D_b B_c   (induction products m_a B_c / rho)
+// tau_xy = P_xy - Q_xy enters M3; tau_d = (P_xx - P_yy) - (Q_xx - Q_yy) enters
+// M4; tau_s = P_xx + P_yy enters M7 and M8 (times -3); eps = R_xy - R_yx is
+// the filtered part of the induction moment E = (u x B)_z.
+template <typename C>
+struct Closure {
+  C tau_xy, tau_d, tau_s, eps;
+};
+
+template <typename C>
+__device__ __forceinline__ Closure<C> closure_terms(C gxx, C gxy, C gyx, C gyy, C hxx, C hxy, C hyx,
+                                                    C hyy, C inv_rho, C k2) {
+  const C kr = k2 * inv_rho;
+  const C pxx = kr * (gxx * gxx + gxy * gxy);
+  const C pyy = kr * (gyx * gyx + gyy * gyy);
+  const C pxy = kr * (gxx * gyx + gxy * gyy);
+  const C qxx = k2 * (hxx * hxx + hxy * hxy);
+  const C qyy = k2 * (hyx * hyx + hyy * hyy);
+  const C qxy = k2 * (hxx * hyx + hxy * hyy);
+  const C rxy = kr * (gxx * hyx + gxy * hyy);
+  const C ryx = kr * (gyx * hxx + gyy * hxy);
+  Closure<C> c;
+  c.tau_xy = pxy - qxy;
+  c.tau_d = (pxx - pyy) - (qxx - qyy);
+  c.tau_s = pxx + pyy;
+  c.eps = rxy - ryx;
+  return c;
+}
+
+// Discrete gradient from a 3x3 neighbourhood (value at offset (dx, dy)).
+// iso9: D_x a = (a_E - a_W)/3 + (a_NE + a_SE - a_NW - a_SW)/12 (and D_y by
+// symmetry), i.e. 3 sum_i w_i c_i a(x + c_i); central5: (a_E - a_W)/2.
+template <typename C, int STENCIL>
+__device__ __forceinline__ void grad3x3(C e, C w, C n, C s, C ne, C nw, C se, C sw, C& dx, C& dy) {
+  if (STENCIL == LBM_STENCIL_ISO9) {
+    const C third = C(1.0 / 3.0), twelfth = C(1.0 / 12.0);
+    dx = (e - w) * third + ((ne + se) - (nw + sw)) * twelfth;
+    dy = (n - s) * third + ((ne + nw) - (se + sw)) * twelfth;
+  } else {
+    dx = (e - w) * C(0.5);
+    dy = (n - s) * C(0.5);
+  }
+}
+
+// One collision of the 19 populations of a cell (Sec. 2, Sec. 3).
+//  f: M = T f; M* = M - S (M - M_eq) with M_eq the filtered KinMomentEq table
+//     (rho u_x rho u_y / rho - B_x B_y + tau_xy, ...); f* = T^-1 M*.  Conserved
+//     M0..M2 have rate 0, so only M3..M8 are formed: f* = f - T^T diag(s/|row|^2)
+//     (M - M_eq) restricted to rows 3..8.  In deviation storage M(w rho0) =
+//     (rho0, 0, ..., 0, 5 rho0 / 3) shifts only M8's equilibrium.
+//  g: g* = g - s_m (g - g_eq), g_eq_i = w'_i (B + 3 [(c.u) B - (c.B) u]) on D2Q5,
+//     which is g_eq_ix = w'_i (B_x - 3 c_iy E), g_eq_iy = w'_i (B_y + 3 c_ix E)
+//     with E = (m_x B_y - m_y B_x) / rho + eps.
+template <typename C>
+__device__ __forceinline__ void collide19(C v[kQ], const Mom<C>& m, const Closure<C>& cl,
+                                          const Rates<C>& r) {
+  const C rho = r.rho0 + m.drho;
+  const C ir = C(1) / rho;
+  const C mx = m.mx, my = m.my, bx = m.bx, by = m.by;
+  // rows 3..8 of T applied to the stored deviations
+  const C d56 = v[5] - v[6], d78 = v[7] - v[8], d87 = v[8] - v[7];
+  const C s14 = (v[1] + v[2]) + (v[3] + v[4]);
+  const C s58 = (v[5] + v[6]) + (v[7] + v[8]);
+  const C M3 = d56 + d78;
+  const C M4 = (v[1] + v[3]) - (v[2] + v[4]);
+  const C M5 = C(2) * (v[3] - v[1]) + d56 + d87;
+  const C M6 = C(2) * (v[4] - v[2]) + (v[5] + v[6]) - (v[7] + v[8]);
+  const C M7 = C(4) * v[0] - C(5) * s14 + C(4) * s58;
+  const C M8 = C(4) * v[0] - s58;
+  // filtered equilibrium moments (deviation form for M8)
+  const C q2 = (mx * mx + my * my) * ir;
+  const C e3 = mx * my * ir - bx * by + cl.tau_xy;
+  const C e4 = (mx * mx - my * my) * ir - (bx * bx - by * by) + cl.tau_d;
+  const C e7 = C(-3) * q2 - C(3) * cl.tau_s;
+  const C e8 = C(5.0 / 3.0) * m.drho + e7;
+  const C d3 = r.s3q * (M3 - e3);
+  const C d4 = r.s4q * (M4 - e4);
+  const C d5 = r.s5q * (M5 + mx);
+  const C d6 = r.s6q * (M6 + my);
+  const C d7 = r.s7q * (M7 - e7);
+  const C d8 = r.s8q * (M8 - e8);
+  const C g7 = C(5) * d7, h = C(4) * d7 - d8;
+  v[0] -= C(4) * (d7 + d8);
+  v[1] -= (d4 - C(2) * d5) - g7;
+  v[2] -= (-d4 - C(2) * d6) - g7;
+  v[3] -= (d4 + C(2) * d5) - g7;
+  v[4] -= (C(2) * d6 - d4) - g7;
+  v[5] -= (d3 + d5 + d6) + h;
+  v[6] -= (d6 - d3 - d5) + h;
+  v[7] -= (d3 - d5 - d6) + h;
+  v[8] -= (d5 - d3 - d6) + h;
+  // vector distribution, SRT
+  const C E = (mx * by - my * bx) * ir + cl.eps;
+  const C E3 = C(3) * E;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const C wi = C(w5(i));
+    const C gx = wi * (bx - C(cy9(i)) * E3);
+    const C gy = wi * (by + C(cx9(i)) * E3);
+    v[9 + i] -= r.sm * (v[9 + i] - gx);
+    v[14 + i] -= r.sm * (v[14 + i] - gy);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused schedule (two buffers): aligned loads of the state at time t, push to
+// x + c_q of the other buffer.
+// ---------------------------------------------------------------------------
+
+// Closure off (Delta = 0): one thread per cell, 64 x 4 tiles.
+template <typename S, typename C>
+__global__ void __launch_bounds__(256)
+k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const int64_t c0 = (int64_t)y * nx + x;
+  C v[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) v[q] = C(src[q * plane + c0]);
+  const Mom<C> m = moments19(v);
+  const Closure<C> cl = {C(0), C(0), C(0), C(0)};
+  collide19(v, m, cl, r);
+  const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+  const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int xd = qcx(q) > 0 ? xe : (qcx(q) < 0 ? xw : x);
+    const int yd = qcy(q) > 0 ? yn : (qcy(q) < 0 ? ys : y);
+    dst[q * plane + (int64_t)yd * nx + xd] = S(v[q]);
+  }
+}
+
+// Closure on: a workgroup of TX lanes covers columns x0-1 .. x0+TX-2 and
+// writes the TX-2 interior ones; it marches up rows y0 .. y0+ry-1 keeping the
+// moments (m_x, m_y, B_x, B_y) of rows y-1, y, y+1 (and the next) in a 4-slot
+// LDS ring.  Each population value is loaded once per strip (halo columns
+// and the two halo rows are re-read from cache by the neighbouring strips).
+template <typename S, typename C, int TX, int STENCIL>
+__global__ void __launch_bounds__(TX)
+k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry,
+            Rates<C> r) {
+  __shared__ C ring[4][4][TX];
+  const int lane = threadIdx.x;
+  const int x0 = blockIdx.x * (TX - 2);
+  const int xv = x0 - 1 + lane;
+  int xc = xv % nx;
+  if (xc < 0) xc += nx;
+  const bool out = lane >= 1 && lane <= TX - 2 && xv < nx;
+  const int xe = xc + 1 == nx ? 0 : xc + 1, xw = xc == 0 ? nx - 1 : xc - 1;
+  const int y0 = blockIdx.y * ry;
+  const int y1 = min(y0 + ry, ny);
+
+  C cur[kQ], nxt[kQ];
+  auto load_row = [&](int y, C* v) {
+    const S* p = src + (int64_t)y * nx + xc;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) v[q] = C(p[q * plane]);
+  };
+  auto put = [&](int slot, const C* v) {
+    const Mom<C> m = moments19(v);
+    ring[slot][0][lane] = m.mx;
+    ring[slot][1][lane] = m.my;
+    ring[slot][2][lane] = m.bx;
+    ring[slot][3][lane] = m.by;
+  };
+
+  load_row(y0 == 0 ? ny - 1 : y0 - 1, nxt);
+  put(0, nxt);
+  load_row(y0, cur);
+  put(1, cur);
+  for (int y = y0; y < y1; ++y) {
+    const int s = y - y0 + 1;  // ring slot of row y is s & 3
+    const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+    load_row(yn, nxt);
+    put((s + 1) & 3, nxt);
+    __syncthreads();
+    if (out) {
+      const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3;
+      C gr[4][2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        grad3x3<C, STENCIL>(ring[sc][k][lane + 1], ring[sc][k][lane - 1], ring[sn][k][lane],
+                            ring[ss][k][lane], ring[sn][k][lane + 1], ring[sn][k][lane - 1],
+                            ring[ss][k][lane + 1], ring[ss][k][lane - 1], gr[k][0], gr[k][1]);
+      }
+      const Mom<C> m = moments19(cur);
+      const C ir = C(1) / (r.rho0 + m.drho);
+      const Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1],
+                                          gr[3][0], gr[3][1], ir, r.k2);
+      collide19(cur, m, cl, r);
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const int xd = qcx(q) > 0 ? xe : (qcx(q) < 0 ? xw : xc);
+        const int yd = qcy(q) > 0 ? yn : (qcy(q) < 0 ? ys : y);
+        dst[q * plane + (int64_t)yd * nx + xd] = S(cur[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) cur[q] = nxt[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// AA schedule (one buffer, in place).
+//  even t: load A[q][x],             store f*_q to A[opp q][x]
+//  odd  t: load A[opp q][x - c_q],   store f*_q to A[q][x + c_q]
+// ---------------------------------------------------------------------------
+template <typename S, typename C, bool ODD>
+__device__ __forceinline__ void aa_load(const S* __restrict__ A, int64_t plane, int nx, int x, int xe, int xw,
+                                        int y, int yn, int ys, C v[kQ]) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    if (!ODD) {
+      v[q] = C(A[q * plane + (int64_t)y * nx + x]);
+    } else {
+      const int xs = qcx(q) > 0 ? xw : (qcx(q) < 0 ? xe : x);  // x - c_q
+      const int yy = qcy(q) > 0 ? ys : (qcy(q) < 0 ? yn : y);
+      v[q] = C(A[qopp(q) * plane + (int64_t)yy * nx + xs]);
+    }
+  }
+}
+
+template <typename S, typename C, bool ODD>
+__device__ __forceinline__ void aa_store(S* __restrict__ A, int64_t plane, int nx, int x, int xe, int xw, int y,
+                                         int yn, int ys, const C v[kQ]) {
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    if (!ODD) {
+      A[qopp(q) * plane + (int64_t)y * nx + x] = S(v[q]);
+    } else {
+      const int xd = qcx(q) > 0 ? xe : (qcx(q) < 0 ? xw : x);  // x + c_q
+      const int yd = qcy(q) > 0 ? yn : (qcy(q) < 0 ? ys : y);
+      A[q * plane + (int64_t)yd * nx + xd] = S(v[q]);
+    }
+  }
+}
+
+template <typename S, typename C, bool ODD>
+__global__ void __launch_bounds__(256) k_aa_dns(S* __restrict__ A, int nx, int ny, int64_t plane, Rates<C> r) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+  const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+  C v[kQ];
+  aa_load<S, C, ODD>(A, plane, nx, x, xe, xw, y, yn, ys, v);
+  const Mom<C> m = moments19(v);
+  const Closure<C> cl = {C(0), C(0), C(0), C(0)};
+  collide19(v, m, cl, r);
+  aa_store<S, C, ODD>(A, plane, nx, x, xe, xw, y, yn, ys, v);
+}
+
+// Moment sweep of the in-place closure schedule: m_x, m_y, B_x, B_y of the
+// state at time t into four dense planes of the compute type.
+template <typename S, typename C, bool ODD>
+__global__ void __launch_bounds__(256)
+k_aa_moments(const S* __restrict__ A, C* __restrict__ mb, int nx, int ny, int64_t plane) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+  const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+  C v[kQ];
+  aa_load<S, C, ODD>(A, plane, nx, x, xe, xw, y, yn, ys, v);
+  const Mom<C> m = moments19(v);
+  const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
+  mb[c0] = m.mx;
+  mb[n + c0] = m.my;
+  mb[2 * n + c0] = m.bx;
+  mb[3 * n + c0] = m.by;
+}
+
+// Collide sweep of the in-place closure schedule: the 66 x 6 halo tile of the
+// four moment planes is staged in LDS for the gradient stencil.
+template <typename S, typename C, bool ODD, int STENCIL>
+__global__ void __launch_bounds__(256)
+k_aa_les(S* __restrict__ A, const C* __restrict__ mb, int nx, int ny, int64_t plane, Rates<C> r) {
+  __shared__ C tile[4][6][66];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int bx0 = blockIdx.x * 64, by0 = blockIdx.y * 4;
+  const int64_t n = (int64_t)nx * ny;
+  for (int idx = ty * 64 + tx; idx < 6 * 66; idx += 256) {
+    const int ly = idx / 66, lx = idx % 66;
+    int gx = (bx0 + lx - 1) % nx;
+    if (gx < 0) gx += nx;
+    int gy = (by0 + ly - 1) % ny;
+    if (gy < 0) gy += ny;
+    const int64_t c = (int64_t)gy * nx + gx;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tile[k][ly][lx] = mb[k * n + c];
+  }
+  __syncthreads();
+  const int x = bx0 + tx, y = by0 + ty;
+  if (x >= nx || y >= ny) return;
+  const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+  const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+  C v[kQ];
+  aa_load<S, C, ODD>(A, plane, nx, x, xe, xw, y, yn, ys, v);
+  const Mom<C> m = moments19(v);
+  const int lx = tx + 1, ly = ty + 1;
+  C gr[4][2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    grad3x3<C, STENCIL>(tile[k][ly][lx + 1], tile[k][ly][lx - 1], tile[k][ly + 1][lx], tile[k][ly - 1][lx],
+                        tile[k][ly + 1][lx + 1], tile[k][ly + 1][lx - 1], tile[k][ly - 1][lx + 1],
+                        tile[k][ly - 1][lx - 1], gr[k][0], gr[k][1]);
+  }
+  const C ir = C(1) / (r.rho0 + m.drho);
+  const Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
+                                      gr[3][1], ir, r.k2);
+  collide19(v, m, cl, r);
+  aa_store<S, C, ODD>(A, plane, nx, x, xe, xw, y, yn, ys, v);
+}
+
+// ---------------------------------------------------------------------------
+// Natural-layout access for initial state, state IO, moments and diagnostics.
+// `base` is the buffer holding the state at time t; `aa_odd` means the AA
+// buffer after an odd number of steps, where population q of cell x sits in
+// slot opp(q) of cell x - c_q.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t natural_index(int q, int x, int y, int nx, int ny, int64_t plane, bool aa_odd) {
+  if (!aa_odd) return q * plane + (int64_t)y * nx + x;
+  const int xs = wrap1(x - qcx(q), nx), ys = wrap1(y - qcy(q), ny);
+  return qopp(q) * plane + (int64_t)ys * nx + xs;
+}
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output number counter + 1 of
+// the sequence started at `seed`.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Kelvin-Helmholtz double shear layer at the unfiltered equilibria feq / geq
+// (Sec. 2), evaluated in FP64 and rounded to the storage type.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, double rho_ref, lbm_kh_params kh) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const double L = double(ny), d = kh.delta_over_L * L;
+  const double yy = double(y), xx = double(x);
+  const double ux = kh.U0 * (tanh((yy - 0.25 * L) / d) - tanh((yy - 0.75 * L) / d) - 1.0);
+  const uint64_t z = splitmix64_at(kh.seed, (uint64_t)y * (uint64_t)nx + (uint64_t)x);
+  const double xi = 2.0 * (double(z >> 11) * 0x1.0p-53) - 1.0;
+  const double uy = kh.pert_amp_over_U0 * kh.U0 * sin(2.0 * M_PI * xx / double(nx)) + kh.noise_amp * xi;
+  const double rho = kh.rho0, bx = kh.B0, by = 0.0;
+  const double usq = ux * ux + uy * uy, bsq = bx * bx + by * by;
+  const int64_t c0 = (int64_t)y * nx + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double cu = cx9(i) * ux + cy9(i) * uy;
+    const double cb = cx9(i) * bx + cy9(i) * by;
+    const double c2 = double(cx9(i) * cx9(i) + cy9(i) * cy9(i));
+    const double feq = w9(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * w9(i) * (0.5 * bsq * c2 - cb * cb);
+    base[i * plane + c0] = S(feq - w9(i) * rho_ref);
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const double cu = cx9(i) * ux + cy9(i) * uy;
+    const double cb = cx9(i) * bx + cy9(i) * by;
+    base[(9 + i) * plane + c0] = S(w5(i) * (bx + 3.0 * (cu * bx - cb * ux)));
+    base[(14 + i) * plane + c0] = S(w5(i) * (by + 3.0 * (cu * by - cb * uy)));
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_get_state(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, bool aa_odd,
+            double rho_ref) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const double v = double(base[natural_index(q, x, y, nx, ny, plane, aa_odd)]);
+    out[q * n + c0] = q < 9 ? v + w9(q) * rho_ref : v;
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny, int64_t plane, bool aa_odd,
+            double rho_ref) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const double v = in[q * n + c0];
+    base[natural_index(q, x, y, nx, ny, plane, aa_odd)] = S(q < 9 ? v - w9(q) * rho_ref : v);
+  }
+}
+
+// rho, m_x, m_y, B_x, B_y in FP64 (5 dense planes).  With mark_nonfinite,
+// rho is set to NaN where any population is NaN or infinite.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, bool aa_odd,
+              double rho_ref, bool mark_nonfinite) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  double v[kQ];
+  bool finite = true;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    v[q] = double(base[natural_index(q, x, y, nx, ny, plane, aa_odd)]);
+    finite = finite && isfinite(v[q]);
+  }
+  const Mom<double> m = moments19(v);
+  const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
+  out[c0] = (mark_nonfinite && !finite) ? __builtin_nan("") : rho_ref + m.drho;
+  out[n + c0] = m.mx;
+  out[2 * n + c0] = m.my;
+  out[3 * n + c0] = m.bx;
+  out[4 * n + c0] = m.by;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: per-cell FP64 terms from the five moment planes, a fixed-order
+// grid-stride accumulation per thread, wave and block reductions into one
+// partial per workgroup, then a single-workgroup fixed-order final pass.
+// Accumulators: 0 mass, 1-2 momentum, 3-4 sum B, 5 kinetic energy, 6 magnetic
+// energy, 7 enstrophy, 8 J_z^2, 9 (div B)^2, 10 max |div B|, 11 non-finite.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void diag_combine(double* a, const double* b) {
+#pragma unroll
+  for (int k = 0; k < kDiagVals; ++k) a[k] = (k == 10) ? fmax(a[k], b[k]) : a[k] + b[k];
+}
+
+__device__ void block_reduce_diag(double* acc, double* out) {
+  __shared__ double red[4][kDiagVals];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    double o[kDiagVals];
+#pragma unroll
+    for (int k = 0; k < kDiagVals; ++k) o[k] = __shfl_down(acc[k], off, 64);
+    diag_combine(acc, o);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kDiagVals; ++k) red[wid][k] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[kDiagVals];
+#pragma unroll
+    for (int k = 0; k < kDiagVals; ++k) t[k] = red[0][k];
+    for (int w = 1; w < 4; ++w) diag_combine(t, red[w]);
+#pragma unroll
+    for (int k = 0; k < kDiagVals; ++k) out[k] = t[k];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_diag_partial(const double* __restrict__ mom, double* __restrict__ partial, int nx, int ny) {
+  const int64_t n = (int64_t)nx * ny;
+  const double* rho = mom;
+  const double* mx = mom + n;
+  const double* my = mom + 2 * n;
+  const double* bx = mom + 3 * n;
+  const double* by = mom + 4 * n;
+  double acc[kDiagVals];
+#pragma unroll
+  for (int k = 0; k < kDiagVals; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+    const int y = int(c / nx), x = int(c - (int64_t)y * nx);
+    const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+    const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+    const int64_t cE = (int64_t)y * nx + xe, cW = (int64_t)y * nx + xw;
+    const int64_t cN = (int64_t)yn * nx + x, cS = (int64_t)ys * nx + x;
+    const double r = rho[c], mxc = mx[c], myc = my[c], bxc = bx[c], byc = by[c];
+    const double uyE = my[cE] / rho[cE], uyW = my[cW] / rho[cW];
+    const double uxN = mx[cN] / rho[cN], uxS = mx[cS] / rho[cS];
+    const double w = (uyE - uyW) / 2.0 - (uxN - uxS) / 2.0;
+    const double jz = (by[cE] - by[cW]) / 2.0 - (bx[cN] - bx[cS]) / 2.0;
+    const double dv = (bx[cE] - bx[cW]) / 2.0 + (by[cN] - by[cS]) / 2.0;
+    acc[0] += r;
+    acc[1] += mxc;
+    acc[2] += myc;
+    acc[3] += bxc;
+    acc[4] += byc;
+    acc[5] += 0.5 * (mxc * mxc + myc * myc) / r;
+    acc[6] += 0.5 * (bxc * bxc + byc * byc);
+    acc[7] += 0.5 * w * w;
+    acc[8] += jz * jz;
+    acc[9] += dv * dv;
+    acc[10] = fmax(acc[10], fabs(dv));
+    acc[11] += isfinite(r) ? 0.0 : 1.0;
+  }
+  block_reduce_diag(acc, partial + (int64_t)blockIdx.x * kDiagVals);
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ partial, double* __restrict__ out,
+                                                    int nparts) {
+  double acc[kDiagVals];
+#pragma unroll
+  for (int k = 0; k < kDiagVals; ++k) acc[k] = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += blockDim.x) diag_combine(acc, partial + (int64_t)p * kDiagVals);
+  block_reduce_diag(acc, out);
+}
+
+// ---------------------------------------------------------------------------
+// Host side: layout and launchers
+// ---------------------------------------------------------------------------
+size_t storage_bytes(int dtype) { return dtype == LBM_FP64 ? 8 : 4; }
+
+int64_t plane_elems(int nx, int ny) {
+  // Round each plane up to 1024 elements and add an odd multiple of 256 so
+  // that the 19 planes start at staggered offsets rather than at the same
+  // position of every large power-of-two stride.
+  const int64_t n = (int64_t)nx * ny;
+  return ((n + 1023) / 1024) * 1024 + 256;
+}
+
+size_t state_bytes(int nx, int ny, int dtype, int schedule) {
+  const size_t one = (size_t)kQ * (size_t)plane_elems(nx, ny) * storage_bytes(dtype);
+  return schedule == LBM_SCHED_FUSED ? 2 * one : one;
+}
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t work_layout(Launch& L) {
+  const size_t n = (size_t)L.nx * (size_t)L.ny;
+  const size_t cbytes = storage_bytes(L.dtype);
+  size_t off = 0;
+  L.off_mb = off;
+  if (L.schedule == LBM_SCHED_AA) off += align256(4 * n * cbytes);
+  L.off_diag = off;
+  off += align256(5 * n * sizeof(double));
+  const int64_t want = ((int64_t)n + 255) / 256;
+  L.diag_blocks = (int)(want < kDiagBlocksMax ? (want < 1 ? 1 : want) : kDiagBlocksMax);
+  L.off_part = off;
+  off += align256((size_t)L.diag_blocks * kDiagVals * sizeof(double));
+  L.off_final = off;
+  off += align256(kDiagVals * sizeof(double));
+  return off;
+}
+
+static dim3 tile_grid(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
+static const dim3 kTile(64, 4);
+
+template <typename S>
+static S* buffer_at(const Launch& L, int64_t t) {
+  S* base = static_cast<S*>(L.state);
+  if (L.schedule == LBM_SCHED_FUSED && (t & 1)) base += (size_t)kQ * (size_t)L.plane;
+  return base;
+}
+
+static bool aa_odd(const Launch& L, int64_t t) { return L.schedule == LBM_SCHED_AA && (t & 1); }
+
+// Rows per workgroup of the fused closure kernel: enough workgroups to fill
+// the chip several times over, otherwise long strips (fewer halo rows).
+static int fused_rows(int nx, int ny, int strip) {
+  const int64_t strips = (nx + strip - 1) / strip;
+  const int64_t target = 4096;
+  int64_t ry = (int64_t)ny * strips / target;
+  if (ry < 8) ry = 8;
+  if (ry > 128) ry = 128;
+  if (ry > ny) ry = ny;
+  return (int)ry;
+}
+
+template <typename S>
+static hipError_t step_typed(const Launch& L, int64_t t) {
+  using C = typename ComputeOf<S>::type;
+  const Rates<C> r = make_rates<C>(L);
+  const dim3 grid = tile_grid(L.nx, L.ny);
+  const bool les = L.k2 != 0.0;
+  if (L.schedule == LBM_SCHED_FUSED) {
+    const S* src = buffer_at<S>(L, t);
+    S* dst = buffer_at<S>(L, t + 1);
+    if (!les) {
+      hipLaunchKernelGGL((k_fused_dns<S, C>), grid, kTile, 0, L.stream, src, dst, L.nx, L.ny, L.plane, r);
+    } else {
+      constexpr int TX = 64;
+      const int ry = fused_rows(L.nx, L.ny, TX - 2);
+      const dim3 g((L.nx + TX - 3) / (TX - 2), (L.ny + ry - 1) / ry);
+      if (L.stencil == LBM_STENCIL_ISO9)
+        hipLaunchKernelGGL((k_fused_les<S, C, TX, LBM_STENCIL_ISO9>), g, dim3(TX), 0, L.stream, src, dst, L.nx,
+                           L.ny, L.plane, ry, r);
+      else
+        hipLaunchKernelGGL((k_fused_les<S, C, TX, LBM_STENCIL_CENTRAL5>), g, dim3(TX), 0, L.stream, src, dst,
+                           L.nx, L.ny, L.plane, ry, r);
+    }
+    return hipGetLastError();
+  }
+  S* A = static_cast<S*>(L.state);
+  const bool odd = t & 1;
+  if (!les) {
+    if (odd)
+      hipLaunchKernelGGL((k_aa_dns<S, C, true>), grid, kTile, 0, L.stream, A, L.nx, L.ny, L.plane, r);
+    else
+      hipLaunchKernelGGL((k_aa_dns<S, C, false>), grid, kTile, 0, L.stream, A, L.nx, L.ny, L.plane, r);
+    return hipGetLastError();
+  }
+  C* mb = reinterpret_cast<C*>(static_cast<char*>(L.work) + L.off_mb);
+  if (odd)
+    hipLaunchKernelGGL((k_aa_moments<S, C, true>), grid, kTile, 0, L.stream, A, mb, L.nx, L.ny, L.plane);
+  else
+    hipLaunchKernelGGL((k_aa_moments<S, C, false>), grid, kTile, 0, L.stream, A, mb, L.nx, L.ny, L.plane);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (L.stencil == LBM_STENCIL_ISO9) {
+    if (odd)
+      hipLaunchKernelGGL((k_aa_les<S, C, true, LBM_STENCIL_ISO9>), grid, kTile, 0, L.stream, A, mb, L.nx, L.ny,
+                         L.plane, r);
+    else
+      hipLaunchKernelGGL((k_aa_les<S, C, false, LBM_STENCIL_ISO9>), grid, kTile, 0, L.stream, A, mb, L.nx, L.ny,
+                         L.plane, r);
+  } else {
+    if (odd)
+      hipLaunchKernelGGL((k_aa_les<S, C, true, LBM_STENCIL_CENTRAL5>), grid, kTile, 0, L.stream, A, mb, L.nx,
+                         L.ny, L.plane, r);
+    else
+      hipLaunchKernelGGL((k_aa_les<S, C, false, LBM_STENCIL_CENTRAL5>), grid, kTile, 0, L.stream, A, mb, L.nx,
+                         L.ny, L.plane, r);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const Launch& L, int64_t t) {
+  return L.dtype == LBM_FP64 ? step_typed<double>(L, t) : step_typed<float>(L, t);
+}
+
+template <typename S>
+static hipError_t init_typed(const Launch& L, const lbm_kh_params& kh) {
+  hipLaunchKernelGGL((k_init_kh<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, 0), L.nx, L.ny,
+                     L.plane, L.rho0, kh);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh) {
+  return L.dtype == LBM_FP64 ? init_typed<double>(L, kh) : init_typed<float>(L, kh);
+}
+
+template <typename S>
+static hipError_t get_typed(const Launch& L, int64_t t, double* out) {
+  hipLaunchKernelGGL((k_get_state<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), out, L.nx,
+                     L.ny, L.plane, aa_odd(L, t), L.rho0);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(const Launch& L, int64_t t, double* out) {
+  return L.dtype == LBM_FP64 ? get_typed<double>(L, t, out) : get_typed<float>(L, t, out);
+}
+
+template <typename S>
+static hipError_t set_typed(const Launch& L, int64_t t, const double* in) {
+  hipLaunchKernelGGL((k_set_state<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), in, L.nx,
+                     L.ny, L.plane, aa_odd(L, t), L.rho0);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(const Launch& L, int64_t t, const double* in) {
+  return L.dtype == LBM_FP64 ? set_typed<double>(L, t, in) : set_typed<float>(L, t, in);
+}
+
+template <typename S>
+static hipError_t moments_typed(const Launch& L, int64_t t, double* out, bool mark) {
+  hipLaunchKernelGGL((k_moments_out<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), out,
+                     L.nx, L.ny, L.plane, aa_odd(L, t), L.rho0, mark);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const Launch& L, int64_t t, double* out, bool mark_nonfinite) {
+  return L.dtype == LBM_FP64 ? moments_typed<double>(L, t, out, mark_nonfinite)
+                             : moments_typed<float>(L, t, out, mark_nonfinite);
+}
+
+hipError_t launch_diagnostics(const Launch& L, int64_t t, double* vals_host) {
+  char* w = static_cast<char*>(L.work);
+  double* mom = reinterpret_cast<double*>(w + L.off_diag);
+  double* part = reinterpret_cast<double*>(w + L.off_part);
+  double* fin = reinterpret_cast<double*>(w + L.off_final);
+  hipError_t e = launch_moments(L, t, mom, true);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_partial, dim3(L.diag_blocks), dim3(256), 0, L.stream, mom, part, L.nx, L.ny);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, L.stream, part, fin, L.diag_blocks);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(vals_host, fin, kDiagVals * sizeof(double), hipMemcpyDeviceToHost, L.stream)) !=
+      hipSuccess)
+    return e;
+  return hipStreamSynchronize(L.stream);
+}
+
+}  // namespace lbm

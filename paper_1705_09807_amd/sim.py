@@ -1,0 +1,130 @@
+"""Python front end of the C ABI: argument marshalling only.
+
+PyTorch supplies device memory (byte tensors) and the stream; every step of
+the method runs in the HIP kernels of liblbmhd.so.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+from . import native as N
+
+_DTYPES = {"fp64": N.LBM_FP64, "fp32": N.LBM_FP32}
+_STENCILS = {"iso9": N.LBM_STENCIL_ISO9, "central5": N.LBM_STENCIL_CENTRAL5}
+_SCHEDULES = {"fused": N.LBM_SCHED_FUSED, "aa": N.LBM_SCHED_AA}
+
+
+def make_params(nx, ny, nu, eta, delta=0.0, closure_scale=1.0, s5=0.0, s6=0.0, s7=0.0, s8=0.0,
+                grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0) -> N.LbmParams:
+    return N.LbmParams(
+        nx=int(nx), ny=int(ny), nu=float(nu), eta=float(eta),
+        s5=float(s5 or 0.0), s6=float(s6 or 0.0), s7=float(s7 or 0.0), s8=float(s8 or 0.0),
+        delta=float(delta), closure_scale=float(closure_scale),
+        grad_stencil=_STENCILS[grad_stencil], dtype=_DTYPES[dtype],
+        schedule=_SCHEDULES[schedule], reserved=0, rho0=float(rho0))
+
+
+def state_bytes(params: N.LbmParams) -> int:
+    return N.load().lbm_state_bytes(ctypes.byref(params))
+
+
+def work_bytes(params: N.LbmParams) -> int:
+    return N.load().lbm_work_bytes(ctypes.byref(params))
+
+
+class Sim:
+    """One filtered LB-MHD run on one GPU (names follow the C ABI)."""
+
+    def __init__(self, nx, ny, nu, eta, delta=0.0, closure_scale=1.0, s5=0.0, s6=0.0, s7=0.0, s8=0.0,
+                 grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0, device="cuda:0",
+                 stream=None):
+        import torch
+
+        lib = N.load()
+        self._torch = torch
+        self.params = make_params(nx, ny, nu, eta, delta, closure_scale, s5, s6, s7, s8,
+                                  grad_stencil, dtype, schedule, rho0)
+        self.nx, self.ny = int(nx), int(ny)
+        self.device = torch.device(device)
+        sb = lib.lbm_state_bytes(ctypes.byref(self.params))
+        wb = lib.lbm_work_bytes(ctypes.byref(self.params))
+        if sb == 0 or wb == 0:
+            # let lbm_create report the exact reason
+            ctx = ctypes.c_void_p()
+            N.check(lib.lbm_create(ctypes.byref(ctx), ctypes.byref(self.params), None, None, None), "lbm_create")
+        self.state_buf = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        self.work_buf = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ctx = ctypes.c_void_p()
+        N.check(lib.lbm_create(ctypes.byref(self._ctx), ctypes.byref(self.params),
+                               ctypes.c_void_p(self.state_buf.data_ptr()),
+                               ctypes.c_void_p(self.work_buf.data_ptr()),
+                               ctypes.c_void_p(self.stream.cuda_stream)), "lbm_create")
+        self._lib = lib
+
+    # -- the ABI -----------------------------------------------------------
+    def init_kh_jet(self, U0=0.05, delta_over_L=0.05, B0=0.01, rho0=1.0, pert_amp_over_U0=1e-3,
+                    noise_amp=1e-5, seed=0):
+        kh = N.LbmKhParams(U0=U0, delta_over_L=delta_over_L, B0=B0, rho0=rho0,
+                           pert_amp_over_U0=pert_amp_over_U0, noise_amp=noise_amp, seed=int(seed))
+        N.check(self._lib.lbm_init_kh_jet(self._ctx, ctypes.byref(kh)), "lbm_init_kh_jet")
+
+    def step(self, n: int = 1):
+        N.check(self._lib.lbm_step(self._ctx, int(n)), "lbm_step")
+
+    @property
+    def t(self) -> int:
+        t = ctypes.c_int64()
+        N.check(self._lib.lbm_get_time(self._ctx, ctypes.byref(t)), "lbm_get_time")
+        return t.value
+
+    def moments(self, out=None):
+        """[5, ny, nx] float64 device tensor: rho, m_x, m_y, B_x, B_y."""
+        if out is None:
+            out = self._torch.empty((5, self.ny, self.nx), dtype=self._torch.float64, device=self.device)
+        self._check_field(out, 5)
+        N.check(self._lib.lbm_moments(self._ctx, ctypes.c_void_p(out.data_ptr())), "lbm_moments")
+        return out
+
+    def get_state(self, out=None):
+        """[19, ny, nx] float64 device tensor of the populations at time t."""
+        if out is None:
+            out = self._torch.empty((19, self.ny, self.nx), dtype=self._torch.float64, device=self.device)
+        self._check_field(out, 19)
+        N.check(self._lib.lbm_get_state(self._ctx, ctypes.c_void_p(out.data_ptr())), "lbm_get_state")
+        return out
+
+    def set_state(self, state, t: int = 0):
+        """state: [19, ny, nx] float64 (any device; copied to this GPU)."""
+        s = self._torch.as_tensor(state, dtype=self._torch.float64).to(self.device).contiguous()
+        self._check_field(s, 19)
+        N.check(self._lib.lbm_set_state(self._ctx, ctypes.c_void_p(s.data_ptr()), int(t)), "lbm_set_state")
+        self._keep = s  # the copy must outlive the asynchronous kernel
+
+    def diagnostics(self, raise_nonfinite: bool = False) -> dict:
+        d = N.LbmDiag()
+        rc = self._lib.lbm_diagnostics(self._ctx, ctypes.byref(d))
+        if rc != N.LBM_ENONFINITE or raise_nonfinite:
+            N.check(rc, "lbm_diagnostics")
+        return {name: getattr(d, name) for name, _ in N.LbmDiag._fields_}
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.lbm_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_field(self, t, planes):
+        torch = self._torch
+        if t.dtype != torch.float64 or t.device != self.device or not t.is_contiguous() \
+                or tuple(t.shape) != (planes, self.ny, self.nx):
+            raise ValueError(f"expected a contiguous float64 tensor of shape ({planes}, {self.ny}, {self.nx}) "
+                             f"on {self.device}")
+        if t.data_ptr() % 256:
+            raise ValueError("device buffer must be 256-byte aligned")

@@ -1,0 +1,108 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/lbmhd.h declares, validates parameters and enforces call order.
+Nothing here enqueues device work, so it runs without a GPU."""
+
+import ctypes
+import os
+
+import pytest
+
+from paper_1705_09807_amd import native as N
+
+LIB = N.LIB_PATH
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("liblbmhd.so is not built; run __graft_entry__.build() first")
+    return N.load()
+
+
+def _params(**kw):
+    base = dict(nx=64, ny=48, nu=1e-3, eta=2e-3, s5=0.0, s6=0.0, s7=0.0, s8=0.0, delta=2.0,
+                closure_scale=1.0, grad_stencil=0, dtype=0, schedule=0, reserved=0, rho0=1.0)
+    base.update(kw)
+    return N.LbmParams(**base)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = N.header_functions()
+    assert "lbm_step" in names and "lbm_diagnostics" in names and len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(N._SIGNATURES)
+
+
+def test_struct_layouts_match_header():
+    # int32 pairs then doubles: no hidden padding differences between C and ctypes
+    assert ctypes.sizeof(N.LbmParams) == 4 * 2 + 8 * 8 + 4 * 4 + 8
+    assert ctypes.sizeof(N.LbmKhParams) == 7 * 8
+    assert ctypes.sizeof(N.LbmDiag) == 8 + 11 * 8 + 8
+
+
+def test_buffer_sizes(lib):
+    p = _params()
+    n_plane = ((64 * 48 + 1023) // 1024) * 1024 + 256
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 2 * 19 * n_plane * 8
+    p.schedule = N.LBM_SCHED_AA
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 19 * n_plane * 8
+    p.dtype = N.LBM_FP32
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 19 * n_plane * 4
+    w = lib.lbm_work_bytes(ctypes.byref(p))
+    assert w >= 4 * 64 * 48 * 4 + 5 * 64 * 48 * 8
+    p.schedule = N.LBM_SCHED_FUSED
+    assert lib.lbm_work_bytes(ctypes.byref(p)) < w  # no moment planes without the in-place closure sweep
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 3), ("ny", 0), ("nx", 70000), ("nu", 0.0), ("nu", -1e-3), ("eta", float("nan")),
+    ("s5", 2.0), ("s8", float("inf")), ("delta", -1.0), ("closure_scale", float("nan")),
+    ("grad_stencil", 2), ("dtype", 7), ("schedule", 3), ("reserved", 1), ("rho0", 0.0),
+])
+def test_invalid_params_rejected(lib, field, value):
+    p = _params(**{field: value})
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 0
+    assert lib.lbm_work_bytes(ctypes.byref(p)) == 0
+    ctx = ctypes.c_void_p()
+    rc = lib.lbm_create(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(1 << 20),
+                        ctypes.c_void_p(1 << 21), None)
+    assert rc == N.LBM_EINVAL
+    assert not ctx.value
+    assert len(lib.lbm_last_error()) > 0
+
+
+def test_pointer_checks_and_call_order(lib):
+    p = _params()
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(ctx), ctypes.byref(p), None, ctypes.c_void_p(1 << 20), None) == N.LBM_EINVAL
+    assert lib.lbm_create(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p((1 << 20) + 64),
+                          ctypes.c_void_p(1 << 21), None) == N.LBM_EINVAL
+    assert b"aligned" in lib.lbm_last_error()
+    # fake aligned device addresses: lbm_create enqueues no device work
+    assert lib.lbm_create(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(1 << 20),
+                          ctypes.c_void_p(1 << 21), None) == N.LBM_OK
+    try:
+        assert lib.lbm_step(ctx, 1) == N.LBM_ESTATE
+        assert b"not initialised" in lib.lbm_last_error()
+        assert lib.lbm_diagnostics(ctx, ctypes.byref(N.LbmDiag())) == N.LBM_ESTATE
+        assert lib.lbm_moments(ctx, ctypes.c_void_p(1 << 22)) == N.LBM_ESTATE
+        assert lib.lbm_get_state(ctx, ctypes.c_void_p(1 << 22)) == N.LBM_ESTATE
+        assert lib.lbm_set_state(ctx, None, 0) == N.LBM_EINVAL
+        assert lib.lbm_set_state(ctx, ctypes.c_void_p(1 << 22), -1) == N.LBM_EINVAL
+        kh = N.LbmKhParams(U0=0.05, delta_over_L=0.0, B0=0.01, rho0=1.0, pert_amp_over_U0=1e-3,
+                           noise_amp=1e-5, seed=0)
+        assert lib.lbm_init_kh_jet(ctx, ctypes.byref(kh)) == N.LBM_EINVAL
+        assert lib.lbm_init_kh_jet(ctx, None) == N.LBM_EINVAL
+        t = ctypes.c_int64(-5)
+        assert lib.lbm_get_time(ctx, ctypes.byref(t)) == N.LBM_OK and t.value == 0
+    finally:
+        assert lib.lbm_destroy(ctx) == N.LBM_OK
+    assert lib.lbm_destroy(None) == N.LBM_OK
+    assert lib.lbm_step(None, 1) == N.LBM_EINVAL
+
+
+def test_strerror(lib):
+    for code in (N.LBM_OK, N.LBM_EINVAL, N.LBM_ESTATE, N.LBM_EHIP, N.LBM_ENONFINITE):
+        assert len(lib.lbm_strerror(code)) > 0
+    assert lib.lbm_strerror(12345) == b"unknown error"
