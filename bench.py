@@ -137,10 +137,11 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     log(f"device: {torch.cuda.get_device_name(dev)}")
 
+    bref = (KH["B0"], 0.0)
     les = Sim(nx=LES_N, ny=LES_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype="fp32", schedule="fused",
-              device=dev, stream=stream)
+              b_ref=bref, device=dev, stream=stream)
     dns = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=0.0, dtype="fp32", schedule="fused",
-              device=dev, stream=stream)
+              b_ref=bref, device=dev, stream=stream)
     les.init_kh_jet(seed=0, **KH)
     dns.init_kh_jet(seed=0, **KH)
 
@@ -207,7 +208,7 @@ def main() -> int:
     if args.les4096_steps > 0:
         del les
         big = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype="fp32", schedule="fused",
-                  device=dev, stream=stream)
+                  b_ref=bref, device=dev, stream=stream)
         big.init_kh_jet(seed=0, **KH)
         big.step(20)
         a, b = ev(), ev()

@@ -48,9 +48,10 @@ extern "C" {
 #define LBM_ENONFINITE (-4)  /* diagnostics found NaN/Inf populations          */
 
 /* Storage precision of the populations (arithmetic: FP64 for LBM_FP64, FP32
- * otherwise).  LBM_FP32 stores f as the deviation f_i - w_i rho0 from the
- * rest equilibrium; LBM_FP64 stores f_i itself (exact state round trips);
- * g is stored as is. */
+ * otherwise).  LBM_FP32 stores deviations from a rest state, f_i - w_i rho0
+ * and g_i - w'_i B_ref (lbm_params rho0, bref_x, bref_y), so the small
+ * dynamic part keeps its digits; LBM_FP64 stores f_i and g_i themselves
+ * (exact state round trips). */
 #define LBM_FP64 0
 #define LBM_FP32 1
 
@@ -68,7 +69,7 @@ typedef struct lbm_ctx lbm_ctx;
 /* Run parameters, lattice units.  Rates follow Sec. 2: s3 = s4 = 2/(6 nu + 1)
  * (from nu = 1/(3 s) - 1/6), s_m = 2/(6 eta + 1); s0..s2 = 0 (conserved). */
 typedef struct {
-  int32_t nx, ny;          /* periodic grid, each >= 4 and <= 65536           */
+  int32_t nx, ny;          /* periodic grid, each >= 4 and <= 32768           */
   double nu, eta;          /* > 0, giving rates in (0, 2)                     */
   double s5, s6, s7, s8;   /* MRT ghost rates in (0, 2); <= 0 means "= s3",
                               i.e. the single-relaxation-time runs of Sec. 3 */
@@ -79,6 +80,8 @@ typedef struct {
   int32_t schedule;        /* LBM_SCHED_*                                     */
   int32_t reserved;        /* must be 0                                       */
   double rho0;             /* reference density of the FP32 deviations, > 0   */
+  double bref_x, bref_y;   /* reference field of the FP32 g deviations (finite;
+                              the run's mean field, e.g. (B0, 0) for the jet) */
 } lbm_params;
 
 /* Double-shear-layer Kelvin-Helmholtz jet: u_x = U0 [tanh((y - L/4)/d)

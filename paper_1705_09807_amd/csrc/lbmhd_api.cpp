@@ -38,8 +38,8 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 // Validate and derive rates.  Returns LBM_OK or LBM_EINVAL with a message.
 int check_params(const lbm_params* p, lbm::Launch* L) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
-  if (p->nx < 4 || p->ny < 4 || p->nx > 65536 || p->ny > 65536)
-    return fail(LBM_EINVAL, "nx and ny must lie in [4, 65536]");
+  if (p->nx < 4 || p->ny < 4 || p->nx > 32768 || p->ny > 32768)
+    return fail(LBM_EINVAL, "nx and ny must lie in [4, 32768]");
   if ((int64_t)p->nx * (int64_t)p->ny > (int64_t)1 << 31)
     return fail(LBM_EINVAL, "nx*ny must not exceed 2^31 cells");
   if (!finite_pos(p->nu) || !finite_pos(p->eta)) return fail(LBM_EINVAL, "nu and eta must be finite and > 0");
@@ -57,6 +57,7 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     return fail(LBM_EINVAL, "schedule must be LBM_SCHED_FUSED or LBM_SCHED_AA");
   if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
   if (!finite_pos(p->rho0)) return fail(LBM_EINVAL, "rho0 must be finite and > 0");
+  if (!std::isfinite(p->bref_x) || !std::isfinite(p->bref_y)) return fail(LBM_EINVAL, "bref must be finite");
   if (L) {
     // nu = 1/(3 s) - 1/6, eta = 1/(3 s_m) - 1/6 (Sec. 2); nu, eta > 0 put s in (0, 2).
     const double s = 2.0 / (6.0 * p->nu + 1.0);
@@ -72,9 +73,12 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     for (int k = 0; k < 4; ++k) L->rate[5 + k] = ghost[k] > 0.0 ? ghost[k] : s;
     L->sm = 2.0 / (6.0 * p->eta + 1.0);
     L->k2 = p->closure_scale * p->delta * p->delta / 12.0;
-    // FP32 stores f_i - w_i rho0 (the small dynamic part keeps its digits);
-    // FP64 stores f_i itself, so natural-layout state IO round-trips exactly.
+    // FP32 stores f_i - w_i rho0 and g_i - w'_i B_ref (the small dynamic part
+    // keeps its digits); FP64 stores the populations themselves, so
+    // natural-layout state IO round-trips exactly.
     L->rho0 = p->dtype == LBM_FP64 ? 0.0 : p->rho0;
+    L->bref[0] = p->dtype == LBM_FP64 ? 0.0 : p->bref_x;
+    L->bref[1] = p->dtype == LBM_FP64 ? 0.0 : p->bref_y;
   }
   return LBM_OK;
 }

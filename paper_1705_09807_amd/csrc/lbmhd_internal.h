@@ -25,6 +25,7 @@ struct Launch {
   double sm = 0;                  // magnetic SRT rate
   double k2 = 0;                  // closure_scale * Delta^2 / 12
   double rho0 = 1;                // rest density subtracted from stored f (0 for FP64)
+  double bref[2] = {0, 0};        // reference field subtracted from stored g (0 for FP64)
   void* state = nullptr;          // caller-owned population storage
   void* work = nullptr;           // caller-owned work buffer
   size_t off_mb = 0;              // moment planes for the in-place closure sweep

@@ -8,15 +8,17 @@
 // dropped (simplified M3).
 //
 // Storage: 19 structure-of-arrays planes (f_0..f_8, g_x0..g_x4, g_y0..g_y4),
-// x fastest, plane stride padded.  f is stored as the deviation
-// f_i - w_i rho0 from the rest equilibrium, so that FP32 keeps the small
-// dynamic part accurately; g is stored as is.
+// x fastest, plane stride padded.  FP32 stores f as the deviation
+// f_i - w_i rho0 from the rest equilibrium, so that the small dynamic part
+// keeps its digits; FP64 stores f itself (rho0 = 0 below); g is stored as is.
 //
 // Two schedules:
-//  * fused (two buffers): the state at time t is read with aligned loads,
-//    collided and pushed to x + c_i of the other buffer.  With the closure on,
-//    one workgroup marches up a column strip and keeps a 4-row ring of
-//    moments in LDS, so the 3x3 gradient stencil costs no extra HBM pass.
+//  * fused (two buffers, pull streaming): a buffer holds post-collision
+//    populations at their source cell; a sweep gathers f_q(x) from x - c_q
+//    (loads shifted by at most one cell), collides and stores aligned rows.
+//    With the closure on, one workgroup marches up a column strip and keeps
+//    a 4-row ring of moments in LDS, so the 3x3 gradient stencil costs no
+//    extra HBM pass.
 //  * AA (one buffer, in place): even steps read and write the cell's own
 //    slots (reversed), odd steps read from and write to the neighbours; the
 //    read set of a cell equals its write set, so cells never race.  With the
@@ -71,6 +73,7 @@ template <typename C>
 struct Rates {
   C s3q, s4q, s5q, s6q, s7q, s8q;
   C sm, k2, rho0;
+  C bx0, by0;  // reference field of the stored g deviations
 };
 
 template <typename C>
@@ -85,6 +88,8 @@ static Rates<C> make_rates(const Launch& L) {
   r.sm = C(L.sm);
   r.k2 = C(L.k2);
   r.rho0 = C(L.rho0);
+  r.bx0 = C(L.bref[0]);
+  r.by0 = C(L.bref[1]);
   return r;
 }
 
@@ -93,20 +98,21 @@ static Rates<C> make_rates(const Launch& L) {
 // ---------------------------------------------------------------------------
 template <typename C>
 struct Mom {
-  C drho, mx, my, bx, by;  // rho - rho0, rho u, B
+  C drho, mx, my, dbx, dby;  // rho - rho0, rho u, B - B_ref
 };
 
 // rho = sum f_i, rho u = sum c_i f_i, B = sum g_i (Sec. 2), from the stored
-// deviations (sum_i w_i = 1, sum_i w_i c_i = 0).  Fixed summation order: every
-// kernel gets bit-identical moments for a cell.
+// deviations f_i - w_i rho0 and g_i - w'_i B_ref (sum_i w_i = sum_i w'_i = 1,
+// sum_i w_i c_i = 0).  Fixed summation order: every kernel gets bit-identical
+// moments for a cell.
 template <typename C>
 __device__ __forceinline__ Mom<C> moments19(const C v[kQ]) {
   Mom<C> m;
   m.drho = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
   m.mx = ((v[1] - v[3]) + (v[5] - v[6])) + (v[8] - v[7]);
   m.my = ((v[2] - v[4]) + (v[5] - v[7])) + (v[6] - v[8]);
-  m.bx = ((v[9] + v[10]) + (v[11] + v[12])) + v[13];
-  m.by = ((v[14] + v[15]) + (v[16] + v[17])) + v[18];
+  m.dbx = ((v[9] + v[10]) + (v[11] + v[12])) + v[13];
+  m.dby = ((v[14] + v[15]) + (v[16] + v[17])) + v[18];
   return m;
 }
 
@@ -160,11 +166,12 @@ __device__ __forceinline__ void grad3x3(C e, C w, C n, C s, C ne, C nw, C se, C 
 }
 
 // One collision of the 19 populations of a cell (Sec. 2, Sec. 3).
-//  f: M = T f; M* = M - S (M - M_eq) with M_eq the filtered KinMomentEq table
-//     (rho u_x rho u_y / rho - B_x B_y + tau_xy, ...); f* = T^-1 M*.  Conserved
-//     M0..M2 have rate 0, so only M3..M8 are formed: f* = f - T^T diag(s/|row|^2)
-//     (M - M_eq) restricted to rows 3..8.  In deviation storage M(w rho0) =
-//     (rho0, 0, ..., 0, 5 rho0 / 3) shifts only M8's equilibrium.
+//  f: the collision term of LBKinEqn with rate tensor s' = T^-1 S T, i.e.
+//     f* = f - T^-1 S (M - M_eq), M = T f, M_eq the filtered KinMomentEq table
+//     (rho u_x rho u_y / rho - B_x B_y + tau_xy, ...).  Conserved M0..M2 have
+//     rate 0, so only rows 3..8 are formed, and T^-1 = T^T diag(1/|row|^2).
+//     In deviation storage M(w rho0) = (rho0, 0, ..., 0, 5 rho0 / 3) shifts
+//     only M8's equilibrium.
 //  g: g* = g - s_m (g - g_eq), g_eq_i = w'_i (B + 3 [(c.u) B - (c.B) u]) on D2Q5,
 //     which is g_eq_ix = w'_i (B_x - 3 c_iy E), g_eq_iy = w'_i (B_y + 3 c_ix E)
 //     with E = (m_x B_y - m_y B_x) / rho + eps.
@@ -173,7 +180,7 @@ __device__ __forceinline__ void collide19(C v[kQ], const Mom<C>& m, const Closur
                                           const Rates<C>& r) {
   const C rho = r.rho0 + m.drho;
   const C ir = C(1) / rho;
-  const C mx = m.mx, my = m.my, bx = m.bx, by = m.by;
+  const C mx = m.mx, my = m.my, bx = r.bx0 + m.dbx, by = r.by0 + m.dby;
   // rows 3..8 of T applied to the stored deviations
   const C d56 = v[5] - v[6], d78 = v[7] - v[8], d87 = v[8] - v[7];
   const C s14 = (v[1] + v[2]) + (v[3] + v[4]);
@@ -206,112 +213,190 @@ __device__ __forceinline__ void collide19(C v[kQ], const Mom<C>& m, const Closur
   v[6] -= (d6 - d3 - d5) + h;
   v[7] -= (d3 - d5 - d6) + h;
   v[8] -= (d5 - d3 - d6) + h;
-  // vector distribution, SRT
+  // vector distribution, SRT; the w'_i B_ref part of the stored deviation
+  // cancels against that of g_eq
   const C E = (mx * by - my * bx) * ir + cl.eps;
   const C E3 = C(3) * E;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     const C wi = C(w5(i));
-    const C gx = wi * (bx - C(cy9(i)) * E3);
-    const C gy = wi * (by + C(cx9(i)) * E3);
+    const C gx = wi * (m.dbx - C(cy9(i)) * E3);
+    const C gy = wi * (m.dby + C(cx9(i)) * E3);
     v[9 + i] -= r.sm * (v[9 + i] - gx);
     v[14 + i] -= r.sm * (v[14 + i] - gy);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Fused schedule (two buffers): aligned loads of the state at time t, push to
-// x + c_q of the other buffer.
+// Fused schedule (two buffers, pull streaming).  A buffer holds the
+// post-collision populations of the previous step at their source cell, so
+// the state at time t is f_q(x) = buf[q][x - c_q]: every sweep gathers with
+// loads shifted by at most one cell and stores aligned, coalesced rows.
 // ---------------------------------------------------------------------------
 
-// Closure off (Delta = 0): one thread per cell, 64 x 4 tiles.
+template <typename S> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+// f_q(x, y) = src[q][x - c_q][y - c_q] for one cell.
 template <typename S, typename C>
-__global__ void __launch_bounds__(256)
-k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  if (x >= nx || y >= ny) return;
-  const int64_t c0 = (int64_t)y * nx + x;
-  C v[kQ];
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) v[q] = C(src[q * plane + c0]);
-  const Mom<C> m = moments19(v);
-  const Closure<C> cl = {C(0), C(0), C(0), C(0)};
-  collide19(v, m, cl, r);
+__device__ __forceinline__ void pull_cell(const S* __restrict__ src, int64_t plane, int nx, int ny, int x, int y,
+                                          C v[kQ]) {
   const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
   const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const int xd = qcx(q) > 0 ? xe : (qcx(q) < 0 ? xw : x);
-    const int yd = qcy(q) > 0 ? yn : (qcy(q) < 0 ? ys : y);
-    dst[q * plane + (int64_t)yd * nx + xd] = S(v[q]);
+    const int xs = qcx(q) > 0 ? xw : (qcx(q) < 0 ? xe : x);
+    const int yy = qcy(q) > 0 ? ys : (qcy(q) < 0 ? yn : y);
+    v[q] = C(src[q * plane + (int64_t)yy * nx + xs]);
   }
 }
 
-// Closure on: a workgroup of TX lanes covers columns x0-1 .. x0+TX-2 and
-// writes the TX-2 interior ones; it marches up rows y0 .. y0+ry-1 keeping the
-// moments (m_x, m_y, B_x, B_y) of rows y-1, y, y+1 (and the next) in a 4-slot
-// LDS ring.  Each population value is loaded once per strip (halo columns
-// and the two halo rows are re-read from cache by the neighbouring strips).
-template <typename S, typename C, int TX, int STENCIL>
-__global__ void __launch_bounds__(TX)
-k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry,
-            Rates<C> r) {
-  __shared__ C ring[4][4][TX];
+// Two horizontally adjacent cells x, x + 1 (x even, nx even): the c_x = 0
+// populations come in one aligned two-element load.
+template <typename S, typename C>
+__device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t plane, int nx, int ny, int x, int y,
+                                          C a[kQ], C b[kQ]) {
+  using V2 = typename Vec2<S>::type;
+  const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+  const int xw = x == 0 ? nx - 1 : x - 1, xee = x + 2 == nx ? 0 : x + 2;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int yy = qcy(q) > 0 ? ys : (qcy(q) < 0 ? yn : y);
+    const S* row = src + q * plane + (int64_t)yy * nx;
+    if (qcx(q) == 0) {
+      const V2 t = *reinterpret_cast<const V2*>(row + x);
+      a[q] = C(t.x);
+      b[q] = C(t.y);
+    } else if (qcx(q) > 0) {
+      a[q] = C(row[xw]);
+      b[q] = C(row[x]);
+    } else {
+      a[q] = C(row[x + 1]);
+      b[q] = C(row[xee]);
+    }
+  }
+}
+
+// Closure off (Delta = 0).  One row segment of 2 * 128 cells per workgroup,
+// two cells per thread, aligned two-element stores.  Requires nx even.
+template <typename S, typename C>
+__global__ void __launch_bounds__(128)
+k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
+  using V2 = typename Vec2<S>::type;
+  const int x = (blockIdx.x * 128 + threadIdx.x) * 2;
+  const int y = blockIdx.y;
+  if (x >= nx) return;
+  C a[kQ], b[kQ];
+  pull_pair<S, C>(src, plane, nx, ny, x, y, a, b);
+  const Closure<C> cl = {C(0), C(0), C(0), C(0)};
+  {
+    const Mom<C> m = moments19(a);
+    collide19(a, m, cl, r);
+  }
+  {
+    const Mom<C> m = moments19(b);
+    collide19(b, m, cl, r);
+  }
+  const int64_t c0 = (int64_t)y * nx + x;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    V2 t;
+    t.x = S(a[q]);
+    t.y = S(b[q]);
+    *reinterpret_cast<V2*>(dst + q * plane + c0) = t;
+  }
+}
+
+// Closure off, any nx: one cell per thread, row segments of 256 cells.
+template <typename S, typename C>
+__global__ void __launch_bounds__(256)
+k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= nx) return;
+  C v[kQ];
+  pull_cell<S, C>(src, plane, nx, ny, x, y, v);
+  const Mom<C> m = moments19(v);
+  const Closure<C> cl = {C(0), C(0), C(0), C(0)};
+  collide19(v, m, cl, r);
+  const int64_t c0 = (int64_t)y * nx + x;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) dst[q * plane + c0] = S(v[q]);
+}
+
+// Closure on.  A workgroup of W lanes owns the column strip x0 .. x0+W-1 and
+// marches up rows y0 .. y0+ry-1.  The moments (m_x, m_y, B_x, B_y) of rows
+// y-1, y, y+1 (and the next) live in a 4-slot LDS ring indexed by lane + 1;
+// the two edge lanes also gather the halo columns x0-1 and the column after
+// the strip's last cell.  One barrier per row: a slot is rewritten two rows
+// after its last read.
+template <typename S, typename C, int W, int STENCIL>
+__global__ void __launch_bounds__(W)
+k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry, Rates<C> r) {
+  __shared__ C ring[4][4][W + 2];
   const int lane = threadIdx.x;
-  const int x0 = blockIdx.x * (TX - 2);
-  const int xv = x0 - 1 + lane;
-  int xc = xv % nx;
-  if (xc < 0) xc += nx;
-  const bool out = lane >= 1 && lane <= TX - 2 && xv < nx;
-  const int xe = xc + 1 == nx ? 0 : xc + 1, xw = xc == 0 ? nx - 1 : xc - 1;
+  const int x0 = blockIdx.x * W;
+  const int x = x0 + lane;
+  const int last = min(x0 + W, nx) - 1;      // last column of this strip
+  const bool valid = x <= last;
+  const bool lo = lane == 0;      // also gathers the column left of the strip
+  const bool hi = x == last;      // also gathers the column right of the strip
+  const int xlo = x0 == 0 ? nx - 1 : x0 - 1;
+  const int xhi = last + 1 == nx ? 0 : last + 1;
   const int y0 = blockIdx.y * ry;
   const int y1 = min(y0 + ry, ny);
 
   C cur[kQ], nxt[kQ];
-  auto load_row = [&](int y, C* v) {
-    const S* p = src + (int64_t)y * nx + xc;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) v[q] = C(p[q * plane]);
-  };
-  auto put = [&](int slot, const C* v) {
+  auto put1 = [&](int slot, int idx, const C* v) {
     const Mom<C> m = moments19(v);
-    ring[slot][0][lane] = m.mx;
-    ring[slot][1][lane] = m.my;
-    ring[slot][2][lane] = m.bx;
-    ring[slot][3][lane] = m.by;
+    ring[slot][0][idx] = m.mx;
+    ring[slot][1][idx] = m.my;
+    ring[slot][2][idx] = m.dbx;
+    ring[slot][3][idx] = m.dby;
   };
-
-  load_row(y0 == 0 ? ny - 1 : y0 - 1, nxt);
-  put(0, nxt);
-  load_row(y0, cur);
-  put(1, cur);
+  auto put = [&](int slot, int y, const C* v) {
+    if (valid) put1(slot, lane + 1, v);
+    if (lo) {
+      C h[kQ];
+      pull_cell<S, C>(src, plane, nx, ny, xlo, y, h);
+      put1(slot, 0, h);
+    }
+    if (hi) {
+      C h[kQ];
+      pull_cell<S, C>(src, plane, nx, ny, xhi, y, h);
+      put1(slot, last - x0 + 2, h);
+    }
+  };
+  const int xr = valid ? x : last;  // idle lanes load a valid cell (never stored)
+  const int ym = y0 == 0 ? ny - 1 : y0 - 1;
+  pull_cell<S, C>(src, plane, nx, ny, xr, ym, nxt);
+  put(0, ym, nxt);
+  pull_cell<S, C>(src, plane, nx, ny, xr, y0, cur);
+  put(1, y0, cur);
   for (int y = y0; y < y1; ++y) {
     const int s = y - y0 + 1;  // ring slot of row y is s & 3
-    const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
-    load_row(yn, nxt);
-    put((s + 1) & 3, nxt);
+    const int yn = y + 1 == ny ? 0 : y + 1;
+    pull_cell<S, C>(src, plane, nx, ny, xr, yn, nxt);
+    put((s + 1) & 3, yn, nxt);
     __syncthreads();
-    if (out) {
-      const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3;
+    if (valid) {
+      const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = lane + 1;
       C gr[4][2];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        grad3x3<C, STENCIL>(ring[sc][k][lane + 1], ring[sc][k][lane - 1], ring[sn][k][lane],
-                            ring[ss][k][lane], ring[sn][k][lane + 1], ring[sn][k][lane - 1],
-                            ring[ss][k][lane + 1], ring[ss][k][lane - 1], gr[k][0], gr[k][1]);
+        grad3x3<C, STENCIL>(ring[sc][k][l + 1], ring[sc][k][l - 1], ring[sn][k][l], ring[ss][k][l],
+                            ring[sn][k][l + 1], ring[sn][k][l - 1], ring[ss][k][l + 1], ring[ss][k][l - 1], gr[k][0],
+                            gr[k][1]);
       }
       const Mom<C> m = moments19(cur);
       const C ir = C(1) / (r.rho0 + m.drho);
-      const Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1],
-                                          gr[3][0], gr[3][1], ir, r.k2);
+      const Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
+                                          gr[3][1], ir, r.k2);
       collide19(cur, m, cl, r);
+      const int64_t c0 = (int64_t)y * nx + x;
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        const int xd = qcx(q) > 0 ? xe : (qcx(q) < 0 ? xw : xc);
-        const int yd = qcy(q) > 0 ? yn : (qcy(q) < 0 ? ys : y);
-        dst[q * plane + (int64_t)yd * nx + xd] = S(cur[q]);
-      }
+      for (int q = 0; q < kQ; ++q) dst[q * plane + c0] = S(cur[q]);
     }
 #pragma unroll
     for (int q = 0; q < kQ; ++q) cur[q] = nxt[q];
@@ -384,8 +469,8 @@ k_aa_moments(const S* __restrict__ A, C* __restrict__ mb, int nx, int ny, int64_
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
   mb[c0] = m.mx;
   mb[n + c0] = m.my;
-  mb[2 * n + c0] = m.bx;
-  mb[3 * n + c0] = m.by;
+  mb[2 * n + c0] = m.dbx;
+  mb[3 * n + c0] = m.dby;
 }
 
 // Collide sweep of the in-place closure schedule: the 66 x 6 halo tile of the
@@ -432,14 +517,30 @@ k_aa_les(S* __restrict__ A, const C* __restrict__ mb, int nx, int ny, int64_t pl
 
 // ---------------------------------------------------------------------------
 // Natural-layout access for initial state, state IO, moments and diagnostics.
-// `base` is the buffer holding the state at time t; `aa_odd` means the AA
-// buffer after an odd number of steps, where population q of cell x sits in
-// slot opp(q) of cell x - c_q.
+// `base` is the buffer holding the state at time t and `layout` says where
+// population q of cell x sits in it:
+//   kLayoutNatural: slot q of cell x                (AA buffer, even t)
+//   kLayoutAAOdd:   slot opp(q) of cell x - c_q     (AA buffer, odd t)
+//   kLayoutPull:    slot q of cell x - c_q          (fused buffers, any t)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t natural_index(int q, int x, int y, int nx, int ny, int64_t plane, bool aa_odd) {
-  if (!aa_odd) return q * plane + (int64_t)y * nx + x;
+constexpr int kLayoutNatural = 0;
+constexpr int kLayoutAAOdd = 1;
+constexpr int kLayoutPull = 2;
+
+__device__ __forceinline__ int64_t natural_index(int q, int x, int y, int nx, int ny, int64_t plane, int layout) {
+  if (layout == kLayoutNatural) return q * plane + (int64_t)y * nx + x;
   const int xs = wrap1(x - qcx(q), nx), ys = wrap1(y - qcy(q), ny);
-  return qopp(q) * plane + (int64_t)ys * nx + xs;
+  return (layout == kLayoutAAOdd ? qopp(q) : q) * plane + (int64_t)ys * nx + xs;
+}
+
+// Rest values subtracted from the stored populations: w_q rho0 for f,
+// w'_i B_ref for g (all zero for FP64 storage).
+struct RestRef {
+  double rho0, bx0, by0;
+};
+
+__device__ __forceinline__ double rest_value(int q, const RestRef& ref) {
+  return q < 9 ? w9(q) * ref.rho0 : (q < 14 ? w5(q - 9) * ref.bx0 : w5(q - 14) * ref.by0);
 }
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output number counter + 1 of
@@ -455,7 +556,7 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t counte
 // (Sec. 2), evaluated in FP64 and rounded to the storage type.
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, double rho_ref, lbm_kh_params kh) {
+k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestRef ref, lbm_kh_params kh) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= nx || y >= ny) return;
@@ -467,43 +568,44 @@ k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, double rho_ref, l
   const double uy = kh.pert_amp_over_U0 * kh.U0 * sin(2.0 * M_PI * xx / double(nx)) + kh.noise_amp * xi;
   const double rho = kh.rho0, bx = kh.B0, by = 0.0;
   const double usq = ux * ux + uy * uy, bsq = bx * bx + by * by;
-  const int64_t c0 = (int64_t)y * nx + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double cu = cx9(i) * ux + cy9(i) * uy;
     const double cb = cx9(i) * bx + cy9(i) * by;
     const double c2 = double(cx9(i) * cx9(i) + cy9(i) * cy9(i));
     const double feq = w9(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * w9(i) * (0.5 * bsq * c2 - cb * cb);
-    base[i * plane + c0] = S(feq - w9(i) * rho_ref);
+    base[natural_index(i, x, y, nx, ny, plane, layout)] = S(feq - rest_value(i, ref));
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     const double cu = cx9(i) * ux + cy9(i) * uy;
     const double cb = cx9(i) * bx + cy9(i) * by;
-    base[(9 + i) * plane + c0] = S(w5(i) * (bx + 3.0 * (cu * bx - cb * ux)));
-    base[(14 + i) * plane + c0] = S(w5(i) * (by + 3.0 * (cu * by - cb * uy)));
+    const double gx = w5(i) * (bx + 3.0 * (cu * bx - cb * ux));
+    const double gy = w5(i) * (by + 3.0 * (cu * by - cb * uy));
+    base[natural_index(9 + i, x, y, nx, ny, plane, layout)] = S(gx - rest_value(9 + i, ref));
+    base[natural_index(14 + i, x, y, nx, ny, plane, layout)] = S(gy - rest_value(14 + i, ref));
   }
 }
 
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_get_state(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, bool aa_odd,
-            double rho_ref) {
+k_get_state(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, int layout,
+            RestRef ref) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= nx || y >= ny) return;
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const double v = double(base[natural_index(q, x, y, nx, ny, plane, aa_odd)]);
-    out[q * n + c0] = q < 9 ? v + w9(q) * rho_ref : v;
+    const double v = double(base[natural_index(q, x, y, nx, ny, plane, layout)]);
+    out[q * n + c0] = v + rest_value(q, ref);
   }
 }
 
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny, int64_t plane, bool aa_odd,
-            double rho_ref) {
+k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny, int64_t plane, int layout,
+            RestRef ref) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= nx || y >= ny) return;
@@ -511,7 +613,7 @@ k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny,
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     const double v = in[q * n + c0];
-    base[natural_index(q, x, y, nx, ny, plane, aa_odd)] = S(q < 9 ? v - w9(q) * rho_ref : v);
+    base[natural_index(q, x, y, nx, ny, plane, layout)] = S(v - rest_value(q, ref));
   }
 }
 
@@ -519,8 +621,8 @@ k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny,
 // rho is set to NaN where any population is NaN or infinite.
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, bool aa_odd,
-              double rho_ref, bool mark_nonfinite) {
+k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, int layout,
+              RestRef ref, bool mark_nonfinite) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= nx || y >= ny) return;
@@ -528,16 +630,16 @@ k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int 
   bool finite = true;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    v[q] = double(base[natural_index(q, x, y, nx, ny, plane, aa_odd)]);
+    v[q] = double(base[natural_index(q, x, y, nx, ny, plane, layout)]);
     finite = finite && isfinite(v[q]);
   }
   const Mom<double> m = moments19(v);
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
-  out[c0] = (mark_nonfinite && !finite) ? __builtin_nan("") : rho_ref + m.drho;
+  out[c0] = (mark_nonfinite && !finite) ? __builtin_nan("") : ref.rho0 + m.drho;
   out[n + c0] = m.mx;
   out[2 * n + c0] = m.my;
-  out[3 * n + c0] = m.bx;
-  out[4 * n + c0] = m.by;
+  out[3 * n + c0] = ref.bx0 + m.dbx;
+  out[4 * n + c0] = ref.by0 + m.dby;
 }
 
 // ---------------------------------------------------------------------------
@@ -673,16 +775,20 @@ static S* buffer_at(const Launch& L, int64_t t) {
   return base;
 }
 
-static bool aa_odd(const Launch& L, int64_t t) { return L.schedule == LBM_SCHED_AA && (t & 1); }
+static RestRef rest_ref(const Launch& L) { return RestRef{L.rho0, L.bref[0], L.bref[1]}; }
 
-// Rows per workgroup of the fused closure kernel: enough workgroups to fill
-// the chip several times over, otherwise long strips (fewer halo rows).
+static int layout_at(const Launch& L, int64_t t) {
+  if (L.schedule == LBM_SCHED_FUSED) return kLayoutPull;
+  return (t & 1) ? kLayoutAAOdd : kLayoutNatural;
+}
+
+// Rows per workgroup of the fused closure kernel: long strips (the two halo
+// rows are re-read once per strip) as long as the launch still has enough
+// workgroups to fill the 256 compute units several times.
 static int fused_rows(int nx, int ny, int strip) {
   const int64_t strips = (nx + strip - 1) / strip;
-  const int64_t target = 4096;
-  int64_t ry = (int64_t)ny * strips / target;
-  if (ry < 8) ry = 8;
-  if (ry > 128) ry = 128;
+  int64_t ry = 128;
+  while (ry > 8 && strips * ((ny + ry - 1) / ry) < 1024) ry /= 2;
   if (ry > ny) ry = ny;
   return (int)ry;
 }
@@ -697,17 +803,22 @@ static hipError_t step_typed(const Launch& L, int64_t t) {
     const S* src = buffer_at<S>(L, t);
     S* dst = buffer_at<S>(L, t + 1);
     if (!les) {
-      hipLaunchKernelGGL((k_fused_dns<S, C>), grid, kTile, 0, L.stream, src, dst, L.nx, L.ny, L.plane, r);
-    } else {
-      constexpr int TX = 64;
-      const int ry = fused_rows(L.nx, L.ny, TX - 2);
-      const dim3 g((L.nx + TX - 3) / (TX - 2), (L.ny + ry - 1) / ry);
-      if (L.stencil == LBM_STENCIL_ISO9)
-        hipLaunchKernelGGL((k_fused_les<S, C, TX, LBM_STENCIL_ISO9>), g, dim3(TX), 0, L.stream, src, dst, L.nx,
-                           L.ny, L.plane, ry, r);
+      if ((L.nx & 1) == 0)
+        hipLaunchKernelGGL((k_fused_dns_pair<S, C>), dim3((L.nx + 255) / 256, L.ny), dim3(128), 0, L.stream, src,
+                           dst, L.nx, L.ny, L.plane, r);
       else
-        hipLaunchKernelGGL((k_fused_les<S, C, TX, LBM_STENCIL_CENTRAL5>), g, dim3(TX), 0, L.stream, src, dst,
-                           L.nx, L.ny, L.plane, ry, r);
+        hipLaunchKernelGGL((k_fused_dns<S, C>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream, src, dst,
+                           L.nx, L.ny, L.plane, r);
+    } else {
+      constexpr int W = 256;
+      const int ry = fused_rows(L.nx, L.ny, W);
+      const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
+      if (L.stencil == LBM_STENCIL_ISO9)
+        hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9>), g, dim3(W), 0, L.stream, src, dst, L.nx, L.ny,
+                           L.plane, ry, r);
+      else
+        hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5>), g, dim3(W), 0, L.stream, src, dst, L.nx,
+                           L.ny, L.plane, ry, r);
     }
     return hipGetLastError();
   }
@@ -752,7 +863,7 @@ hipError_t launch_step(const Launch& L, int64_t t) {
 template <typename S>
 static hipError_t init_typed(const Launch& L, const lbm_kh_params& kh) {
   hipLaunchKernelGGL((k_init_kh<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, 0), L.nx, L.ny,
-                     L.plane, L.rho0, kh);
+                     L.plane, layout_at(L, 0), rest_ref(L), kh);
   return hipGetLastError();
 }
 
@@ -763,7 +874,7 @@ hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh) {
 template <typename S>
 static hipError_t get_typed(const Launch& L, int64_t t, double* out) {
   hipLaunchKernelGGL((k_get_state<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), out, L.nx,
-                     L.ny, L.plane, aa_odd(L, t), L.rho0);
+                     L.ny, L.plane, layout_at(L, t), rest_ref(L));
   return hipGetLastError();
 }
 
@@ -774,7 +885,7 @@ hipError_t launch_get_state(const Launch& L, int64_t t, double* out) {
 template <typename S>
 static hipError_t set_typed(const Launch& L, int64_t t, const double* in) {
   hipLaunchKernelGGL((k_set_state<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), in, L.nx,
-                     L.ny, L.plane, aa_odd(L, t), L.rho0);
+                     L.ny, L.plane, layout_at(L, t), rest_ref(L));
   return hipGetLastError();
 }
 
@@ -785,7 +896,7 @@ hipError_t launch_set_state(const Launch& L, int64_t t, const double* in) {
 template <typename S>
 static hipError_t moments_typed(const Launch& L, int64_t t, double* out, bool mark) {
   hipLaunchKernelGGL((k_moments_out<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), out,
-                     L.nx, L.ny, L.plane, aa_odd(L, t), L.rho0, mark);
+                     L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L), mark);
   return hipGetLastError();
 }
 

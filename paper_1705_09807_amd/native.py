@@ -41,6 +41,7 @@ class LbmParams(ctypes.Structure):
         ("grad_stencil", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("rho0", ctypes.c_double),
+        ("bref_x", ctypes.c_double), ("bref_y", ctypes.c_double),
     ]
 
 

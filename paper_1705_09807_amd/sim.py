@@ -16,13 +16,14 @@ _SCHEDULES = {"fused": N.LBM_SCHED_FUSED, "aa": N.LBM_SCHED_AA}
 
 
 def make_params(nx, ny, nu, eta, delta=0.0, closure_scale=1.0, s5=0.0, s6=0.0, s7=0.0, s8=0.0,
-                grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0) -> N.LbmParams:
+                grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0, b_ref=(0.0, 0.0)) -> N.LbmParams:
     return N.LbmParams(
         nx=int(nx), ny=int(ny), nu=float(nu), eta=float(eta),
         s5=float(s5 or 0.0), s6=float(s6 or 0.0), s7=float(s7 or 0.0), s8=float(s8 or 0.0),
         delta=float(delta), closure_scale=float(closure_scale),
         grad_stencil=_STENCILS[grad_stencil], dtype=_DTYPES[dtype],
-        schedule=_SCHEDULES[schedule], reserved=0, rho0=float(rho0))
+        schedule=_SCHEDULES[schedule], reserved=0, rho0=float(rho0),
+        bref_x=float(b_ref[0]), bref_y=float(b_ref[1]))
 
 
 def state_bytes(params: N.LbmParams) -> int:
@@ -37,14 +38,14 @@ class Sim:
     """One filtered LB-MHD run on one GPU (names follow the C ABI)."""
 
     def __init__(self, nx, ny, nu, eta, delta=0.0, closure_scale=1.0, s5=0.0, s6=0.0, s7=0.0, s8=0.0,
-                 grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0, device="cuda:0",
-                 stream=None):
+                 grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0, b_ref=(0.0, 0.0),
+                 device="cuda:0", stream=None):
         import torch
 
         lib = N.load()
         self._torch = torch
         self.params = make_params(nx, ny, nu, eta, delta, closure_scale, s5, s6, s7, s8,
-                                  grad_stencil, dtype, schedule, rho0)
+                                  grad_stencil, dtype, schedule, rho0, b_ref)
         self.nx, self.ny = int(nx), int(ny)
         self.device = torch.device(device)
         sb = lib.lbm_state_bytes(ctypes.byref(self.params))

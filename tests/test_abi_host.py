@@ -21,7 +21,8 @@ def lib():
 
 def _params(**kw):
     base = dict(nx=64, ny=48, nu=1e-3, eta=2e-3, s5=0.0, s6=0.0, s7=0.0, s8=0.0, delta=2.0,
-                closure_scale=1.0, grad_stencil=0, dtype=0, schedule=0, reserved=0, rho0=1.0)
+                closure_scale=1.0, grad_stencil=0, dtype=0, schedule=0, reserved=0, rho0=1.0,
+                bref_x=0.01, bref_y=0.0)
     base.update(kw)
     return N.LbmParams(**base)
 
@@ -36,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_struct_layouts_match_header():
     # int32 pairs then doubles: no hidden padding differences between C and ctypes
-    assert ctypes.sizeof(N.LbmParams) == 4 * 2 + 8 * 8 + 4 * 4 + 8
+    assert ctypes.sizeof(N.LbmParams) == 4 * 2 + 8 * 8 + 4 * 4 + 3 * 8
     assert ctypes.sizeof(N.LbmKhParams) == 7 * 8
     assert ctypes.sizeof(N.LbmDiag) == 8 + 11 * 8 + 8
 
@@ -56,9 +57,10 @@ def test_buffer_sizes(lib):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nx", 3), ("ny", 0), ("nx", 70000), ("nu", 0.0), ("nu", -1e-3), ("eta", float("nan")),
+    ("nx", 3), ("ny", 0), ("nx", 40000), ("nu", 0.0), ("nu", -1e-3), ("eta", float("nan")),
     ("s5", 2.0), ("s8", float("inf")), ("delta", -1.0), ("closure_scale", float("nan")),
     ("grad_stencil", 2), ("dtype", 7), ("schedule", 3), ("reserved", 1), ("rho0", 0.0),
+    ("bref_x", float("nan")), ("bref_y", float("inf")),
 ])
 def test_invalid_params_rejected(lib, field, value):
     p = _params(**{field: value})

@@ -115,7 +115,8 @@ def test_kh_64_fp64_every_step(schedule):
 def test_kh_64_fp32_100_steps(schedule):
     n = 64
     _say("kh64 fp32", schedule)
-    s = _sim(nx=n, ny=n, nu=1e-3, eta=1e-3, delta=2.0, dtype="fp32", schedule=schedule)
+    s = _sim(nx=n, ny=n, nu=1e-3, eta=1e-3, delta=2.0, dtype="fp32", schedule=schedule,
+             b_ref=(KH0["B0"], 0.0))
     o = O.Oracle(n, n, 1e-3, 1e-3, delta=2.0)
     s.init_kh_jet(seed=1, **KH0)
     o.init_kh_jet(seed=1, **KH0)
@@ -135,6 +136,10 @@ CASES = [
     (70, 9, 4.0, "central5", (0, 0, 0, 0)),
     (130, 66, 4.0, "iso9", (0.7, 1.3, 1.9, 0.5)),
     (4, 4, 2.0, "iso9", (0, 0, 0, 0)),
+    (257, 10, 2.0, "iso9", (0, 0, 0, 0)),      # last column strip holds one cell
+    (300, 7, 0.0, "iso9", (1.1, 0.8, 1.3, 1.6)),  # even width, partial row block
+    (301, 5, 0.0, "iso9", (0, 0, 0, 0)),        # odd width: one cell per thread
+    (513, 6, 3.0, "central5", (0, 0, 0, 0)),
 ]
 
 
@@ -201,12 +206,12 @@ def test_schedules_agree_and_runs_repeat_bitwise():
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
 def test_checkpoint_resume_bitwise(schedule, dtype):
     n = 48
-    a = _sim(nx=n, ny=n, nu=1e-3, eta=1e-3, delta=2.0, dtype=dtype, schedule=schedule)
+    a = _sim(nx=n, ny=n, nu=1e-3, eta=1e-3, delta=2.0, dtype=dtype, schedule=schedule, b_ref=(0.01, 0.0))
     a.init_kh_jet(seed=4, **KH0)
     a.step(13)
     ck = a.get_state().clone()
     a.step(17)
-    b = _sim(nx=n, ny=n, nu=1e-3, eta=1e-3, delta=2.0, dtype=dtype, schedule=schedule)
+    b = _sim(nx=n, ny=n, nu=1e-3, eta=1e-3, delta=2.0, dtype=dtype, schedule=schedule, b_ref=(0.01, 0.0))
     b.set_state(ck, t=13)
     b.step(17)
     assert b.t == a.t == 30
@@ -217,8 +222,9 @@ def test_checkpoint_resume_bitwise(schedule, dtype):
 @pytest.mark.parametrize("source", ["kh", "random"])
 def test_diagnostics_match_oracle(dtype, source):
     """Every diagnostic against the oracle's exactly summed (fsum) values.
-    Quantities built from differences of neighbouring values (enstrophy, J_z^2,
-    div B) carry an absolute round-off floor of (eps_storage * 0.05)^2."""
+    Enstrophy, J_z^2 and div B are built from differences of neighbouring
+    values of size <= 0.05, each carrying an absolute rounding error
+    c = 10 eps 0.05; a quadratic mean q then carries 2 sqrt(q) c + c^2."""
     nx, ny = 64, 48
     s = _sim(nx=nx, ny=ny, nu=1e-3, eta=1e-3, delta=2.0, dtype=dtype)
     o = O.Oracle(nx, ny, 1e-3, 1e-3, delta=2.0)
@@ -235,7 +241,7 @@ def test_diagnostics_match_oracle(dtype, source):
         o.set_state(f, g)
     eps = np.finfo(np.float64 if dtype == "fp64" else np.float32).eps
     tol = 1e-12 if dtype == "fp64" else 2e-5
-    floor = 10 * (eps * 0.05) ** 2
+    c = 10 * eps * 0.05
     for steps in (0, 37):
         s.step(steps)
         o.step(steps)
@@ -245,9 +251,10 @@ def test_diagnostics_match_oracle(dtype, source):
         for key in ("mass", "e_kin", "e_mag"):
             assert abs(dg[key] - do[key]) <= tol * abs(do[key]), (key, dg[key], do[key])
         for key in ("enstrophy", "j2"):
-            assert abs(dg[key] - do[key]) <= tol * abs(do[key]) + floor, (key, dg[key], do[key])
+            slack = 2 * math.sqrt(abs(do[key])) * c + c * c
+            assert abs(dg[key] - do[key]) <= tol * abs(do[key]) + slack, (key, dg[key], do[key])
         for key in ("divb_rms", "divb_max"):
-            assert abs(dg[key] - do[key]) <= tol * abs(do[key]) + math.sqrt(floor), (key, dg[key], do[key])
+            assert abs(dg[key] - do[key]) <= tol * abs(do[key]) + c, (key, dg[key], do[key])
         for key in ("mom_x", "mom_y", "bsum_x", "bsum_y"):
             scale = do["mass"] * 0.05
             assert abs(dg[key] - do[key]) <= tol * scale, (key, dg[key], do[key])
@@ -302,7 +309,7 @@ def test_full_size_sampled(case):
     label, n, delta, dtype, nu, B0 = case
     _say("full-size", case)
     kh = dict(U0=0.05, delta_over_L=1 / 40, B0=B0, rho0=1.0, pert_amp_over_U0=1e-3, noise_amp=1e-5)
-    s = _sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype=dtype)
+    s = _sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype=dtype, b_ref=(B0, 0.0))
     s.init_kh_jet(seed=11, **kh)
     d0 = s.diagnostics()
     steps = 3
@@ -331,8 +338,10 @@ def test_full_size_sampled(case):
         assert np.abs(mom[:, k] - mo).max() <= tol, (x, y)
     d = s.diagnostics()
     assert d["nonfinite"] == 0
-    # periodic domain: mass, momentum and B are conserved (to storage round-off)
-    assert abs(d["mass"] - d0["mass"]) <= 1e-11 * d0["mass"]
+    # periodic domain: mass, momentum and B are conserved to storage round-off
+    # (FP32: correlated rounding of nearly uniform rows, ~1e-11 per cell-step)
+    ctol = 1e-13 if dtype == "fp64" else 1e-9
+    assert abs(d["mass"] - d0["mass"]) <= ctol * d0["mass"]
     for key in ("mom_x", "mom_y", "bsum_x", "bsum_y"):
-        assert abs(d[key] - d0[key]) <= 1e-11 * d0["mass"] * 0.05, key
-    assert abs(d0["mass"] - n * n) <= 1e-12 * n * n
+        assert abs(d[key] - d0[key]) <= ctol * d0["mass"] * 0.05, key
+    assert abs(d0["mass"] - n * n) <= (1e-12 if dtype == "fp64" else 1e-9) * n * n
