@@ -69,7 +69,8 @@ typedef struct lbm_ctx lbm_ctx;
 /* Run parameters, lattice units.  Rates follow Sec. 2: s3 = s4 = 2/(6 nu + 1)
  * (from nu = 1/(3 s) - 1/6), s_m = 2/(6 eta + 1); s0..s2 = 0 (conserved). */
 typedef struct {
-  int32_t nx, ny;          /* periodic grid, each >= 4 and <= 32768           */
+  int32_t nx, ny;          /* periodic grid, each >= 4 and <= 32768, with one
+                              plane (nx*ny values of the storage type) <= 4 GiB */
   double nu, eta;          /* > 0, giving rates in (0, 2)                     */
   double s5, s6, s7, s8;   /* MRT ghost rates in (0, 2); <= 0 means "= s3",
                               i.e. the single-relaxation-time runs of Sec. 3 */

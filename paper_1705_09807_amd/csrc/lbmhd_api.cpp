@@ -40,8 +40,9 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 4 || p->ny < 4 || p->nx > 32768 || p->ny > 32768)
     return fail(LBM_EINVAL, "nx and ny must lie in [4, 32768]");
-  if ((int64_t)p->nx * (int64_t)p->ny > (int64_t)1 << 31)
-    return fail(LBM_EINVAL, "nx*ny must not exceed 2^31 cells");
+  if ((p->dtype == LBM_FP64 || p->dtype == LBM_FP32) &&
+      (int64_t)p->nx * (int64_t)p->ny * (int64_t)lbm::storage_bytes(p->dtype) > ((int64_t)1 << 32))
+    return fail(LBM_EINVAL, "one population plane (nx*ny values) must not exceed 4 GiB");
   if (!finite_pos(p->nu) || !finite_pos(p->eta)) return fail(LBM_EINVAL, "nu and eta must be finite and > 0");
   const double ghost[4] = {p->s5, p->s6, p->s7, p->s8};
   for (double g : ghost) {

@@ -238,57 +238,106 @@ template <typename S> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 
+// Addressing: a plane base is wave-uniform (scalar registers) and every
+// access adds a 32-bit byte offset (row offset + column offset), which maps
+// onto the scalar-base + vector-offset form of global loads and stores and
+// keeps 64-bit address arithmetic out of the vector ALU.  A plane is at most
+// 4 GB (checked at creation).
+template <typename S>
+__device__ __forceinline__ const S* at(const S* __restrict__ base, uint32_t byte_off) {
+  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename S>
+__device__ __forceinline__ S* at(S* __restrict__ base, uint32_t byte_off) {
+  return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
+// Streaming store: non-temporal when the working set exceeds the caches.
+template <bool NT, typename T>
+__device__ __forceinline__ void store(T* p, T v) {
+  if (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// Byte offsets of the rows y - 1, y, y + 1 (periodic) and the columns
+// x - 1, x, x + 1 of a cell.
+struct Rows {
+  uint32_t s, c, n;
+};
+template <typename S>
+__device__ __forceinline__ Rows rows_of(int y, int nx, int ny) {
+  const uint32_t rb = uint32_t(nx) * uint32_t(sizeof(S));
+  Rows r;
+  r.c = uint32_t(y) * rb;
+  r.s = uint32_t(y == 0 ? ny - 1 : y - 1) * rb;
+  r.n = uint32_t(y + 1 == ny ? 0 : y + 1) * rb;
+  return r;
+}
+struct Cols {
+  uint32_t w, c, e;
+};
+template <typename S>
+__device__ __forceinline__ Cols cols_of(int x, int nx) {
+  Cols c;
+  c.c = uint32_t(x) * uint32_t(sizeof(S));
+  c.w = uint32_t(x == 0 ? nx - 1 : x - 1) * uint32_t(sizeof(S));
+  c.e = uint32_t(x + 1 == nx ? 0 : x + 1) * uint32_t(sizeof(S));
+  return c;
+}
+
 // f_q(x, y) = src[q][x - c_q][y - c_q] for one cell.
 template <typename S, typename C>
-__device__ __forceinline__ void pull_cell(const S* __restrict__ src, int64_t plane, int nx, int ny, int x, int y,
+__device__ __forceinline__ void pull_cell(const S* __restrict__ src, int64_t plane, const Rows& rw, const Cols& cl,
                                           C v[kQ]) {
-  const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
-  const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const int xs = qcx(q) > 0 ? xw : (qcx(q) < 0 ? xe : x);
-    const int yy = qcy(q) > 0 ? ys : (qcy(q) < 0 ? yn : y);
-    v[q] = C(src[q * plane + (int64_t)yy * nx + xs]);
+    const uint32_t xo = qcx(q) > 0 ? cl.w : (qcx(q) < 0 ? cl.e : cl.c);
+    const uint32_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
+    v[q] = C(*at(src + q * plane, yo + xo));
   }
 }
 
 // Two horizontally adjacent cells x, x + 1 (x even, nx even): the c_x = 0
 // populations come in one aligned two-element load.
 template <typename S, typename C>
-__device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t plane, int nx, int ny, int x, int y,
+__device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t plane, int nx, const Rows& rw, int x,
                                           C a[kQ], C b[kQ]) {
   using V2 = typename Vec2<S>::type;
-  const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
-  const int xw = x == 0 ? nx - 1 : x - 1, xee = x + 2 == nx ? 0 : x + 2;
+  const uint32_t es = uint32_t(sizeof(S));
+  const uint32_t xw = uint32_t(x == 0 ? nx - 1 : x - 1) * es, x0 = uint32_t(x) * es, x1 = x0 + es;
+  const uint32_t x2 = uint32_t(x + 2 == nx ? 0 : x + 2) * es;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const int yy = qcy(q) > 0 ? ys : (qcy(q) < 0 ? yn : y);
-    const S* row = src + q * plane + (int64_t)yy * nx;
+    const uint32_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
+    const S* pq = src + q * plane;
     if (qcx(q) == 0) {
-      const V2 t = *reinterpret_cast<const V2*>(row + x);
+      const V2 t = *reinterpret_cast<const V2*>(at(pq, yo + x0));
       a[q] = C(t.x);
       b[q] = C(t.y);
     } else if (qcx(q) > 0) {
-      a[q] = C(row[xw]);
-      b[q] = C(row[x]);
+      a[q] = C(*at(pq, yo + xw));
+      b[q] = C(*at(pq, yo + x0));
     } else {
-      a[q] = C(row[x + 1]);
-      b[q] = C(row[xee]);
+      a[q] = C(*at(pq, yo + x1));
+      b[q] = C(*at(pq, yo + x2));
     }
   }
 }
 
 // Closure off (Delta = 0).  One row segment of 2 * 128 cells per workgroup,
 // two cells per thread, aligned two-element stores.  Requires nx even.
-template <typename S, typename C>
+template <typename S, typename C, bool NT>
 __global__ void __launch_bounds__(128)
 k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
-  using V2 = typename Vec2<S>::type;
+  typedef S nv2 __attribute__((ext_vector_type(2)));
   const int x = (blockIdx.x * 128 + threadIdx.x) * 2;
   const int y = blockIdx.y;
   if (x >= nx) return;
+  const Rows rw = rows_of<S>(y, nx, ny);
   C a[kQ], b[kQ];
-  pull_pair<S, C>(src, plane, nx, ny, x, y, a, b);
+  pull_pair<S, C>(src, plane, nx, rw, x, a, b);
   const Closure<C> cl = {C(0), C(0), C(0), C(0)};
   {
     const Mom<C> m = moments19(a);
@@ -298,40 +347,43 @@ k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
     const Mom<C> m = moments19(b);
     collide19(b, m, cl, r);
   }
-  const int64_t c0 = (int64_t)y * nx + x;
+  const uint32_t off = rw.c + uint32_t(x) * uint32_t(sizeof(S));
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    V2 t;
+    nv2 t;
     t.x = S(a[q]);
     t.y = S(b[q]);
-    *reinterpret_cast<V2*>(dst + q * plane + c0) = t;
+    store<NT>(reinterpret_cast<nv2*>(at(dst + q * plane, off)), t);
   }
 }
 
 // Closure off, any nx: one cell per thread, row segments of 256 cells.
-template <typename S, typename C>
+template <typename S, typename C, bool NT>
 __global__ void __launch_bounds__(256)
 k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
   const int x = blockIdx.x * 256 + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= nx) return;
+  const Rows rw = rows_of<S>(y, nx, ny);
+  const Cols cl = cols_of<S>(x, nx);
   C v[kQ];
-  pull_cell<S, C>(src, plane, nx, ny, x, y, v);
+  pull_cell<S, C>(src, plane, rw, cl, v);
   const Mom<C> m = moments19(v);
-  const Closure<C> cl = {C(0), C(0), C(0), C(0)};
-  collide19(v, m, cl, r);
-  const int64_t c0 = (int64_t)y * nx + x;
+  const Closure<C> zero = {C(0), C(0), C(0), C(0)};
+  collide19(v, m, zero, r);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) dst[q * plane + c0] = S(v[q]);
+  for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, rw.c + cl.c), S(v[q]));
 }
 
 // Closure on.  A workgroup of W lanes owns the column strip x0 .. x0+W-1 and
-// marches up rows y0 .. y0+ry-1.  The moments (m_x, m_y, B_x, B_y) of rows
-// y-1, y, y+1 (and the next) live in a 4-slot LDS ring indexed by lane + 1;
-// the two edge lanes also gather the halo columns x0-1 and the column after
-// the strip's last cell.  One barrier per row: a slot is rewritten two rows
-// after its last read.
-template <typename S, typename C, int W, int STENCIL>
+// marches up rows y0 .. y0+ry-1.  The moments (m_x, m_y, B_x - B_ref,
+// B_y - B_ref) of the rows y-1 .. y+2 live in a 4-slot LDS ring indexed by
+// lane + 1; the two edge lanes also gather the halo columns x0-1 and the
+// column after the strip's last cell.  Rows are software-pipelined two deep:
+// the loads of row y+2 are issued before row y is collided.  One barrier per
+// row: a ring slot is rewritten only after the barrier that follows its last
+// read.
+template <typename S, typename C, int W, int STENCIL, bool NT>
 __global__ void __launch_bounds__(W)
 k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry, Rates<C> r) {
   __shared__ C ring[4][4][W + 2];
@@ -340,14 +392,14 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
   const int x = x0 + lane;
   const int last = min(x0 + W, nx) - 1;      // last column of this strip
   const bool valid = x <= last;
-  const bool lo = lane == 0;      // also gathers the column left of the strip
-  const bool hi = x == last;      // also gathers the column right of the strip
-  const int xlo = x0 == 0 ? nx - 1 : x0 - 1;
-  const int xhi = last + 1 == nx ? 0 : last + 1;
+  const bool lo = lane == 0;                 // also gathers the column left of the strip
+  const bool hi = x == last;                 // also gathers the column right of the strip
+  const Cols cx = cols_of<S>(valid ? x : last, nx);   // idle lanes load a valid cell (never stored)
+  const Cols clo = cols_of<S>(x0 == 0 ? nx - 1 : x0 - 1, nx);
+  const Cols chi = cols_of<S>(last + 1 == nx ? 0 : last + 1, nx);
   const int y0 = blockIdx.y * ry;
   const int y1 = min(y0 + ry, ny);
 
-  C cur[kQ], nxt[kQ];
   auto put1 = [&](int slot, int idx, const C* v) {
     const Mom<C> m = moments19(v);
     ring[slot][0][idx] = m.mx;
@@ -355,31 +407,41 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
     ring[slot][2][idx] = m.dbx;
     ring[slot][3][idx] = m.dby;
   };
-  auto put = [&](int slot, int y, const C* v) {
-    if (valid) put1(slot, lane + 1, v);
+  auto halo = [&](int slot, const Rows& rw) {
     if (lo) {
       C h[kQ];
-      pull_cell<S, C>(src, plane, nx, ny, xlo, y, h);
+      pull_cell<S, C>(src, plane, rw, clo, h);
       put1(slot, 0, h);
     }
     if (hi) {
       C h[kQ];
-      pull_cell<S, C>(src, plane, nx, ny, xhi, y, h);
+      pull_cell<S, C>(src, plane, rw, chi, h);
       put1(slot, last - x0 + 2, h);
     }
   };
-  const int xr = valid ? x : last;  // idle lanes load a valid cell (never stored)
-  const int ym = y0 == 0 ? ny - 1 : y0 - 1;
-  pull_cell<S, C>(src, plane, nx, ny, xr, ym, nxt);
-  put(0, ym, nxt);
-  pull_cell<S, C>(src, plane, nx, ny, xr, y0, cur);
-  put(1, y0, cur);
+  auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
+
+  C cur[kQ], nxt[kQ], nn[kQ];
+  {
+    const Rows r0 = rows_of<S>(wrapy(y0 - 1), nx, ny);
+    pull_cell<S, C>(src, plane, r0, cx, nn);
+    if (valid) put1(0, lane + 1, nn);
+    halo(0, r0);
+    const Rows r1 = rows_of<S>(y0, nx, ny);
+    pull_cell<S, C>(src, plane, r1, cx, cur);
+    if (valid) put1(1, lane + 1, cur);
+    halo(1, r1);
+    const Rows r2 = rows_of<S>(wrapy(y0 + 1), nx, ny);
+    pull_cell<S, C>(src, plane, r2, cx, nxt);
+    if (valid) put1(2, lane + 1, nxt);
+    halo(2, r2);
+  }
+  __syncthreads();
   for (int y = y0; y < y1; ++y) {
-    const int s = y - y0 + 1;  // ring slot of row y is s & 3
-    const int yn = y + 1 == ny ? 0 : y + 1;
-    pull_cell<S, C>(src, plane, nx, ny, xr, yn, nxt);
-    put((s + 1) & 3, yn, nxt);
-    __syncthreads();
+    const int s = y - y0 + 1;                 // ring slot of row y is s & 3
+    const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
+    const Rows r2 = rows_of<S>(wrapy(y + 2), nx, ny);
+    if (more) pull_cell<S, C>(src, plane, r2, cx, nn);
     if (valid) {
       const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = lane + 1;
       C gr[4][2];
@@ -394,12 +456,20 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
       const Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
                                           gr[3][1], ir, r.k2);
       collide19(cur, m, cl, r);
-      const int64_t c0 = (int64_t)y * nx + x;
+      const uint32_t off = uint32_t(y) * uint32_t(nx) * uint32_t(sizeof(S)) + cx.c;
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) dst[q * plane + c0] = S(cur[q]);
+      for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, off), S(cur[q]));
     }
+    if (more) {
+      if (valid) put1((s + 2) & 3, lane + 1, nn);
+      halo((s + 2) & 3, r2);
+    }
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) cur[q] = nxt[q];
+    for (int q = 0; q < kQ; ++q) {
+      cur[q] = nxt[q];
+      nxt[q] = nn[q];
+    }
   }
 }
 
@@ -783,14 +853,58 @@ static int layout_at(const Launch& L, int64_t t) {
 }
 
 // Rows per workgroup of the fused closure kernel: long strips (the two halo
-// rows are re-read once per strip) as long as the launch still has enough
-// workgroups to fill the 256 compute units several times.
+// rows are re-read once per strip) as long as the launch keeps at least 512
+// workgroups (measured at 1024^2 .. 8192^2 on MI355X: fewer leave the chip
+// latency bound, longer strips gain little).
 static int fused_rows(int nx, int ny, int strip) {
   const int64_t strips = (nx + strip - 1) / strip;
-  int64_t ry = 128;
-  while (ry > 8 && strips * ((ny + ry - 1) / ry) < 1024) ry /= 2;
+  int64_t ry = 64;
+  while (ry > 2 && strips * ((ny + ry - 1) / ry) < 512) ry /= 2;
   if (ry > ny) ry = ny;
   return (int)ry;
+}
+
+// Non-temporal stores pay off once the two population buffers no longer fit
+// in the 256 MB Infinity Cache; below that the next step re-reads them from it.
+static bool streaming_stores(const Launch& L) {
+  return 2.0 * double(kQ) * double(L.nx) * double(L.ny) * double(storage_bytes(L.dtype)) > 256.0e6;
+}
+
+template <typename S, typename C, int W, bool NT>
+static void launch_les(const Launch& L, const S* src, S* dst, const Rates<C>& r) {
+  const int ry = fused_rows(L.nx, L.ny, W);
+  const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
+  if (L.stencil == LBM_STENCIL_ISO9)
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT>), g, dim3(W), 0, L.stream, src, dst, L.nx, L.ny,
+                       L.plane, ry, r);
+  else
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT>), g, dim3(W), 0, L.stream, src, dst, L.nx,
+                       L.ny, L.plane, ry, r);
+}
+
+template <typename S, typename C, bool NT>
+static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& r) {
+  if (L.k2 == 0.0) {
+    if ((L.nx & 1) == 0)
+      hipLaunchKernelGGL((k_fused_dns_pair<S, C, NT>), dim3((L.nx + 255) / 256, L.ny), dim3(128), 0, L.stream, src,
+                         dst, L.nx, L.ny, L.plane, r);
+    else
+      hipLaunchKernelGGL((k_fused_dns<S, C, NT>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream, src, dst,
+                         L.nx, L.ny, L.plane, r);
+    return;
+  }
+  // Strip width: 512 lanes for wide FP32 grids (the LDS ring of a 512-lane
+  // FP64 strip would exceed 64 KB), 256 otherwise, 64 for narrow grids.
+  if constexpr (sizeof(S) == 4) {
+    if (L.nx >= 1024) {
+      launch_les<S, C, 512, NT>(L, src, dst, r);
+      return;
+    }
+  }
+  if (L.nx >= 256)
+    launch_les<S, C, 256, NT>(L, src, dst, r);
+  else
+    launch_les<S, C, 64, NT>(L, src, dst, r);
 }
 
 template <typename S>
@@ -802,24 +916,10 @@ static hipError_t step_typed(const Launch& L, int64_t t) {
   if (L.schedule == LBM_SCHED_FUSED) {
     const S* src = buffer_at<S>(L, t);
     S* dst = buffer_at<S>(L, t + 1);
-    if (!les) {
-      if ((L.nx & 1) == 0)
-        hipLaunchKernelGGL((k_fused_dns_pair<S, C>), dim3((L.nx + 255) / 256, L.ny), dim3(128), 0, L.stream, src,
-                           dst, L.nx, L.ny, L.plane, r);
-      else
-        hipLaunchKernelGGL((k_fused_dns<S, C>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream, src, dst,
-                           L.nx, L.ny, L.plane, r);
-    } else {
-      constexpr int W = 256;
-      const int ry = fused_rows(L.nx, L.ny, W);
-      const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
-      if (L.stencil == LBM_STENCIL_ISO9)
-        hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9>), g, dim3(W), 0, L.stream, src, dst, L.nx, L.ny,
-                           L.plane, ry, r);
-      else
-        hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5>), g, dim3(W), 0, L.stream, src, dst, L.nx,
-                           L.ny, L.plane, ry, r);
-    }
+    if (streaming_stores(L))
+      launch_fused<S, C, true>(L, src, dst, r);
+    else
+      launch_fused<S, C, false>(L, src, dst, r);
     return hipGetLastError();
   }
   S* A = static_cast<S*>(L.state);
