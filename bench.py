@@ -118,6 +118,9 @@ def main() -> int:
     ap.add_argument("--cpu-les-steps", type=int, default=3)
     ap.add_argument("--cpu-dns-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="after timing, run a plain device-to-device copy of this many bytes "
+                         "(reference kernel for the HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -256,6 +259,14 @@ def main() -> int:
     }
     del dns
     torch.cuda.empty_cache()
+    if args.copy_bytes > 0:
+        a = torch.empty(args.copy_bytes, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize(dev)
+        del a, b
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_les_steps, args.cpu_dns_steps)
     print(json.dumps(out), flush=True)
