@@ -5,7 +5,7 @@ Workload (one "step" = one timestep of each run, the whole hot path):
   * LES, 1024 x 1024, filter width Delta = 4 (plain Delta^2/12 closure), FP32;
   * DNS, 4096 x 4096, closure off, FP32;
 both the Kelvin-Helmholtz double shear layer U0 = 0.05, delta = L/40,
-B0 = 0.01, nu = eta = 2e-4, with the FP64 diagnostics (energy, enstrophy,
+B0 = 0.01, nu = eta = 2e-4 (MRT ghost rates 1.6), with the FP64 diagnostics (energy, enstrophy,
 J_z^2, div B, conservation sums) of both runs every 100 steps inside the
 timed region.  Inputs are synthetic (analytic initial state), resident in HBM
 before timing starts.
@@ -34,6 +34,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_LUP_FP32 = 38 * 4    # 19 populations read + 19 written per lattice update
 KH = dict(U0=0.05, delta_over_L=1.0 / 40.0, B0=0.01, rho0=1.0, pert_amp_over_U0=1e-3, noise_amp=1e-5)
 NU = ETA = 2e-4
+# MRT ghost rates s5..s8.  At nu = eta = 2e-4 (tau = 0.5006, grid Reynolds number
+# U0/nu = 250) the single-relaxation-time collision (ghost rates = s3) grows a
+# grid-scale mode and overflows after ~1.5-3.5k steps, on the oracle as on the
+# GPU; ghost rates >= 1.4 keep both runs finite for 20000 steps.
+GHOST = 1.6
 LES_N, LES_DELTA = 1024, 4.0
 DNS_N = 4096
 KERNEL_SRC = os.path.join(ROOT, "paper_1705_09807_amd", "csrc", "lbmhd_kernels.hip")
@@ -58,7 +63,7 @@ def measured_traffic(kernel: str, lups: int):
     vals = {}
     with open(path) as fh:
         for line in fh:
-            m = re.match(r"^\s*([a-z_]+)\s*[:=]\s*(\S+)", line)
+            m = re.match(r"^\s*([a-z0-9_]+)\s*[:=]\s*(\S+)", line)
             if m:
                 vals[m.group(1)] = m.group(2)
     try:
@@ -86,7 +91,7 @@ def cpu_baseline(les_steps: int, dns_steps: int) -> dict:
         for n, delta, steps in ((LES_N, LES_DELTA, les_steps), (DNS_N, 0.0, dns_steps)):
             if steps <= 0:
                 continue
-            o = Oracle(n, n, NU, ETA, delta=delta)
+            o = Oracle(n, n, NU, ETA, delta=delta, s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
             o.init_kh_jet(seed=0, **KH)
             t0 = time.perf_counter()
             o.step(steps)
@@ -115,8 +120,8 @@ def main() -> int:
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--les4096-steps", type=int, default=300,
                     help="steps of a supplementary 4096^2 LES timing (0 = skip)")
-    ap.add_argument("--cpu-les-steps", type=int, default=3)
-    ap.add_argument("--cpu-dns-steps", type=int, default=1)
+    ap.add_argument("--cpu-les-steps", type=int, default=15)
+    ap.add_argument("--cpu-dns-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, run a plain device-to-device copy of this many bytes "
@@ -141,10 +146,11 @@ def main() -> int:
     log(f"device: {torch.cuda.get_device_name(dev)}")
 
     bref = (KH["B0"], 0.0)
+    ghost = dict(s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
     les = Sim(nx=LES_N, ny=LES_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype="fp32", schedule="fused",
-              b_ref=bref, device=dev, stream=stream)
+              b_ref=bref, device=dev, stream=stream, **ghost)
     dns = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=0.0, dtype="fp32", schedule="fused",
-              b_ref=bref, device=dev, stream=stream)
+              b_ref=bref, device=dev, stream=stream, **ghost)
     les.init_kh_jet(seed=0, **KH)
     dns.init_kh_jet(seed=0, **KH)
 
@@ -211,7 +217,7 @@ def main() -> int:
     if args.les4096_steps > 0:
         del les
         big = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype="fp32", schedule="fused",
-                  b_ref=bref, device=dev, stream=stream)
+                  b_ref=bref, device=dev, stream=stream, **ghost)
         big.init_kh_jet(seed=0, **KH)
         big.step(20)
         a, b = ev(), ev()
@@ -247,6 +253,7 @@ def main() -> int:
             "grids": [LES_N, DNS_N],
             "delta": [LES_DELTA, 0.0],
             "U0": KH["U0"], "delta_over_L": KH["delta_over_L"], "B0": KH["B0"], "nu": NU, "eta": ETA,
+            "mrt_ghost_rates": GHOST,
             "diag_every": args.diag_every,
             "schedule": "fused",
             "parallelism": "single GPU",
