@@ -375,75 +375,62 @@ k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
   for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, rw.c + cl.c), S(v[q]));
 }
 
-// Closure on.  A workgroup of W lanes owns the column strip x0 .. x0+W-1 and
-// marches up rows y0 .. y0+ry-1.  The moments (m_x, m_y, B_x - B_ref,
-// B_y - B_ref) of the rows y-1 .. y+2 live in a 4-slot LDS ring indexed by
-// lane + 1; the two edge lanes also gather the halo columns x0-1 and the
-// column after the strip's last cell.  Rows are software-pipelined two deep:
-// the loads of row y+2 are issued before row y is collided.  One barrier per
-// row: a ring slot is rewritten only after the barrier that follows its last
-// read.
+// Closure on.  A workgroup of W + 64 lanes owns the column strip
+// x0 .. x0+W-1 and marches up rows y0 .. y0+ry-1.  The moments (m_x, m_y,
+// B_x - B_ref, B_y - B_ref) of the rows y-1 .. y+2 live in a 4-slot LDS ring
+// indexed by column - x0 + 1.  Lanes 0..W-1 gather, collide and store their
+// cells; one extra wave gathers the two halo columns (x0 - 1 and the column
+// after the strip's last cell), so no collision wave carries extra loads
+// (every wave of the workgroup waits at the per-row barrier for the slowest).
+// Rows are software-pipelined two deep: the loads of row y+2 are issued
+// before row y is collided.  A ring slot is rewritten only after the barrier
+// that follows its last read.
 template <typename S, typename C, int W, int STENCIL, bool NT>
-__global__ void __launch_bounds__(W)
+__global__ void __launch_bounds__(W + 64)
 k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry, Rates<C> r) {
   __shared__ C ring[4][4][W + 2];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const bool halo_wave = tid >= W;
   const int x0 = blockIdx.x * W;
-  const int x = x0 + lane;
   const int last = min(x0 + W, nx) - 1;      // last column of this strip
-  const bool valid = x <= last;
-  const bool lo = lane == 0;                 // also gathers the column left of the strip
-  const bool hi = x == last;                 // also gathers the column right of the strip
-  const Cols cx = cols_of<S>(valid ? x : last, nx);   // idle lanes load a valid cell (never stored)
-  const Cols clo = cols_of<S>(x0 == 0 ? nx - 1 : x0 - 1, nx);
-  const Cols chi = cols_of<S>(last + 1 == nx ? 0 : last + 1, nx);
+  const bool valid = !halo_wave && x0 + tid <= last;
+  const int hl = tid - W;                    // lane within the halo wave
+  const bool hlo = halo_wave && hl == 0;     // gathers the column left of the strip
+  const bool hhi = halo_wave && hl == 1;     // gathers the column right of the strip
+  const bool writer = valid || hlo || hhi;   // lanes that put moments into the ring
+  const bool loader = !halo_wave || hl < 2;
+  const int widx = hlo ? 0 : (hhi ? last - x0 + 2 : tid + 1);
+  const int xc = hlo ? (x0 == 0 ? nx - 1 : x0 - 1)
+                     : (hhi ? (last + 1 == nx ? 0 : last + 1) : (valid ? x0 + tid : last));
+  const Cols cx = cols_of<S>(xc, nx);        // idle lanes address a valid cell, never stored
   const int y0 = blockIdx.y * ry;
   const int y1 = min(y0 + ry, ny);
 
-  auto put1 = [&](int slot, int idx, const C* v) {
+  auto put = [&](int slot, const C* v) {
     const Mom<C> m = moments19(v);
-    ring[slot][0][idx] = m.mx;
-    ring[slot][1][idx] = m.my;
-    ring[slot][2][idx] = m.dbx;
-    ring[slot][3][idx] = m.dby;
-  };
-  auto halo = [&](int slot, const Rows& rw) {
-    if (lo) {
-      C h[kQ];
-      pull_cell<S, C>(src, plane, rw, clo, h);
-      put1(slot, 0, h);
-    }
-    if (hi) {
-      C h[kQ];
-      pull_cell<S, C>(src, plane, rw, chi, h);
-      put1(slot, last - x0 + 2, h);
-    }
+    ring[slot][0][widx] = m.mx;
+    ring[slot][1][widx] = m.my;
+    ring[slot][2][widx] = m.dbx;
+    ring[slot][3][widx] = m.dby;
   };
   auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
 
   C cur[kQ], nxt[kQ], nn[kQ];
-  {
-    const Rows r0 = rows_of<S>(wrapy(y0 - 1), nx, ny);
-    pull_cell<S, C>(src, plane, r0, cx, nn);
-    if (valid) put1(0, lane + 1, nn);
-    halo(0, r0);
-    const Rows r1 = rows_of<S>(y0, nx, ny);
-    pull_cell<S, C>(src, plane, r1, cx, cur);
-    if (valid) put1(1, lane + 1, cur);
-    halo(1, r1);
-    const Rows r2 = rows_of<S>(wrapy(y0 + 1), nx, ny);
-    pull_cell<S, C>(src, plane, r2, cx, nxt);
-    if (valid) put1(2, lane + 1, nxt);
-    halo(2, r2);
+  if (loader) {
+    pull_cell<S, C>(src, plane, rows_of<S>(wrapy(y0 - 1), nx, ny), cx, nn);
+    if (writer) put(0, nn);
+    pull_cell<S, C>(src, plane, rows_of<S>(y0, nx, ny), cx, cur);
+    if (writer) put(1, cur);
+    pull_cell<S, C>(src, plane, rows_of<S>(wrapy(y0 + 1), nx, ny), cx, nxt);
+    if (writer) put(2, nxt);
   }
   __syncthreads();
   for (int y = y0; y < y1; ++y) {
     const int s = y - y0 + 1;                 // ring slot of row y is s & 3
     const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
-    const Rows r2 = rows_of<S>(wrapy(y + 2), nx, ny);
-    if (more) pull_cell<S, C>(src, plane, r2, cx, nn);
+    if (more && loader) pull_cell<S, C>(src, plane, rows_of<S>(wrapy(y + 2), nx, ny), cx, nn);
     if (valid) {
-      const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = lane + 1;
+      const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
       C gr[4][2];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -460,10 +447,7 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
 #pragma unroll
       for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, off), S(cur[q]));
     }
-    if (more) {
-      if (valid) put1((s + 2) & 3, lane + 1, nn);
-      halo((s + 2) & 3, r2);
-    }
+    if (more && writer) put((s + 2) & 3, nn);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
@@ -875,11 +859,11 @@ static void launch_les(const Launch& L, const S* src, S* dst, const Rates<C>& r)
   const int ry = fused_rows(L.nx, L.ny, W);
   const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
   if (L.stencil == LBM_STENCIL_ISO9)
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT>), g, dim3(W), 0, L.stream, src, dst, L.nx, L.ny,
-                       L.plane, ry, r);
-  else
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT>), g, dim3(W), 0, L.stream, src, dst, L.nx,
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT>), g, dim3(W + 64), 0, L.stream, src, dst, L.nx,
                        L.ny, L.plane, ry, r);
+  else
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT>), g, dim3(W + 64), 0, L.stream, src, dst,
+                       L.nx, L.ny, L.plane, ry, r);
 }
 
 template <typename S, typename C, bool NT>
