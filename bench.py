@@ -120,6 +120,8 @@ def main() -> int:
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--les4096-steps", type=int, default=300,
                     help="steps of a supplementary 4096^2 LES timing (0 = skip)")
+    ap.add_argument("--lowprec-steps", type=int, default=50,
+                    help="steps of the supplementary 8192^2 FP32/FP16/BF16 timings (0 = skip)")
     ap.add_argument("--cpu-les-steps", type=int, default=15)
     ap.add_argument("--cpu-dns-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -232,6 +234,32 @@ def main() -> int:
                             "kernel": "k_fused_les<float> (plain closure, Delta=4)"}
         log(f"les 4096^2: {ms * 1e3:.1f} us/step, {bw:.0f} GB/s algorithmic")
         del big
+
+    if args.lowprec_steps > 0:
+        # 8192^2 jet, nu = eta = 1e-4: storage precision FP32 vs 16-bit deviations
+        n8 = 8192
+        lups8 = n8 * n8
+        kh8 = dict(KH)
+        for delta8 in (0.0, LES_DELTA):
+            for dt, width in (("fp32", 4), ("fp16", 2), ("bf16", 2)):
+                sim8 = Sim(nx=n8, ny=n8, nu=1e-4, eta=1e-4, delta=delta8, dtype=dt, schedule="fused",
+                           b_ref=bref, device=dev, stream=stream, **ghost)
+                sim8.init_kh_jet(seed=0, **kh8)
+                sim8.step(5)
+                a, b = ev(), ev()
+                a.record(stream)
+                sim8.step(args.lowprec_steps)
+                b.record(stream)
+                torch.cuda.synchronize(dev)
+                ms = a.elapsed_time(b) / args.lowprec_steps
+                bw = 38 * width * lups8 / (ms * 1e-3) / 1e9
+                key = f"{'les' if delta8 else 'dns'}8192_{dt}"
+                extra[key] = {"mlups": round(lups8 / (ms * 1e-3) / 1e6, 1), "avg_launch_us": round(ms * 1e3, 2),
+                              "bytes_per_lup": 38 * width, "achieved_GBps": round(bw, 1),
+                              "frac": round(bw / HBM_PEAK_GBS, 4)}
+                log(f"{key}: {ms * 1e3:.1f} us/step, {lups8 / (ms * 1e-3) / 1e6:.0f} MLUPS, {bw:.0f} GB/s")
+                del sim8
+                torch.cuda.empty_cache()
 
     last_dns, last_les = diag_log[-1] if diag_log else ({}, {})
     out = {

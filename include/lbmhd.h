@@ -48,12 +48,16 @@ extern "C" {
 #define LBM_ENONFINITE (-4)  /* diagnostics found NaN/Inf populations          */
 
 /* Storage precision of the populations (arithmetic: FP64 for LBM_FP64, FP32
- * otherwise).  LBM_FP32 stores deviations from a rest state, f_i - w_i rho0
- * and g_i - w'_i B_ref (lbm_params rho0, bref_x, bref_y), so the small
- * dynamic part keeps its digits; LBM_FP64 stores f_i and g_i themselves
- * (exact state round trips). */
+ * otherwise).  LBM_FP32, LBM_FP16 and LBM_BF16 store deviations from a rest
+ * state, f_i - w_i rho0 and g_i - w'_i B_ref (lbm_params rho0, bref_x,
+ * bref_y), so the small dynamic part keeps its digits; LBM_FP16 stores them
+ * scaled by 2^8 (clear of the FP16 subnormal range); LBM_FP64 stores f_i and
+ * g_i themselves (exact state round trips).  All conversions round to
+ * nearest even. */
 #define LBM_FP64 0
 #define LBM_FP32 1
+#define LBM_FP16 2
+#define LBM_BF16 3
 
 /* Discrete gradient used by the closure. */
 #define LBM_STENCIL_ISO9 0      /* (a_E-a_W)/3 + (a_NE+a_SE-a_NW-a_SW)/12 */
@@ -77,7 +81,7 @@ typedef struct {
   double delta;            /* filter width Delta >= 0; 0 = unfiltered (DNS)   */
   double closure_scale;    /* multiplies Delta^2/12; 1 = as printed in Sec. 3 */
   int32_t grad_stencil;    /* LBM_STENCIL_*                                   */
-  int32_t dtype;           /* LBM_FP64 or LBM_FP32                            */
+  int32_t dtype;           /* LBM_FP64, LBM_FP32, LBM_FP16 or LBM_BF16        */
   int32_t schedule;        /* LBM_SCHED_*                                     */
   int32_t reserved;        /* must be 0                                       */
   double rho0;             /* reference density of the FP32 deviations, > 0   */

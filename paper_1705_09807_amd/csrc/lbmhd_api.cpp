@@ -38,10 +38,11 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 // Validate and derive rates.  Returns LBM_OK or LBM_EINVAL with a message.
 int check_params(const lbm_params* p, lbm::Launch* L) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->dtype != LBM_FP64 && p->dtype != LBM_FP32 && p->dtype != LBM_FP16 && p->dtype != LBM_BF16)
+    return fail(LBM_EINVAL, "dtype must be LBM_FP64, LBM_FP32, LBM_FP16 or LBM_BF16");
   if (p->nx < 4 || p->ny < 4 || p->nx > 32768 || p->ny > 32768)
     return fail(LBM_EINVAL, "nx and ny must lie in [4, 32768]");
-  if ((p->dtype == LBM_FP64 || p->dtype == LBM_FP32) &&
-      (int64_t)p->nx * (int64_t)p->ny * (int64_t)lbm::storage_bytes(p->dtype) > ((int64_t)1 << 32))
+  if ((int64_t)p->nx * (int64_t)p->ny * (int64_t)lbm::storage_bytes(p->dtype) > ((int64_t)1 << 32))
     return fail(LBM_EINVAL, "one population plane (nx*ny values) must not exceed 4 GiB");
   if (!finite_pos(p->nu) || !finite_pos(p->eta)) return fail(LBM_EINVAL, "nu and eta must be finite and > 0");
   const double ghost[4] = {p->s5, p->s6, p->s7, p->s8};
@@ -53,7 +54,6 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
   if (!std::isfinite(p->closure_scale)) return fail(LBM_EINVAL, "closure_scale must be finite");
   if (p->grad_stencil != LBM_STENCIL_ISO9 && p->grad_stencil != LBM_STENCIL_CENTRAL5)
     return fail(LBM_EINVAL, "grad_stencil must be LBM_STENCIL_ISO9 or LBM_STENCIL_CENTRAL5");
-  if (p->dtype != LBM_FP64 && p->dtype != LBM_FP32) return fail(LBM_EINVAL, "dtype must be LBM_FP64 or LBM_FP32");
   if (p->schedule != LBM_SCHED_FUSED && p->schedule != LBM_SCHED_AA)
     return fail(LBM_EINVAL, "schedule must be LBM_SCHED_FUSED or LBM_SCHED_AA");
   if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");

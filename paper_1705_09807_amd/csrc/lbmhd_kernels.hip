@@ -65,6 +65,33 @@ static_assert(qcx(10) == 1 && qcy(16) == 1 && qopp(15) == 17, "vector planes");
 template <typename S> struct ComputeOf { using type = float; };
 template <> struct ComputeOf<double> { using type = double; };
 
+// Storage codecs.  FP64 and FP32 store values as they are.  The 16-bit
+// storage types hold the deviations (see below) for FP32 arithmetic: FP16
+// scaled by 2^8, which lifts the small deviations out of the FP16 subnormal
+// range (normal values start at 6.1e-5) while the largest ones (~0.1) stay
+// far below 65504; BF16 unscaled (it has the FP32 exponent range).  All
+// conversions round to nearest even.
+template <typename S> struct Codec {
+  static constexpr float kScale = 1.0f;
+};
+template <> struct Codec<_Float16> {
+  static constexpr float kScale = 256.0f;
+};
+template <typename C, typename S>
+__device__ __forceinline__ C decode(S v) {
+  if constexpr (sizeof(S) == 2)
+    return C(float(v) * (1.0f / Codec<S>::kScale));
+  else
+    return C(v);
+}
+template <typename S, typename C>
+__device__ __forceinline__ S encode(C v) {
+  if constexpr (sizeof(S) == 2)
+    return S(float(v) * Codec<S>::kScale);
+  else
+    return S(v);
+}
+
 __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // Rates in the compute type, with the 1/|row|^2 of T^-1 = T^T diag(1/|row|^2)
@@ -234,9 +261,8 @@ __device__ __forceinline__ void collide19(C v[kQ], const Mom<C>& m, const Closur
 // loads shifted by at most one cell and stores aligned, coalesced rows.
 // ---------------------------------------------------------------------------
 
-template <typename S> struct Vec2;
-template <> struct Vec2<float> { using type = float2; };
-template <> struct Vec2<double> { using type = double2; };
+// Two consecutive stored values (one aligned load or store).
+template <typename S> using Vec2 = S __attribute__((ext_vector_type(2)));
 
 // Addressing: a plane base is wave-uniform (scalar registers) and every
 // access adds a 32-bit byte offset (row offset + column offset), which maps
@@ -295,7 +321,7 @@ __device__ __forceinline__ void pull_cell(const S* __restrict__ src, int64_t pla
   for (int q = 0; q < kQ; ++q) {
     const uint32_t xo = qcx(q) > 0 ? cl.w : (qcx(q) < 0 ? cl.e : cl.c);
     const uint32_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
-    v[q] = C(*at(src + q * plane, yo + xo));
+    v[q] = decode<C>(*at(src + q * plane, yo + xo));
   }
 }
 
@@ -304,7 +330,7 @@ __device__ __forceinline__ void pull_cell(const S* __restrict__ src, int64_t pla
 template <typename S, typename C>
 __device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t plane, int nx, const Rows& rw, int x,
                                           C a[kQ], C b[kQ]) {
-  using V2 = typename Vec2<S>::type;
+  using V2 = Vec2<S>;
   const uint32_t es = uint32_t(sizeof(S));
   const uint32_t xw = uint32_t(x == 0 ? nx - 1 : x - 1) * es, x0 = uint32_t(x) * es, x1 = x0 + es;
   const uint32_t x2 = uint32_t(x + 2 == nx ? 0 : x + 2) * es;
@@ -314,14 +340,14 @@ __device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t pla
     const S* pq = src + q * plane;
     if (qcx(q) == 0) {
       const V2 t = *reinterpret_cast<const V2*>(at(pq, yo + x0));
-      a[q] = C(t.x);
-      b[q] = C(t.y);
+      a[q] = decode<C>(t.x);
+      b[q] = decode<C>(t.y);
     } else if (qcx(q) > 0) {
-      a[q] = C(*at(pq, yo + xw));
-      b[q] = C(*at(pq, yo + x0));
+      a[q] = decode<C>(*at(pq, yo + xw));
+      b[q] = decode<C>(*at(pq, yo + x0));
     } else {
-      a[q] = C(*at(pq, yo + x1));
-      b[q] = C(*at(pq, yo + x2));
+      a[q] = decode<C>(*at(pq, yo + x1));
+      b[q] = decode<C>(*at(pq, yo + x2));
     }
   }
 }
@@ -331,7 +357,7 @@ __device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t pla
 template <typename S, typename C, bool NT>
 __global__ void __launch_bounds__(128)
 k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
-  typedef S nv2 __attribute__((ext_vector_type(2)));
+  using nv2 = Vec2<S>;
   const int x = (blockIdx.x * 128 + threadIdx.x) * 2;
   const int y = blockIdx.y;
   if (x >= nx) return;
@@ -351,8 +377,8 @@ k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     nv2 t;
-    t.x = S(a[q]);
-    t.y = S(b[q]);
+    t.x = encode<S>(a[q]);
+    t.y = encode<S>(b[q]);
     store<NT>(reinterpret_cast<nv2*>(at(dst + q * plane, off)), t);
   }
 }
@@ -372,7 +398,7 @@ k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
   const Closure<C> zero = {C(0), C(0), C(0), C(0)};
   collide19(v, m, zero, r);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, rw.c + cl.c), S(v[q]));
+  for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, rw.c + cl.c), encode<S>(v[q]));
 }
 
 // Closure on.  A workgroup of W + 64 lanes owns the column strip
@@ -445,7 +471,7 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
       collide19(cur, m, cl, r);
       const uint32_t off = uint32_t(y) * uint32_t(nx) * uint32_t(sizeof(S)) + cx.c;
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, off), S(cur[q]));
+      for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, off), encode<S>(cur[q]));
     }
     if (more && writer) put((s + 2) & 3, nn);
     __syncthreads();
@@ -468,11 +494,11 @@ __device__ __forceinline__ void aa_load(const S* __restrict__ A, int64_t plane, 
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     if (!ODD) {
-      v[q] = C(A[q * plane + (int64_t)y * nx + x]);
+      v[q] = decode<C>(A[q * plane + (int64_t)y * nx + x]);
     } else {
       const int xs = qcx(q) > 0 ? xw : (qcx(q) < 0 ? xe : x);  // x - c_q
       const int yy = qcy(q) > 0 ? ys : (qcy(q) < 0 ? yn : y);
-      v[q] = C(A[qopp(q) * plane + (int64_t)yy * nx + xs]);
+      v[q] = decode<C>(A[qopp(q) * plane + (int64_t)yy * nx + xs]);
     }
   }
 }
@@ -483,11 +509,11 @@ __device__ __forceinline__ void aa_store(S* __restrict__ A, int64_t plane, int n
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     if (!ODD) {
-      A[qopp(q) * plane + (int64_t)y * nx + x] = S(v[q]);
+      A[qopp(q) * plane + (int64_t)y * nx + x] = encode<S>(v[q]);
     } else {
       const int xd = qcx(q) > 0 ? xe : (qcx(q) < 0 ? xw : x);  // x + c_q
       const int yd = qcy(q) > 0 ? yn : (qcy(q) < 0 ? ys : y);
-      A[q * plane + (int64_t)yd * nx + xd] = S(v[q]);
+      A[q * plane + (int64_t)yd * nx + xd] = encode<S>(v[q]);
     }
   }
 }
@@ -628,7 +654,7 @@ k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestR
     const double cb = cx9(i) * bx + cy9(i) * by;
     const double c2 = double(cx9(i) * cx9(i) + cy9(i) * cy9(i));
     const double feq = w9(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * w9(i) * (0.5 * bsq * c2 - cb * cb);
-    base[natural_index(i, x, y, nx, ny, plane, layout)] = S(feq - rest_value(i, ref));
+    base[natural_index(i, x, y, nx, ny, plane, layout)] = encode<S>(feq - rest_value(i, ref));
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -636,8 +662,8 @@ k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestR
     const double cb = cx9(i) * bx + cy9(i) * by;
     const double gx = w5(i) * (bx + 3.0 * (cu * bx - cb * ux));
     const double gy = w5(i) * (by + 3.0 * (cu * by - cb * uy));
-    base[natural_index(9 + i, x, y, nx, ny, plane, layout)] = S(gx - rest_value(9 + i, ref));
-    base[natural_index(14 + i, x, y, nx, ny, plane, layout)] = S(gy - rest_value(14 + i, ref));
+    base[natural_index(9 + i, x, y, nx, ny, plane, layout)] = encode<S>(gx - rest_value(9 + i, ref));
+    base[natural_index(14 + i, x, y, nx, ny, plane, layout)] = encode<S>(gy - rest_value(14 + i, ref));
   }
 }
 
@@ -651,7 +677,7 @@ k_get_state(const S* __restrict__ base, double* __restrict__ out, int nx, int ny
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const double v = double(base[natural_index(q, x, y, nx, ny, plane, layout)]);
+    const double v = decode<double>(base[natural_index(q, x, y, nx, ny, plane, layout)]);
     out[q * n + c0] = v + rest_value(q, ref);
   }
 }
@@ -667,7 +693,7 @@ k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny,
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     const double v = in[q * n + c0];
-    base[natural_index(q, x, y, nx, ny, plane, layout)] = S(v - rest_value(q, ref));
+    base[natural_index(q, x, y, nx, ny, plane, layout)] = encode<S>(v - rest_value(q, ref));
   }
 }
 
@@ -684,7 +710,7 @@ k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int 
   bool finite = true;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    v[q] = double(base[natural_index(q, x, y, nx, ny, plane, layout)]);
+    v[q] = decode<double>(base[natural_index(q, x, y, nx, ny, plane, layout)]);
     finite = finite && isfinite(v[q]);
   }
   const Mom<double> m = moments19(v);
@@ -785,7 +811,9 @@ __global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ p
 // ---------------------------------------------------------------------------
 // Host side: layout and launchers
 // ---------------------------------------------------------------------------
-size_t storage_bytes(int dtype) { return dtype == LBM_FP64 ? 8 : 4; }
+size_t storage_bytes(int dtype) {
+  return dtype == LBM_FP64 ? 8 : (dtype == LBM_FP32 ? 4 : 2);
+}
 
 int64_t plane_elems(int nx, int ny) {
   // Round each plane up to 1024 elements and add an odd multiple of 256 so
@@ -804,7 +832,7 @@ static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 size_t work_layout(Launch& L) {
   const size_t n = (size_t)L.nx * (size_t)L.ny;
-  const size_t cbytes = storage_bytes(L.dtype);
+  const size_t cbytes = L.dtype == LBM_FP64 ? 8 : 4;  // compute type of the moment planes
   size_t off = 0;
   L.off_mb = off;
   if (L.schedule == LBM_SCHED_AA) off += align256(4 * n * cbytes);
@@ -879,7 +907,7 @@ static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& 
   }
   // Strip width: 512 lanes for wide FP32 grids (the LDS ring of a 512-lane
   // FP64 strip would exceed 64 KB), 256 otherwise, 64 for narrow grids.
-  if constexpr (sizeof(S) == 4) {
+  if constexpr (sizeof(C) == 4) {
     if (L.nx >= 1024) {
       launch_les<S, C, 512, NT>(L, src, dst, r);
       return;
@@ -941,7 +969,12 @@ static hipError_t step_typed(const Launch& L, int64_t t) {
 }
 
 hipError_t launch_step(const Launch& L, int64_t t) {
-  return L.dtype == LBM_FP64 ? step_typed<double>(L, t) : step_typed<float>(L, t);
+  switch (L.dtype) {
+    case LBM_FP64: return step_typed<double>(L, t);
+    case LBM_FP32: return step_typed<float>(L, t);
+    case LBM_FP16: return step_typed<_Float16>(L, t);
+    default: return step_typed<__bf16>(L, t);
+  }
 }
 
 template <typename S>
@@ -952,7 +985,12 @@ static hipError_t init_typed(const Launch& L, const lbm_kh_params& kh) {
 }
 
 hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh) {
-  return L.dtype == LBM_FP64 ? init_typed<double>(L, kh) : init_typed<float>(L, kh);
+  switch (L.dtype) {
+    case LBM_FP64: return init_typed<double>(L, kh);
+    case LBM_FP32: return init_typed<float>(L, kh);
+    case LBM_FP16: return init_typed<_Float16>(L, kh);
+    default: return init_typed<__bf16>(L, kh);
+  }
 }
 
 template <typename S>
@@ -963,7 +1001,12 @@ static hipError_t get_typed(const Launch& L, int64_t t, double* out) {
 }
 
 hipError_t launch_get_state(const Launch& L, int64_t t, double* out) {
-  return L.dtype == LBM_FP64 ? get_typed<double>(L, t, out) : get_typed<float>(L, t, out);
+  switch (L.dtype) {
+    case LBM_FP64: return get_typed<double>(L, t, out);
+    case LBM_FP32: return get_typed<float>(L, t, out);
+    case LBM_FP16: return get_typed<_Float16>(L, t, out);
+    default: return get_typed<__bf16>(L, t, out);
+  }
 }
 
 template <typename S>
@@ -974,7 +1017,12 @@ static hipError_t set_typed(const Launch& L, int64_t t, const double* in) {
 }
 
 hipError_t launch_set_state(const Launch& L, int64_t t, const double* in) {
-  return L.dtype == LBM_FP64 ? set_typed<double>(L, t, in) : set_typed<float>(L, t, in);
+  switch (L.dtype) {
+    case LBM_FP64: return set_typed<double>(L, t, in);
+    case LBM_FP32: return set_typed<float>(L, t, in);
+    case LBM_FP16: return set_typed<_Float16>(L, t, in);
+    default: return set_typed<__bf16>(L, t, in);
+  }
 }
 
 template <typename S>
@@ -985,8 +1033,12 @@ static hipError_t moments_typed(const Launch& L, int64_t t, double* out, bool ma
 }
 
 hipError_t launch_moments(const Launch& L, int64_t t, double* out, bool mark_nonfinite) {
-  return L.dtype == LBM_FP64 ? moments_typed<double>(L, t, out, mark_nonfinite)
-                             : moments_typed<float>(L, t, out, mark_nonfinite);
+  switch (L.dtype) {
+    case LBM_FP64: return moments_typed<double>(L, t, out, mark_nonfinite);
+    case LBM_FP32: return moments_typed<float>(L, t, out, mark_nonfinite);
+    case LBM_FP16: return moments_typed<_Float16>(L, t, out, mark_nonfinite);
+    default: return moments_typed<__bf16>(L, t, out, mark_nonfinite);
+  }
 }
 
 hipError_t launch_diagnostics(const Launch& L, int64_t t, double* vals_host) {

@@ -25,6 +25,8 @@ LBM_ENONFINITE = -4
 
 LBM_FP64 = 0
 LBM_FP32 = 1
+LBM_FP16 = 2
+LBM_BF16 = 3
 LBM_STENCIL_ISO9 = 0
 LBM_STENCIL_CENTRAL5 = 1
 LBM_SCHED_FUSED = 0
