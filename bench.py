@@ -112,6 +112,50 @@ def cpu_baseline(les_steps: int, dns_steps: int) -> dict:
     }
 
 
+def precision_study(steps: int, dev, stream) -> int:
+    """Per-field relative L2 error (rho; m as a vector field; B as a vector
+    field) of FP32, FP16 and BF16 storage against an FP64 run of the same
+    8192^2 jet, every `steps // 10` steps."""
+    import torch
+
+    from paper_1705_09807_amd import Sim
+
+    n, nu, b0 = 8192, 1e-4, 0.01
+    kh = dict(KH)
+    kh["B0"] = b0
+    ghost = dict(s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
+    sims = {dt: Sim(nx=n, ny=n, nu=nu, eta=nu, delta=0.0, dtype=dt, b_ref=(b0, 0.0), device=dev, stream=stream,
+                    **ghost) for dt in ("fp64", "fp32", "fp16", "bf16")}
+    for sim in sims.values():
+        sim.init_kh_jet(seed=0, **kh)
+    out = {"study": "storage precision vs FP64", "grid": n, "nu": nu, "eta": nu, "B0": b0,
+           "mrt_ghost_rates": GHOST, "delta": 0.0, "records": []}
+    every = max(1, steps // 10)
+    ref = torch.empty((5, n, n), dtype=torch.float64, device=dev)
+    cur = torch.empty_like(ref)
+
+    def rel(a, b):
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+    done = 0
+    while done < steps:
+        c = min(every, steps - done)
+        for sim in sims.values():
+            sim.step(c)
+        done += c
+        sims["fp64"].moments(ref)
+        rec = {"t": done}
+        for dt in ("fp32", "fp16", "bf16"):
+            sims[dt].moments(cur)
+            rec[dt] = {"rho": rel(cur[0], ref[0]), "m": rel(cur[1:3], ref[1:3]), "B": rel(cur[3:5], ref[3:5])}
+        d = sims["fp64"].diagnostics()
+        rec["fp64_e_kin"], rec["fp64_enstrophy"], rec["fp64_nonfinite"] = d["e_kin"], d["enstrophy"], d["nonfinite"]
+        out["records"].append(rec)
+        log(json.dumps(rec))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +169,10 @@ def main() -> int:
     ap.add_argument("--cpu-les-steps", type=int, default=15)
     ap.add_argument("--cpu-dns-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
+                    help="instead of the benchmark: run the 8192^2 jet (nu = eta = 1e-4, B0 = 0.01) "
+                         "for STEPS steps in FP64, FP32, FP16 and BF16 storage and print the per-field "
+                         "relative L2 errors against the FP64 run as one JSON line")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, run a plain device-to-device copy of this many bytes "
                          "(reference kernel for the HBM byte counters)")
@@ -146,6 +194,8 @@ def main() -> int:
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     log(f"device: {torch.cuda.get_device_name(dev)}")
+    if args.precision_study > 0:
+        return precision_study(args.precision_study, dev, stream)
 
     bref = (KH["B0"], 0.0)
     ghost = dict(s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
