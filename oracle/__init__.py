@@ -19,6 +19,15 @@ linear
     A brute-force Fourier-space linearisation of one timestep about a uniform
     equilibrium.  Its eigenvalues give the exact discrete decay rates and
     frequencies of small-amplitude waves, used to pin the oracle.
+learned
+    The learned closure: Gaussian filtering and subsampling of a fine-grid
+    state, the exact subgrid terms of the filtered products, the analytic
+    closure in the same four components, the network's input patches, a
+    two-hidden-layer network with the GPU's bfloat16 roundings, its loss
+    gradients and Adam.  ``Oracle(closure_correction=...)`` adds a correction
+    to the analytic closure.
+spectra
+    Radially binned kinetic and magnetic energy spectra.
 
 Parity status: every function of ``lbmhd_oracle`` is pinned by the CPU tests
 (printed matrices and tables, closed forms, invariants, brute force) except the

@@ -316,7 +316,7 @@ class Oracle:
 
     def __init__(self, nx: int, ny: int, nu: float, eta: float, delta: float = 0.0,
                  closure_scale: float = 1.0, s5=None, s6=None, s7=None, s8=None,
-                 grad_stencil: str = "iso9"):
+                 grad_stencil: str = "iso9", closure_correction=None):
         if nx < 4 or ny < 4:
             raise ValueError("grid must be at least 4 x 4")
         self.nx, self.ny = int(nx), int(ny)
@@ -329,6 +329,9 @@ class Oracle:
         if not all(0.0 < r < 2.0 for r in list(self.rates[3:]) + [self.s_m]):
             raise ValueError("relaxation rates must lie in (0, 2)")
         self.grad_stencil = grad_stencil
+        # optional learned correction: (rho, m_x, m_y, B_x, B_y) -> [4, ny, nx] of
+        # (tau_xx, tau_xy, tau_yy, eps) added to the analytic closure terms
+        self.closure_correction = closure_correction
         self.f = np.zeros((9, self.ny, self.nx))
         self.g = np.zeros((5, 2, self.ny, self.nx))
         self.t = 0
@@ -381,9 +384,19 @@ class Oracle:
         rho, mx, my, Bx, By = self._moments(f, g)
         P, Q, R = closure_terms(rho, mx, my, Bx, By, self.k2, self.grad_stencil)
         meq = filtered_equilibrium_moments(rho, mx, my, Bx, By, P, Q)
+        lam = filtered_induction(rho, mx, my, Bx, By, R)
+        if self.closure_correction is not None:
+            # tau_xy enters M3, tau_xx - tau_yy M4, -3 (tau_xx + tau_yy) M7 and M8,
+            # eps the induction moment Lam[x, y] = -Lam[y, x]
+            c = self.closure_correction(rho, mx, my, Bx, By)
+            meq[3] = meq[3] + c[1]
+            meq[4] = meq[4] + c[0] - c[2]
+            meq[7] = meq[7] - 3.0 * (c[0] + c[2])
+            meq[8] = meq[8] - 3.0 * (c[0] + c[2])
+            lam[0, 1] = lam[0, 1] + c[3]
+            lam[1, 0] = lam[1, 0] - c[3]
         M = np.tensordot(T, f, axes=(1, 0))
         fstar = f - np.tensordot(T_INV, self.rates[:, None, None] * (M - meq), axes=(1, 0))
-        lam = filtered_induction(rho, mx, my, Bx, By, R)
         geq = g_equilibrium_from_moments(Bx, By, lam)
         gstar = g - self.s_m * (g - geq)
         return fstar, gstar
