@@ -22,10 +22,15 @@ The learned network predicts exact minus analytic.  Inputs: the 3x3 patch of
 differences), index = field * 9 + (dy + 1) * 3 + (dx + 1), padded to 64.
 
 MLP 63 -> 64 -> 64 -> 4, tanh hidden activations, inputs normalised as
-(x - shift) * scale, outputs multiplied by out_scale.  The GPU rounds the
-normalised inputs, both hidden activations and all weights to bfloat16
-(round to nearest even) and accumulates in FP32; the reference below does
-the same roundings and accumulates in FP64.
+z = (x - shift) * scale with one shift and scale per input field (the mean
+and inverse standard deviation of the field's centre feature), outputs
+multiplied by out_scale (the root mean square of each target).  The GPU
+rounds the normalised inputs, both hidden activations and all weights to
+bfloat16 (round to nearest even) and accumulates in FP32; the reference below
+does the same roundings and accumulates in FP64.  The normalisation itself is
+FP32 arithmetic on both sides, because its bfloat16 rounding and the
+out-of-distribution test |z| > 6 are decisions that must be taken in the same
+precision.
 """
 
 from __future__ import annotations
@@ -143,10 +148,37 @@ def init_params(seed: int) -> dict:
             "w3": glorot(N_HID, N_OUT), "b3": np.zeros(N_OUT)}
 
 
+def feature_stats(X: np.ndarray, T: np.ndarray):
+    """(shift[64], scale[64], out_scale[4]) as FP32 values: per field f the
+    mean and 1/std (population) of the centre column X[:, 9 f + 4], expanded
+    to the field's nine columns; the pad column 63 gets shift 0, scale 1;
+    out_scale = RMS of each target column.  Zero spreads map to 1."""
+    shift = np.zeros(N_PAD)
+    scale = np.ones(N_PAD)
+    for f in range(7):
+        c = X[:, 9 * f + 4]
+        mu = c.mean()
+        sd = math.sqrt(np.mean((c - mu) ** 2))
+        shift[9 * f: 9 * f + 9] = mu
+        scale[9 * f: 9 * f + 9] = 1.0 / sd if sd > 0 else 1.0
+    rms = np.sqrt(np.mean(T * T, axis=0))
+    out_scale = np.where(rms > 0, rms, 1.0)
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    return f32(shift), f32(scale), f32(out_scale)
+
+
+def normalise(X, shift, scale) -> np.ndarray:
+    """z = (x - shift) * scale in FP32 arithmetic (pad column forced to 0)."""
+    z = (np.asarray(X, np.float32) - np.asarray(shift, np.float32)) * np.asarray(scale, np.float32)
+    z = z.astype(np.float64)
+    z[:, N_IN:] = 0.0
+    return z
+
+
 def forward(p: dict, X: np.ndarray, shift: np.ndarray, scale: np.ndarray, rnd=bf16):
     """Normalised output y [n, 4] and the cached activations.  `rnd` is the
     rounding applied where the GPU rounds to bfloat16 (identity: exact math)."""
-    z = rnd((X - shift) * scale)
+    z = rnd(normalise(X, shift, scale))
     a1 = z @ rnd(p["w1"]) + p["b1"]
     h1 = rnd(np.tanh(a1))
     a2 = h1 @ rnd(p["w2"]) + p["b2"]
@@ -180,7 +212,7 @@ def learned_correction(p: dict, shift, scale, out_scale, ood: float = 6.0):
     def corr(rho, mx, my, bx, by):
         X = closure_features(rho, mx, my, bx, by)
         y, _ = forward(p, X, shift, scale)
-        zn = np.abs((X - shift) * scale)
+        zn = np.abs(normalise(X, shift, scale))
         y = np.where((zn > ood).any(axis=1, keepdims=True), 0.0, y * out_scale)
         return y.T.reshape((N_OUT,) + rho.shape)
     return corr

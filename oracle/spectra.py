@@ -11,6 +11,9 @@ periodic N x N grid with integer wavenumbers k = (k_x, k_y), k_a in
   E_M(n) = the same with B_x, B_y,
 with u = m / rho, n = 0 .. nbins - 1 and round(r) = floor(r + 1/2).  With this
 normalisation sum_n E_K(n) is the mean of |u|^2 / 2 over the grid (Parseval).
+The streamwise spectrum E_x(m) = 1/2 sum_{k : |k_x| = m} (...), m = 0 .. N/2,
+follows single Fourier modes of the jet (the growth of its m = 1 mode is the
+Kelvin-Helmholtz growth rate).
 """
 
 from __future__ import annotations
@@ -43,3 +46,11 @@ def spectrum(*fields) -> np.ndarray:
 def energy_spectra(rho, mx, my, bx, by):
     """(E_K, E_M) of one state's moments."""
     return spectrum(mx / rho, my / rho), spectrum(bx, by)
+
+
+def x_spectrum(*fields) -> np.ndarray:
+    """1/2 sum over the fields of |FFT(a) / N^2|^2, summed per |k_x|."""
+    n = fields[0].shape[0]
+    p = sum(np.abs(np.fft.fft2(a) / (n * n)) ** 2 for a in fields).sum(axis=0)
+    kx = np.abs(np.fft.fftfreq(n) * n).astype(np.int64)
+    return 0.5 * np.bincount(kx, weights=p, minlength=n // 2 + 1)

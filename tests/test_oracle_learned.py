@@ -225,11 +225,39 @@ def test_mlp_forward_against_torch():
         def tb(a):
             return torch.from_numpy(np.asarray(a, dtype=np.float64))
         r = (lambda t: t) if rnd is not L.bf16 else (lambda t: t.to(torch.float32).to(torch.bfloat16).to(torch.float64))
-        z = r(tb((X - shift) * scale))
+        # FP32 normalisation (torch float32 arithmetic), pad column 0
+        z32 = (torch.from_numpy(X.astype(np.float32)) - torch.from_numpy(shift.astype(np.float32))) \
+            * torch.from_numpy(scale.astype(np.float32))
+        z32[:, 63] = 0
+        z = r(z32.to(torch.float64))
         h = r(torch.tanh(z @ r(tb(p["w1"])) + tb(p["b1"])))
         h = r(torch.tanh(h @ r(tb(p["w2"])) + tb(p["b2"])))
         want = (h @ r(tb(p["w3"])) + tb(p["b3"])).numpy()
         assert np.max(np.abs(y - want)) < 1e-12
+
+
+def test_feature_stats_brute_force():
+    rng = np.random.default_rng(14)
+    n = 50
+    X = rng.standard_normal((n, 64)) * 0.3 + 1.0
+    X[:, 5 * 9 + 4] = 0.25                      # a constant field: scale 1
+    T = rng.standard_normal((n, 4)) * 1e-5
+    shift, scale, out_scale = L.feature_stats(X, T)
+    for f in range(7):
+        c = [X[i, 9 * f + 4] for i in range(n)]
+        mu = sum(c) / n
+        var = sum((v - mu) ** 2 for v in c) / n
+        want_scale = 1.0 / math.sqrt(var) if var > 0 else 1.0
+        for k in range(9 * f, 9 * f + 9):
+            assert shift[k] == float(np.float32(mu))
+            assert abs(scale[k] - want_scale) <= 1e-7 * want_scale
+    assert shift[63] == 0 and scale[63] == 1
+    for o in range(4):
+        assert abs(out_scale[o] - math.sqrt(sum(T[i, o] ** 2 for i in range(n)) / n)) <= 1e-7 * out_scale[o]
+    # the normalised centre features then have mean 0 and unit spread
+    z = L.normalise(X, shift, scale)
+    assert abs(z[:, 4].mean()) < 1e-6 and abs(z[:, 4].std() - 1) < 1e-6
+    assert np.all(z[:, 63] == 0)
 
 
 def test_mlp_gradients_finite_differences():
@@ -391,3 +419,18 @@ def test_energy_spectra_sum_to_diagnostic_energies():
     EK, EM = S.energy_spectra(rho, mx, my, bx, by)
     assert abs(EK.sum() - 0.5 * np.mean((mx * mx + my * my) / rho ** 2)) < 1e-15
     assert abs(EM.sum() - 0.5 * np.mean(bx * bx + by * by)) < 1e-15
+
+
+def test_x_spectrum_single_modes_and_parseval():
+    n = 32
+    y, x = np.mgrid[0:n, 0:n]
+    a = 0.2 * np.cos(2 * np.pi * (3 * x + 5 * y) / n) + 0.1 * np.sin(2 * np.pi * 7 * y / n)
+    E = S.x_spectrum(a)
+    assert E.shape == (n // 2 + 1,)
+    assert abs(E[3] - 0.2 ** 2 / 4) < 1e-15 and abs(E[0] - 0.1 ** 2 / 4) < 1e-15
+    assert np.max(np.abs(np.delete(E, [0, 3]))) < 1e-30
+    b = np.random.default_rng(15).standard_normal((n, n))
+    assert abs(S.x_spectrum(a, b).sum() - 0.5 * np.mean(a * a + b * b)) < 1e-14
+    # the Nyquist column k_x = -n/2 lands in the last entry
+    c = np.cos(np.pi * x)
+    assert abs(S.x_spectrum(c)[n // 2] - 0.5) < 1e-15
