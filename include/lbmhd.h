@@ -68,6 +68,11 @@ extern "C" {
 #define LBM_SCHED_AA 1     /* one buffer updated in place (AA pattern); with the
                               closure on, a moment sweep precedes the collide sweep */
 
+/* Subgrid closure of the LES (Delta > 0). */
+#define LBM_CLOSURE_ANALYTIC 0  /* the Delta^2/12 closure of Sec. 2.1 / Sec. 3      */
+#define LBM_CLOSURE_LEARNED 1   /* analytic plus a learned per-cell correction
+                                   (lbmhd_learned.h); LBM_SCHED_FUSED only        */
+
 typedef struct lbm_ctx lbm_ctx;
 
 /* Run parameters, lattice units.  Rates follow Sec. 2: s3 = s4 = 2/(6 nu + 1)
@@ -83,7 +88,7 @@ typedef struct {
   int32_t grad_stencil;    /* LBM_STENCIL_*                                   */
   int32_t dtype;           /* LBM_FP64, LBM_FP32, LBM_FP16 or LBM_BF16        */
   int32_t schedule;        /* LBM_SCHED_*                                     */
-  int32_t reserved;        /* must be 0                                       */
+  int32_t closure;         /* LBM_CLOSURE_*                                   */
   double rho0;             /* reference density of the FP32 deviations, > 0   */
   double bref_x, bref_y;   /* reference field of the FP32 g deviations (finite;
                               the run's mean field, e.g. (B0, 0) for the jet) */
@@ -115,7 +120,8 @@ typedef struct {
 /* Bytes of the caller-owned device buffers for these parameters (0 if the
  * parameters are invalid).  The state holds the populations in the storage
  * precision, one buffer (AA) or two (fused); the work buffer holds moment
- * planes and reduction partials. */
+ * planes and reduction partials (and, with the learned closure, the network
+ * and its input and output planes). */
 size_t lbm_state_bytes(const lbm_params* p);
 size_t lbm_work_bytes(const lbm_params* p);
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbmhd.so")
 
-SOURCES = ["lbmhd_kernels.hip", "lbmhd_api.cpp"]
+SOURCES = ["lbmhd_kernels.hip", "lbmhd_learned.hip", "lbmhd_api.cpp"]
 
 # Packed FP32 instructions are disabled for all device code; the host pass
 # warns that it does not know the feature, which is harmless.

@@ -1,6 +1,7 @@
-// C ABI of the filtered LB-MHD engine: parameter validation, rates, buffer
-// binding, time/parity bookkeeping and error reporting.  The per-cell
-// arithmetic and all device work live in lbmhd_kernels.hip.
+// C ABI of the filtered LB-MHD engine (lbmhd.h, lbmhd_learned.h): parameter
+// validation, rates, buffer binding, time/parity bookkeeping and error
+// reporting.  The per-cell arithmetic and all device work live in
+// lbmhd_kernels.hip and lbmhd_learned.hip.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -12,12 +13,14 @@
 
 #include "lbmhd.h"
 #include "lbmhd_internal.h"
+#include "lbmhd_learned.h"
 
 struct lbm_ctx {
   lbm_params p;
   lbm::Launch L;
   int64_t t = 0;
   bool initialized = false;
+  bool mlp_set = false;  // learned closure: a network has been installed
 };
 
 namespace {
@@ -56,7 +59,10 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     return fail(LBM_EINVAL, "grad_stencil must be LBM_STENCIL_ISO9 or LBM_STENCIL_CENTRAL5");
   if (p->schedule != LBM_SCHED_FUSED && p->schedule != LBM_SCHED_AA)
     return fail(LBM_EINVAL, "schedule must be LBM_SCHED_FUSED or LBM_SCHED_AA");
-  if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+  if (p->closure != LBM_CLOSURE_ANALYTIC && p->closure != LBM_CLOSURE_LEARNED)
+    return fail(LBM_EINVAL, "closure must be LBM_CLOSURE_ANALYTIC or LBM_CLOSURE_LEARNED");
+  if (p->closure == LBM_CLOSURE_LEARNED && p->schedule != LBM_SCHED_FUSED)
+    return fail(LBM_EINVAL, "the learned closure runs with LBM_SCHED_FUSED only");
   if (!finite_pos(p->rho0)) return fail(LBM_EINVAL, "rho0 must be finite and > 0");
   if (!std::isfinite(p->bref_x) || !std::isfinite(p->bref_y)) return fail(LBM_EINVAL, "bref must be finite");
   if (L) {
@@ -68,6 +74,7 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     L->dtype = p->dtype;
     L->schedule = p->schedule;
     L->stencil = p->grad_stencil;
+    L->learned = p->closure == LBM_CLOSURE_LEARNED;
     for (double& r : L->rate) r = 0.0;
     L->rate[3] = s;
     L->rate[4] = s;
@@ -148,6 +155,8 @@ int lbm_step(lbm_ctx* ctx, int64_t n) {
   int rc = check_ctx(ctx, true);
   if (rc != LBM_OK) return rc;
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (ctx->L.learned && !ctx->mlp_set)
+    return fail(LBM_ESTATE, "learned closure: install a network with lbm_set_closure_mlp first");
   for (int64_t k = 0; k < n; ++k) {
     hipError_t e = lbm::launch_step(ctx->L, ctx->t);
     if (e != hipSuccess) return hip_fail(e, "lbm_step");
@@ -215,6 +224,171 @@ int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out_host) {
   out_host->nonfinite = (int64_t)v[11];
   if (out_host->nonfinite > 0) return fail(LBM_ENONFINITE, "state holds non-finite populations");
   return LBM_OK;
+}
+
+int lbm_set_closure_mlp(lbm_ctx* ctx, const void* packed_dev) {
+  int rc = check_ctx(ctx, false);
+  if (rc != LBM_OK) return rc;
+  if (!ctx->L.learned) return fail(LBM_ESTATE, "context was not created with closure = LBM_CLOSURE_LEARNED");
+  if (!packed_dev || !aligned(packed_dev))
+    return fail(LBM_EINVAL, "packed_dev must be a non-NULL 256-byte aligned pointer");
+  hipError_t e = hipMemcpyAsync(static_cast<char*>(ctx->L.work) + ctx->L.off_mlp, packed_dev, LBM_MLP_PACKED_BYTES,
+                                hipMemcpyDeviceToDevice, ctx->L.stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_set_closure_mlp");
+  ctx->mlp_set = true;
+  return LBM_OK;
+}
+
+int lbm_closure_correction(lbm_ctx* ctx, float* out_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc != LBM_OK) return rc;
+  if (!ctx->L.learned || !ctx->mlp_set)
+    return fail(LBM_ESTATE, "needs closure = LBM_CLOSURE_LEARNED and an installed network");
+  if (!out_dev || !aligned(out_dev)) return fail(LBM_EINVAL, "out_dev must be a non-NULL 256-byte aligned pointer");
+  hipError_t e = lbm::launch_correction(ctx->L, ctx->t, out_dev);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_closure_correction");
+}
+
+// ---------------------------------------------------------------------------
+// Learned closure, filtered DNS and spectra (lbmhd_learned.h)
+// ---------------------------------------------------------------------------
+
+int lbm_mlp_pack(const float* params_dev, const lbm_mlp_norm* norm_dev, void* packed_dev, void* hip_stream) {
+  if (!params_dev || !norm_dev || !packed_dev || !aligned(params_dev) || !aligned(norm_dev) || !aligned(packed_dev))
+    return fail(LBM_EINVAL, "params, norm and packed must be non-NULL 256-byte aligned device pointers");
+  hipError_t e = lbm::launch_mlp_pack(params_dev, norm_dev, packed_dev, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_mlp_pack");
+}
+
+int lbm_mlp_forward(const void* packed_dev, const float* x_dev, int64_t n, float* y_dev, int32_t* ood_dev,
+                    void* hip_stream) {
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  if (!packed_dev || !x_dev || !y_dev || !aligned(packed_dev) || !aligned(x_dev) || !aligned(y_dev) ||
+      (ood_dev && !aligned(ood_dev)))
+    return fail(LBM_EINVAL, "packed, x, y (and ood if given) must be non-NULL 256-byte aligned device pointers");
+  hipError_t e = lbm::launch_mlp_forward(packed_dev, x_dev, n, y_dev, ood_dev, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_mlp_forward");
+}
+
+size_t lbm_mlp_stats_work_bytes(int64_t n) { return n >= 2 ? lbm::mlp_stats_work_bytes() : 0; }
+
+int lbm_mlp_feature_stats(const float* x_dev, const float* t_dev, int64_t n, lbm_mlp_norm* norm_dev, void* work_dev,
+                          size_t work_bytes, void* hip_stream) {
+  if (n < 2) return fail(LBM_EINVAL, "n must be >= 2");
+  if (!x_dev || !t_dev || !norm_dev || !work_dev || !aligned(x_dev) || !aligned(t_dev) || !aligned(norm_dev) ||
+      !aligned(work_dev))
+    return fail(LBM_EINVAL, "x, t, norm and work must be non-NULL 256-byte aligned device pointers");
+  if (work_bytes < lbm::mlp_stats_work_bytes()) return fail(LBM_EINVAL, "work buffer too small");
+  hipError_t e = lbm::launch_mlp_stats(x_dev, t_dev, n, norm_dev, work_dev, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_mlp_feature_stats");
+}
+
+size_t lbm_mlp_train_work_bytes(int32_t batch) {
+  return (batch >= 1 && batch <= (1 << 20)) ? lbm::mlp_train_work_bytes(batch) : 0;
+}
+
+int lbm_mlp_gradient(const float* params_dev, const lbm_mlp_norm* norm_dev, const float* x_dev, const float* t_dev,
+                     const int32_t* idx_dev, int32_t batch, void* work_dev, size_t work_bytes, float* grad_dev,
+                     float* loss_dev, void* hip_stream) {
+  if (batch < 1 || batch > (1 << 20)) return fail(LBM_EINVAL, "batch must lie in [1, 2^20]");
+  const void* ptrs[] = {params_dev, norm_dev, x_dev, t_dev, idx_dev, work_dev, grad_dev};
+  for (const void* q : ptrs)
+    if (!q || !aligned(q)) return fail(LBM_EINVAL, "device pointers must be non-NULL and 256-byte aligned");
+  if (work_bytes < lbm::mlp_train_work_bytes(batch)) return fail(LBM_EINVAL, "work buffer too small");
+  hipError_t e = lbm::launch_mlp_gradient(params_dev, norm_dev, x_dev, t_dev, idx_dev, batch, work_dev, grad_dev,
+                                          loss_dev, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_mlp_gradient");
+}
+
+int lbm_mlp_adam(float* params_dev, float* adam_m_dev, float* adam_v_dev, const float* grad_dev, int64_t step,
+                 double lr, void* hip_stream) {
+  if (step < 1) return fail(LBM_EINVAL, "step must be >= 1");
+  if (!std::isfinite(lr) || lr <= 0.0) return fail(LBM_EINVAL, "lr must be finite and > 0");
+  const void* ptrs[] = {params_dev, adam_m_dev, adam_v_dev, grad_dev};
+  for (const void* q : ptrs)
+    if (!q || !aligned(q)) return fail(LBM_EINVAL, "device pointers must be non-NULL and 256-byte aligned");
+  hipError_t e = lbm::launch_mlp_adam(params_dev, adam_m_dev, adam_v_dev, grad_dev, step, lr,
+                                      static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_mlp_adam");
+}
+
+int lbm_mlp_train_step(float* params_dev, float* adam_m_dev, float* adam_v_dev, int64_t step, double lr,
+                       const lbm_mlp_norm* norm_dev, const float* x_dev, const float* t_dev, const int32_t* idx_dev,
+                       int32_t batch, void* work_dev, size_t work_bytes, float* loss_dev, void* hip_stream) {
+  if (batch < 1 || batch > (1 << 20)) return fail(LBM_EINVAL, "batch must lie in [1, 2^20]");
+  if (step < 1) return fail(LBM_EINVAL, "step must be >= 1");
+  if (!std::isfinite(lr) || lr <= 0.0) return fail(LBM_EINVAL, "lr must be finite and > 0");
+  const void* ptrs[] = {params_dev, adam_m_dev, adam_v_dev, norm_dev, x_dev, t_dev, idx_dev, work_dev};
+  for (const void* q : ptrs)
+    if (!q || !aligned(q)) return fail(LBM_EINVAL, "device pointers must be non-NULL and 256-byte aligned");
+  if (work_bytes < lbm::mlp_train_work_bytes(batch)) return fail(LBM_EINVAL, "work buffer too small");
+  hipError_t e = lbm::launch_mlp_train(params_dev, adam_m_dev, adam_v_dev, step, lr, norm_dev, x_dev, t_dev, idx_dev,
+                                       batch, work_dev, loss_dev, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_mlp_train_step");
+}
+
+namespace {
+int check_filter(int32_t nx, int32_t ny, int32_t factor, double delta) {
+  if (nx < 4 || ny < 4 || nx > 32768 || ny > 32768) return fail(LBM_EINVAL, "nx and ny must lie in [4, 32768]");
+  if (factor != 1 && factor != 2 && factor != 4 && factor != 8 && factor != 16)
+    return fail(LBM_EINVAL, "factor must be 1, 2, 4, 8 or 16");
+  if (nx % factor || ny % factor) return fail(LBM_EINVAL, "factor must divide nx and ny");
+  if (!std::isfinite(delta) || delta <= 0.0) return fail(LBM_EINVAL, "delta must be finite and > 0");
+  const int R = lbm::filter_radius(delta);
+  if (R > 127 || R >= nx || R >= ny) return fail(LBM_EINVAL, "filter radius ceil(5 delta / sqrt(12)) too large");
+  return LBM_OK;
+}
+}  // namespace
+
+size_t lbm_filter_work_bytes(int32_t nx, int32_t ny, int32_t factor, double delta) {
+  if (check_filter(nx, ny, factor, delta) != LBM_OK) return 0;
+  return lbm::filter_work_bytes(nx, ny, factor);
+}
+
+int lbm_filter_subsample(const double* mom_dev, int32_t nx, int32_t ny, int32_t factor, double delta,
+                         double* out_dev, void* work_dev, size_t work_bytes, void* hip_stream) {
+  int rc = check_filter(nx, ny, factor, delta);
+  if (rc != LBM_OK) return rc;
+  if (!mom_dev || !out_dev || !work_dev || !aligned(mom_dev) || !aligned(out_dev) || !aligned(work_dev))
+    return fail(LBM_EINVAL, "mom, out and work must be non-NULL 256-byte aligned device pointers");
+  if (work_bytes < lbm::filter_work_bytes(nx, ny, factor)) return fail(LBM_EINVAL, "work buffer too small");
+  hipError_t e =
+      lbm::launch_filter(mom_dev, nx, ny, factor, delta, out_dev, work_dev, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_filter_subsample");
+}
+
+int lbm_closure_samples(const double* coarse_dev, int32_t nx, int32_t ny, double delta, int32_t grad_stencil,
+                        float* x_dev, float* t_dev, void* hip_stream) {
+  if (nx < 4 || ny < 4 || nx > 32768 || ny > 32768) return fail(LBM_EINVAL, "nx and ny must lie in [4, 32768]");
+  if (!std::isfinite(delta) || delta < 0.0) return fail(LBM_EINVAL, "delta must be finite and >= 0");
+  if (grad_stencil != LBM_STENCIL_ISO9 && grad_stencil != LBM_STENCIL_CENTRAL5)
+    return fail(LBM_EINVAL, "grad_stencil must be LBM_STENCIL_ISO9 or LBM_STENCIL_CENTRAL5");
+  if (!coarse_dev || !x_dev || !t_dev || !aligned(coarse_dev) || !aligned(x_dev) || !aligned(t_dev))
+    return fail(LBM_EINVAL, "coarse, x and t must be non-NULL 256-byte aligned device pointers");
+  hipError_t e = lbm::launch_closure_samples(coarse_dev, nx, ny, delta, grad_stencil, x_dev, t_dev,
+                                             static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_closure_samples");
+}
+
+namespace {
+bool spectra_n_ok(int32_t n) { return n >= 8 && n <= 4096 && (n & (n - 1)) == 0; }
+}  // namespace
+
+int32_t lbm_spectra_bins(int32_t n) { return spectra_n_ok(n) ? lbm::spectra_bins(n) : 0; }
+
+size_t lbm_spectra_work_bytes(int32_t n) { return spectra_n_ok(n) ? lbm::spectra_work_bytes(n) : 0; }
+
+int lbm_spectra(const double* mom_dev, int32_t n, double* ek_dev, double* em_dev, double* ekx_dev, void* work_dev,
+                size_t work_bytes, void* hip_stream) {
+  if (!spectra_n_ok(n)) return fail(LBM_EINVAL, "n must be a power of two in [8, 4096]");
+  if (!mom_dev || !ek_dev || !em_dev || !work_dev || !aligned(mom_dev) || !aligned(ek_dev) || !aligned(em_dev) ||
+      !aligned(work_dev) || (ekx_dev && !aligned(ekx_dev)))
+    return fail(LBM_EINVAL, "mom, ek, em, work (and ekx if given) must be non-NULL 256-byte aligned device pointers");
+  if (work_bytes < lbm::spectra_work_bytes(n)) return fail(LBM_EINVAL, "work buffer too small");
+  hipError_t e =
+      lbm::launch_spectra(mom_dev, n, ek_dev, em_dev, ekx_dev, work_dev, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_spectra");
 }
 
 int lbm_destroy(lbm_ctx* ctx) {

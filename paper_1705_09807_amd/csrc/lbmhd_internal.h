@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "lbmhd.h"
+#include "lbmhd_learned.h"
 
 namespace lbm {
 
@@ -33,6 +34,10 @@ struct Launch {
   size_t off_part = 0;            // per-block reduction partials
   size_t off_final = 0;           // final reduction values
   int diag_blocks = 0;
+  bool learned = false;           // analytic closure plus the network's correction
+  size_t off_mom5 = 0;            // 5 FP32 moment planes (network input)
+  size_t off_corr = 0;            // 4 FP32 correction planes
+  size_t off_mlp = 0;             // packed network
   hipStream_t stream = nullptr;
 };
 
@@ -51,5 +56,33 @@ hipError_t launch_set_state(const Launch& L, int64_t t, const double* in);
 hipError_t launch_moments(const Launch& L, int64_t t, double* out, bool mark_nonfinite);
 // Diagnostics: enqueue, copy kDiagVals doubles to host, synchronise the stream.
 hipError_t launch_diagnostics(const Launch& L, int64_t t, double* vals_host);
+// Learned correction of the state at time t into 4 FP32 planes.
+hipError_t launch_correction(const Launch& L, int64_t t, float* out);
+
+// Learned closure, filtered DNS and spectra (lbmhd_learned.hip).
+hipError_t launch_mlp_pack(const float* params, const lbm_mlp_norm* norm, void* packed, hipStream_t st);
+hipError_t launch_mlp_forward(const void* packed, const float* x, int64_t n, float* y, int32_t* ood, hipStream_t st);
+size_t mlp_train_work_bytes(int batch);
+hipError_t launch_mlp_gradient(const float* params, const lbm_mlp_norm* norm, const float* x, const float* t,
+                               const int32_t* idx, int batch, void* work, float* grad, float* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t step, double lr,
+                           hipStream_t st);
+hipError_t launch_mlp_train(float* params, float* m, float* v, int64_t step, double lr, const lbm_mlp_norm* norm,
+                            const float* x, const float* t, const int32_t* idx, int batch, void* work, float* loss,
+                            hipStream_t st);
+size_t mlp_stats_work_bytes();
+hipError_t launch_mlp_stats(const float* x, const float* t, int64_t n, lbm_mlp_norm* norm, void* work,
+                            hipStream_t st);
+int filter_radius(double delta);
+size_t filter_work_bytes(int nx, int ny, int factor);
+hipError_t launch_filter(const double* mom, int nx, int ny, int factor, double delta, double* out, void* work,
+                         hipStream_t st);
+hipError_t launch_closure_samples(const double* c12, int nx, int ny, double delta, int stencil, float* x, float* t,
+                                  hipStream_t st);
+hipError_t launch_mlp_correct(const float* mom5, const void* packed, float* corr, int nx, int ny, hipStream_t st);
+int spectra_bins(int n);
+size_t spectra_work_bytes(int n);
+hipError_t launch_spectra(const double* mom, int n, double* ek, double* em, double* ekx, void* work,
+                          hipStream_t st);
 
 }  // namespace lbm

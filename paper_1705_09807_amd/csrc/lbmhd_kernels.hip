@@ -31,7 +31,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbmhd_device.h"
 #include "lbmhd_internal.h"
+#include "lbmhd_learned.h"
 
 namespace lbm {
 
@@ -141,55 +143,6 @@ __device__ __forceinline__ Mom<C> moments19(const C v[kQ]) {
   m.dbx = ((v[9] + v[10]) + (v[11] + v[12])) + v[13];
   m.dby = ((v[14] + v[15]) + (v[16] + v[17])) + v[18];
   return m;
-}
-
-// Subgrid terms of the filtered equilibria (Sec. 2.1 FilterExampleSmall with
-// density gradients dropped, Sec. 3).  g*_ab = D_b m_a, h*_ab = D_b B_a; with
-// k2 = closure_scale Delta^2 / 12:
-//   P_ac = k2/rho sum_b D_b m_a D_b m_c   (Reynolds products m_a m_c / rho)
-//   Q_ac = k2     sum_b D_b B_a D_b B_c   (Maxwell products B_a B_c)
-//   R_ac = k2/rho sum_b D_b m_a D_b B_c   (induction products m_a B_c / rho)
-// tau_xy = P_xy - Q_xy enters M3; tau_d = (P_xx - P_yy) - (Q_xx - Q_yy) enters
-// M4; tau_s = P_xx + P_yy enters M7 and M8 (times -3); eps = R_xy - R_yx is
-// the filtered part of the induction moment E = (u x B)_z.
-template <typename C>
-struct Closure {
-  C tau_xy, tau_d, tau_s, eps;
-};
-
-template <typename C>
-__device__ __forceinline__ Closure<C> closure_terms(C gxx, C gxy, C gyx, C gyy, C hxx, C hxy, C hyx,
-                                                    C hyy, C inv_rho, C k2) {
-  const C kr = k2 * inv_rho;
-  const C pxx = kr * (gxx * gxx + gxy * gxy);
-  const C pyy = kr * (gyx * gyx + gyy * gyy);
-  const C pxy = kr * (gxx * gyx + gxy * gyy);
-  const C qxx = k2 * (hxx * hxx + hxy * hxy);
-  const C qyy = k2 * (hyx * hyx + hyy * hyy);
-  const C qxy = k2 * (hxx * hyx + hxy * hyy);
-  const C rxy = kr * (gxx * hyx + gxy * hyy);
-  const C ryx = kr * (gyx * hxx + gyy * hxy);
-  Closure<C> c;
-  c.tau_xy = pxy - qxy;
-  c.tau_d = (pxx - pyy) - (qxx - qyy);
-  c.tau_s = pxx + pyy;
-  c.eps = rxy - ryx;
-  return c;
-}
-
-// Discrete gradient from a 3x3 neighbourhood (value at offset (dx, dy)).
-// iso9: D_x a = (a_E - a_W)/3 + (a_NE + a_SE - a_NW - a_SW)/12 (and D_y by
-// symmetry), i.e. 3 sum_i w_i c_i a(x + c_i); central5: (a_E - a_W)/2.
-template <typename C, int STENCIL>
-__device__ __forceinline__ void grad3x3(C e, C w, C n, C s, C ne, C nw, C se, C sw, C& dx, C& dy) {
-  if (STENCIL == LBM_STENCIL_ISO9) {
-    const C third = C(1.0 / 3.0), twelfth = C(1.0 / 12.0);
-    dx = (e - w) * third + ((ne + se) - (nw + sw)) * twelfth;
-    dy = (n - s) * third + ((ne + nw) - (se + sw)) * twelfth;
-  } else {
-    dx = (e - w) * C(0.5);
-    dy = (n - s) * C(0.5);
-  }
 }
 
 // One collision of the 19 populations of a cell (Sec. 2, Sec. 3).
@@ -411,9 +364,13 @@ k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
 // Rows are software-pipelined two deep: the loads of row y+2 are issued
 // before row y is collided.  A ring slot is rewritten only after the barrier
 // that follows its last read.
-template <typename S, typename C, int W, int STENCIL, bool NT>
+//
+// With CORR, four FP32 planes (tau_xx, tau_xy, tau_yy, eps) of a learned
+// correction are added to the analytic subgrid terms of every cell.
+template <typename S, typename C, int W, int STENCIL, bool NT, bool CORR>
 __global__ void __launch_bounds__(W + 64)
-k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry, Rates<C> r) {
+k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry, Rates<C> r,
+            const float* __restrict__ corr) {
   __shared__ C ring[4][4][W + 2];
   const int tid = threadIdx.x;
   const bool halo_wave = tid >= W;
@@ -466,8 +423,16 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
       }
       const Mom<C> m = moments19(cur);
       const C ir = C(1) / (r.rho0 + m.drho);
-      const Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
-                                          gr[3][1], ir, r.k2);
+      Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
+                                    gr[3][1], ir, r.k2);
+      if constexpr (CORR) {
+        const int64_t n = (int64_t)nx * ny, ci = (int64_t)y * nx + x0 + tid;
+        const C txx = C(corr[ci]), txy = C(corr[n + ci]), tyy = C(corr[2 * n + ci]), eps = C(corr[3 * n + ci]);
+        cl.tau_xy += txy;
+        cl.tau_d += txx - tyy;
+        cl.tau_s += txx + tyy;
+        cl.eps += eps;
+      }
       collide19(cur, m, cl, r);
       const uint32_t off = uint32_t(y) * uint32_t(nx) * uint32_t(sizeof(S)) + cx.c;
 #pragma unroll
@@ -722,6 +687,27 @@ k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int 
   out[4 * n + c0] = ref.by0 + m.dby;
 }
 
+// rho, m_x, m_y, B_x, B_y in FP32 (5 dense planes): the network's input.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_moments5f(const S* __restrict__ base, float* __restrict__ out, int nx, int ny, int64_t plane, int layout,
+            RestRef ref) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  using C = typename ComputeOf<S>::type;
+  C v[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) v[q] = decode<C>(base[natural_index(q, x, y, nx, ny, plane, layout)]);
+  const Mom<C> m = moments19(v);
+  const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
+  out[c0] = float(C(ref.rho0) + m.drho);
+  out[n + c0] = float(m.mx);
+  out[2 * n + c0] = float(m.my);
+  out[3 * n + c0] = float(C(ref.bx0) + m.dbx);
+  out[4 * n + c0] = float(C(ref.by0) + m.dby);
+}
+
 // ---------------------------------------------------------------------------
 // Diagnostics: per-cell FP64 terms from the five moment planes, a fixed-order
 // grid-stride accumulation per thread, wave and block reductions into one
@@ -844,6 +830,14 @@ size_t work_layout(Launch& L) {
   off += align256((size_t)L.diag_blocks * kDiagVals * sizeof(double));
   L.off_final = off;
   off += align256(kDiagVals * sizeof(double));
+  if (L.learned) {
+    L.off_mom5 = off;
+    off += align256(5 * n * sizeof(float));
+    L.off_corr = off;
+    off += align256(4 * n * sizeof(float));
+    L.off_mlp = off;
+    off += align256(LBM_MLP_PACKED_BYTES);
+  }
   return off;
 }
 
@@ -882,21 +876,29 @@ static bool streaming_stores(const Launch& L) {
   return 2.0 * double(kQ) * double(L.nx) * double(L.ny) * double(storage_bytes(L.dtype)) > 256.0e6;
 }
 
-template <typename S, typename C, int W, bool NT>
-static void launch_les(const Launch& L, const S* src, S* dst, const Rates<C>& r) {
+template <typename S, typename C, int W, bool NT, bool CORR>
+static void launch_les_k(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
   const int ry = fused_rows(L.nx, L.ny, W);
   const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
   if (L.stencil == LBM_STENCIL_ISO9)
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT>), g, dim3(W + 64), 0, L.stream, src, dst, L.nx,
-                       L.ny, L.plane, ry, r);
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT, CORR>), g, dim3(W + 64), 0, L.stream, src, dst,
+                       L.nx, L.ny, L.plane, ry, r, corr);
   else
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT>), g, dim3(W + 64), 0, L.stream, src, dst,
-                       L.nx, L.ny, L.plane, ry, r);
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT, CORR>), g, dim3(W + 64), 0, L.stream, src,
+                       dst, L.nx, L.ny, L.plane, ry, r, corr);
+}
+
+template <typename S, typename C, int W, bool NT>
+static void launch_les(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
+  if (corr)
+    launch_les_k<S, C, W, NT, true>(L, src, dst, r, corr);
+  else
+    launch_les_k<S, C, W, NT, false>(L, src, dst, r, nullptr);
 }
 
 template <typename S, typename C, bool NT>
-static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& r) {
-  if (L.k2 == 0.0) {
+static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
+  if (L.k2 == 0.0 && !corr) {
     if ((L.nx & 1) == 0)
       hipLaunchKernelGGL((k_fused_dns_pair<S, C, NT>), dim3((L.nx + 255) / 256, L.ny), dim3(128), 0, L.stream, src,
                          dst, L.nx, L.ny, L.plane, r);
@@ -909,14 +911,34 @@ static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& 
   // FP64 strip would exceed 64 KB), 256 otherwise, 64 for narrow grids.
   if constexpr (sizeof(C) == 4) {
     if (L.nx >= 1024) {
-      launch_les<S, C, 512, NT>(L, src, dst, r);
+      launch_les<S, C, 512, NT>(L, src, dst, r, corr);
       return;
     }
   }
   if (L.nx >= 256)
-    launch_les<S, C, 256, NT>(L, src, dst, r);
+    launch_les<S, C, 256, NT>(L, src, dst, r, corr);
   else
-    launch_les<S, C, 64, NT>(L, src, dst, r);
+    launch_les<S, C, 64, NT>(L, src, dst, r, corr);
+}
+
+template <typename S>
+static hipError_t mom5f_typed(const Launch& L, int64_t t, float* out) {
+  hipLaunchKernelGGL((k_moments5f<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), out, L.nx,
+                     L.ny, L.plane, layout_at(L, t), rest_ref(L));
+  return hipGetLastError();
+}
+
+hipError_t launch_correction(const Launch& L, int64_t t, float* out) {
+  float* mom5 = reinterpret_cast<float*>(static_cast<char*>(L.work) + L.off_mom5);
+  hipError_t e;
+  switch (L.dtype) {
+    case LBM_FP64: e = mom5f_typed<double>(L, t, mom5); break;
+    case LBM_FP32: e = mom5f_typed<float>(L, t, mom5); break;
+    case LBM_FP16: e = mom5f_typed<_Float16>(L, t, mom5); break;
+    default: e = mom5f_typed<__bf16>(L, t, mom5); break;
+  }
+  if (e != hipSuccess) return e;
+  return launch_mlp_correct(mom5, static_cast<char*>(L.work) + L.off_mlp, out, L.nx, L.ny, L.stream);
 }
 
 template <typename S>
@@ -928,10 +950,17 @@ static hipError_t step_typed(const Launch& L, int64_t t) {
   if (L.schedule == LBM_SCHED_FUSED) {
     const S* src = buffer_at<S>(L, t);
     S* dst = buffer_at<S>(L, t + 1);
+    const float* corr = nullptr;
+    if (L.learned) {
+      float* c = reinterpret_cast<float*>(static_cast<char*>(L.work) + L.off_corr);
+      const hipError_t e = launch_correction(L, t, c);
+      if (e != hipSuccess) return e;
+      corr = c;
+    }
     if (streaming_stores(L))
-      launch_fused<S, C, true>(L, src, dst, r);
+      launch_fused<S, C, true>(L, src, dst, r, corr);
     else
-      launch_fused<S, C, false>(L, src, dst, r);
+      launch_fused<S, C, false>(L, src, dst, r, corr);
     return hipGetLastError();
   }
   S* A = static_cast<S*>(L.state);

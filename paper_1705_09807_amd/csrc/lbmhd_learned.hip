@@ -1,0 +1,984 @@
+// HIP kernels (gfx950) of the learned subgrid closure, the filtered-DNS
+// pipeline that trains it, and the energy spectra.
+//
+// Method: Flint & Vahala, arXiv 1705.09807.  The analytic closure (Sec. 2.1
+// FilterExampleSmall, Sec. 3) keeps the Delta^2/12 term of the filtered
+// products; the learned closure adds a per-cell correction of the same four
+// subgrid terms (tau_xx, tau_xy, tau_yy, eps), predicted by a 63-64-64-4
+// network trained on filtered DNS (the convolution of Sec. 1, VelFilter, with
+// a Gaussian of variance Delta^2/12).  The spectra are the radially binned
+// kinetic and magnetic energies compared in Sec. 4.
+//
+// Network on the matrix cores.  One wave evaluates 32 cells at a time in the
+// transposed form H^T = W^T X^T, so that every layer's output (rows = hidden
+// units, columns = cells) is directly the B operand of the next layer:
+// v_mfma_f32_32x32x16_bf16 with A = 32 rows of W^T x 16 inputs, B = 16
+// inputs x 32 cells, D = 32 x 32 FP32 (lane l holds column l % 32 and, in
+// register i, row (i/4)*8 + (l/32)*4 + i%4).  The 16-input blocks of layers 2
+// and 3 take their B operand from eight consecutive accumulator registers,
+// which hold hidden rows (2 b + j/4) * 8 + (l/32) * 4 + j % 4; the packed A
+// operands use the same permutation of the contraction index.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lbmhd_device.h"
+#include "lbmhd_internal.h"
+#include "lbmhd_learned.h"
+
+namespace lbm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Packed network (LBM_MLP_PACKED_BYTES): bfloat16 A operands in lane order,
+// FP32 biases, the normalisation.
+constexpr int kPkA1 = 0;       // [ot 2][kb 4][lane 64][8] bf16
+constexpr int kPkA2 = 8192;    // [ot 2][kb 4][lane 64][8] bf16
+constexpr int kPkA3 = 16384;   // [kb 4][lane 64][8] bf16 (rows >= 4 zero)
+constexpr int kPkB1 = 20480;   // 64 floats
+constexpr int kPkB2 = 20736;   // 64 floats
+constexpr int kPkB3 = 20992;   // 4 floats (+ pad)
+constexpr int kPkNorm = 21248;  // lbm_mlp_norm
+static_assert(kPkNorm + (int)sizeof(lbm_mlp_norm) <= LBM_MLP_PACKED_BYTES, "packed size");
+static_assert(sizeof(lbm_mlp_norm) == 128, "norm size");
+
+constexpr float kOodLimit = 6.0f;
+
+// Hidden row held by accumulator register i of lane half h (one 32-row tile).
+__host__ __device__ constexpr int acc_row(int i, int h) { return (i / 4) * 8 + h * 4 + i % 4; }
+// Contraction index of element j of lane half h in 16-wide block kb of a
+// layer fed by accumulator registers (layers 2 and 3).
+__host__ __device__ constexpr int chained_k(int kb, int h, int j) {
+  return (kb / 2) * 32 + (2 * (kb % 2) + j / 4) * 8 + h * 4 + j % 4;
+}
+static_assert(chained_k(1, 0, 0) == 16 && chained_k(0, 1, 4) == 12 && chained_k(3, 1, 7) == 63, "chain");
+
+// Field of feature k < 63 (k / 9) and its 3x3 offset, by multiply-shift.
+__device__ __forceinline__ int feat_field(int k) { return (k * 57) >> 9; }
+
+// tanh in FP32: odd Taylor polynomial through x^9 for |x| < 0.3 (truncation
+// below 2e-8 relative), else (1 - e^{-2|x|}) / (1 + e^{-2|x|}) with the
+// hardware exp2 and reciprocal (about 1e-7 relative).
+__device__ __forceinline__ float tanh_f(float x) {
+  const float a = fabsf(x);
+  const float x2 = x * x;
+  const float p = x * (1.0f + x2 * (-1.0f / 3.0f + x2 * (2.0f / 15.0f + x2 * (-17.0f / 315.0f + x2 * (62.0f / 2835.0f)))));
+  const float t = __builtin_amdgcn_exp2f(-2.885390081777927f * a);  // e^{-2a}
+  const float q = copysignf((1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t), x);
+  return a < 0.3f ? p : q;
+}
+
+__device__ __forceinline__ float bf16_round(float v) { return float(__bf16(v)); }
+
+struct MlpA {
+  bf16x8 a1[2][4], a2[2][4], a3[4];
+};
+
+__device__ __forceinline__ void load_mlp(const char* __restrict__ pk, int lane, MlpA& w) {
+  const bf16x8* p1 = reinterpret_cast<const bf16x8*>(pk + kPkA1);
+  const bf16x8* p2 = reinterpret_cast<const bf16x8*>(pk + kPkA2);
+  const bf16x8* p3 = reinterpret_cast<const bf16x8*>(pk + kPkA3);
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      w.a1[ot][kb] = p1[(ot * 4 + kb) * 64 + lane];
+      w.a2[ot][kb] = p2[(ot * 4 + kb) * 64 + lane];
+    }
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) w.a3[kb] = p3[kb * 64 + lane];
+}
+
+// Accumulator of one 32-row tile preset to the bias of its rows.
+__device__ __forceinline__ f32x16 bias_tile(const float* __restrict__ b, int ot, int h) {
+  f32x16 acc;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(b + ot * 32 + g * 8 + h * 4);
+    acc[g * 4 + 0] = v[0];
+    acc[g * 4 + 1] = v[1];
+    acc[g * 4 + 2] = v[2];
+    acc[g * 4 + 3] = v[3];
+  }
+  return acc;
+}
+
+// tanh of two accumulator tiles, rounded to bfloat16, as the four B operands
+// of the next layer.  The rounded values go to hout (as floats) when given.
+__device__ __forceinline__ void activate(const f32x16 acc[2], bf16x8 hb[4], float* hout) {
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const __bf16 v = __bf16(tanh_f(acc[kb / 2][(kb % 2) * 8 + j]));
+      hb[kb][j] = v;
+      if (hout) hout[kb * 8 + j] = float(v);
+    }
+}
+
+// The network on the 32 cells of a wave: zb = layer-1 B operands of this lane
+// (cell lane % 32, inputs kb*16 + (lane/32)*8 + j).  Returns y in lanes 0..31
+// (components 0..3).  h1, h2 (32 floats each, may be null) receive the
+// bfloat16 activations held by this lane, element kb*8 + j = hidden
+// chained_k(kb, lane/32, j).
+__device__ __forceinline__ f32x4 mlp_wave(const MlpA& w, const bf16x8 zb[4], const char* __restrict__ pk, int lane,
+                                          float* h1, float* h2) {
+  const int h = lane >> 5;
+  const float* b1 = reinterpret_cast<const float*>(pk + kPkB1);
+  const float* b2 = reinterpret_cast<const float*>(pk + kPkB2);
+  const float* b3 = reinterpret_cast<const float*>(pk + kPkB3);
+  f32x16 acc[2];
+  bf16x8 hb[4];
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot) {
+    acc[ot] = bias_tile(b1, ot, h);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a1[ot][kb], zb[kb], acc[ot], 0, 0, 0);
+  }
+  activate(acc, hb, h1);
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot) {
+    acc[ot] = bias_tile(b2, ot, h);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a2[ot][kb], hb[kb], acc[ot], 0, 0, 0);
+  }
+  activate(acc, hb, h2);
+  f32x16 out;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) out[i] = 0.0f;
+  if (h == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[i] = b3[i];
+  }
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[kb], hb[kb], out, 0, 0, 0);
+  f32x4 y;
+  y[0] = out[0];
+  y[1] = out[1];
+  y[2] = out[2];
+  y[3] = out[3];
+  return y;
+}
+
+// ---------------------------------------------------------------------------
+// Packing
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_mlp_pack(const float* __restrict__ p, const lbm_mlp_norm* __restrict__ norm, char* __restrict__ pk) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  __bf16* a = reinterpret_cast<__bf16*>(pk);
+  if (e < 4096) {  // A1: W1^T rows
+    const int ot = e / 2048, kb = (e / 512) % 4, l = (e / 8) % 64, j = e % 8;
+    const int hid = ot * 32 + l % 32, k = kb * 16 + (l / 32) * 8 + j;
+    a[kPkA1 / 2 + e] = __bf16(k < 63 ? p[LBM_MLP_OFF_W1 + k * 64 + hid] : 0.0f);
+  } else if (e < 8192) {  // A2: W2^T rows, chained contraction order
+    const int f = e - 4096;
+    const int ot = f / 2048, kb = (f / 512) % 4, l = (f / 8) % 64, j = f % 8;
+    const int out = ot * 32 + l % 32, k = chained_k(kb, l / 32, j);
+    a[kPkA2 / 2 + f] = __bf16(p[LBM_MLP_OFF_W2 + k * 64 + out]);
+  } else if (e < 10240) {  // A3: W3^T rows 0..3, rest zero
+    const int f = e - 8192;
+    const int kb = f / 512, l = (f / 8) % 64, j = f % 8;
+    const int o = l % 32, k = chained_k(kb, l / 32, j);
+    a[kPkA3 / 2 + f] = __bf16(o < 4 ? p[LBM_MLP_OFF_W3 + k * 4 + o] : 0.0f);
+  } else if (e < 10240 + 64) {
+    const int i = e - 10240;
+    reinterpret_cast<float*>(pk + kPkB1)[i] = p[LBM_MLP_OFF_B1 + i];
+    reinterpret_cast<float*>(pk + kPkB2)[i] = p[LBM_MLP_OFF_B2 + i];
+    reinterpret_cast<float*>(pk + kPkB3)[i] = i < 4 ? p[LBM_MLP_OFF_B3 + i] : 0.0f;
+  } else if (e < 10240 + 64 + 32) {
+    const int i = e - 10240 - 64;
+    reinterpret_cast<float*>(pk + kPkNorm)[i] = reinterpret_cast<const float*>(norm)[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward on feature rows (inference of given inputs; also the parity probe
+// of the matrix-core network)
+// ---------------------------------------------------------------------------
+
+// Layer-1 operands of this lane from feature row `row` of x (FP32): z =
+// (x - shift) * scale per field, pad 0, rounded to bfloat16.  Sets *ood when
+// any |z| exceeds the limit; zf (may be null) receives the rounded values.
+__device__ __forceinline__ void row_operands(const float* __restrict__ x, int64_t row, const lbm_mlp_norm* nm,
+                                             int h, bf16x8 zb[4], bool* ood, float* zf) {
+  bool o = false;
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    const f32x4* src = reinterpret_cast<const f32x4*>(x + row * 64 + kb * 16 + h * 8);
+    const f32x4 u = src[0], v = src[1];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = kb * 16 + h * 8 + j;
+      const float xv = j < 4 ? u[j] : v[j - 4];
+      float z = 0.0f;
+      if (k < 63) {
+        const int f = feat_field(k);
+        z = (xv - nm->shift[f]) * nm->scale[f];
+      }
+      o = o || fabsf(z) > kOodLimit;
+      zb[kb][j] = __bf16(z);
+      if (zf) zf[kb * 8 + j] = float(zb[kb][j]);
+    }
+  }
+  *ood = o;
+}
+
+__global__ void __launch_bounds__(256)
+k_mlp_forward(const char* __restrict__ pk, const float* __restrict__ x, int64_t n, float* __restrict__ y,
+              int32_t* __restrict__ ood_out) {
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  const lbm_mlp_norm* nm = reinterpret_cast<const lbm_mlp_norm*>(pk + kPkNorm);
+  MlpA w;
+  load_mlp(pk, lane, w);
+  for (int64_t g = wave; g * 32 < n; g += nwaves) {
+    const int64_t row = g * 32 + (lane & 31);
+    const int64_t rr = row < n ? row : n - 1;
+    bf16x8 zb[4];
+    bool o;
+    row_operands(x, rr, nm, h, zb, &o, nullptr);
+    const f32x4 v = mlp_wave(w, zb, pk, lane, nullptr, nullptr);
+    // every lane takes part in the exchange (a short-circuit would leave the
+    // flagged lane inactive and its partner would read nothing from it)
+    const int partner = __shfl_xor(int(o), 32, 64);
+    const bool oo = o || partner != 0;
+    if (h == 0 && row < n) {
+      *reinterpret_cast<f32x4*>(y + row * 4) = v;
+      if (ood_out) ood_out[row] = oo ? 1 : 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Correction of a simulation state.  Input: five FP32 planes rho, m_x, m_y,
+// B_x, B_y.  A workgroup stages a 64 x 16 tile with a two-cell halo in LDS,
+// forms u = m / rho, the central-difference vorticity and current on the
+// one-cell halo, normalises the seven fields, and evaluates the network for
+// its 1024 cells (each wave 8 groups of 32).  Output: four FP32 planes
+// tau_xx, tau_xy, tau_yy, eps = out_scale * y, 0 where a cell's inputs are
+// out of distribution.
+// ---------------------------------------------------------------------------
+constexpr int kCorrTX = 64, kCorrTY = 16;
+constexpr int kCorrLX = kCorrTX + 4, kCorrLY = kCorrTY + 4;
+
+__global__ void __launch_bounds__(256)
+k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float* __restrict__ corr, int nx, int ny) {
+  __shared__ float fld[7][kCorrLY][kCorrLX];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, h = lane >> 5;
+  const int x0 = blockIdx.x * kCorrTX, y0 = blockIdx.y * kCorrTY;
+  const int64_t n = (int64_t)nx * ny;
+  const lbm_mlp_norm* nm = reinterpret_cast<const lbm_mlp_norm*>(pk + kPkNorm);
+  // 1. primary fields on the tile and its two-cell halo
+  for (int e = tid; e < kCorrLX * kCorrLY; e += 256) {
+    const int ly = e / kCorrLX, lx = e - ly * kCorrLX;
+    int gx = (x0 + lx - 2) % nx, gy = (y0 + ly - 2) % ny;
+    if (gx < 0) gx += nx;
+    if (gy < 0) gy += ny;
+    const int64_t c = (int64_t)gy * nx + gx;
+    const float r = mom[c];
+    fld[0][ly][lx] = r;
+    fld[1][ly][lx] = mom[n + c] / r;
+    fld[2][ly][lx] = mom[2 * n + c] / r;
+    fld[3][ly][lx] = mom[3 * n + c];
+    fld[4][ly][lx] = mom[4 * n + c];
+  }
+  __syncthreads();
+  // 2. vorticity and current on the tile and its one-cell halo
+  for (int e = tid; e < (kCorrLX - 2) * (kCorrLY - 2); e += 256) {
+    const int ly = e / (kCorrLX - 2) + 1, lx = e % (kCorrLX - 2) + 1;
+    fld[5][ly][lx] = 0.5f * (fld[2][ly][lx + 1] - fld[2][ly][lx - 1]) - 0.5f * (fld[1][ly + 1][lx] - fld[1][ly - 1][lx]);
+    fld[6][ly][lx] = 0.5f * (fld[4][ly][lx + 1] - fld[4][ly][lx - 1]) - 0.5f * (fld[3][ly + 1][lx] - fld[3][ly - 1][lx]);
+  }
+  __syncthreads();
+  // 3. normalise the one-cell-halo region of every field
+  for (int e = tid; e < 7 * (kCorrLX - 2) * (kCorrLY - 2); e += 256) {
+    const int f = e / ((kCorrLX - 2) * (kCorrLY - 2));
+    const int r = e - f * (kCorrLX - 2) * (kCorrLY - 2);
+    const int ly = r / (kCorrLX - 2) + 1, lx = r % (kCorrLX - 2) + 1;
+    fld[f][ly][lx] = (fld[f][ly][lx] - nm->shift[f]) * nm->scale[f];
+  }
+  __syncthreads();
+  MlpA w;
+  load_mlp(pk, lane, w);
+  for (int g = wid; g < kCorrTX * kCorrTY / 32; g += 4) {
+    const int ty = g >> 1, tx = (g & 1) * 32 + (lane & 31);
+    bf16x8 zb[4];
+    bool o = false;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = kb * 16 + h * 8 + j;
+        float z = 0.0f;
+        if (k < 63) {
+          const int f = feat_field(k), d = k - 9 * f;
+          const int dy = (d * 11) >> 5, dx = d - 3 * dy;  // d / 3, d % 3
+          z = fld[f][ty + 1 + dy][tx + 1 + dx];
+        }
+        o = o || fabsf(z) > kOodLimit;
+        zb[kb][j] = __bf16(z);
+      }
+    const f32x4 v = mlp_wave(w, zb, pk, lane, nullptr, nullptr);
+    // every lane takes part in the exchange (a short-circuit would leave the
+    // flagged lane inactive and its partner would read nothing from it)
+    const int partner = __shfl_xor(int(o), 32, 64);
+    const bool oo = o || partner != 0;
+    const int gx = x0 + tx, gy = y0 + ty;
+    if (h == 0 && gx < nx && gy < ny) {
+      const int64_t c = (int64_t)gy * nx + gx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) corr[q * n + c] = oo ? 0.0f : v[q] * nm->out_scale[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Training: forward on the matrix cores, backward in FP32 on the vector ALU.
+// A workgroup of two waves takes chunks of 64 batch rows; activations and
+// deltas go through LDS; each thread owns a fixed set of gradient entries
+// and accumulates them over its workgroup's chunks in a fixed order.  Per-
+// workgroup partial gradients are summed in workgroup order by the Adam
+// kernel.
+// ---------------------------------------------------------------------------
+constexpr int kTrainChunk = 64;
+constexpr int kTrainBlocksMax = 1024;
+constexpr int kGradStride = 8704;  // floats per partial (>= LBM_MLP_PARAMS, 256-byte multiple)
+
+struct TrainLds {
+  float z[kTrainChunk][65], h1[kTrainChunk][65], h2[kTrainChunk][65];
+  float d2[kTrainChunk][65], d1[kTrainChunk][65];
+  float d3[kTrainChunk][4];
+};
+
+__global__ void __launch_bounds__(128)
+k_mlp_train(const char* __restrict__ pk, const float* __restrict__ p, const float* __restrict__ x,
+            const float* __restrict__ t, const int32_t* __restrict__ idx, int batch, float* __restrict__ partial,
+            double* __restrict__ loss_part) {
+  __shared__ TrainLds s;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, h = lane >> 5;
+  const int col = tid & 63, half = tid >> 6;  // owner indices of the backward
+  const lbm_mlp_norm* nm = reinterpret_cast<const lbm_mlp_norm*>(pk + kPkNorm);
+  MlpA w;
+  load_mlp(pk, lane, w);
+  // bfloat16 copies of the weights the backward multiplies by
+  float w2row[64], w3row[4];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) w2row[j] = bf16_round(p[LBM_MLP_OFF_W2 + col * 64 + j]);
+#pragma unroll
+  for (int o = 0; o < 4; ++o) w3row[o] = bf16_round(p[LBM_MLP_OFF_W3 + col * 4 + o]);
+  float g1[32], g2[32], g3[2];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) g1[k] = g2[k] = 0.0f;
+  g3[0] = g3[1] = 0.0f;
+  float gb1 = 0.0f, gb2 = 0.0f, gb3 = 0.0f;
+  double loss = 0.0;
+  const float inv = 2.0f / (float(batch) * 4.0f);
+  const int chunks = (batch + kTrainChunk - 1) / kTrainChunk;
+  for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
+    // forward: wave wid takes rows c*64 + wid*32 + (lane % 32)
+    {
+      const int sl = wid * 32 + (lane & 31);
+      const int b = c * kTrainChunk + sl;
+      const bool valid = b < batch;
+      const int64_t row = idx[valid ? b : batch - 1];
+      bf16x8 zb[4];
+      float zf[32], h1[32], h2[32];
+      bool o;
+      row_operands(x, row, nm, h, zb, &o, zf);
+      const f32x4 y = mlp_wave(w, zb, pk, lane, h1, h2);
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          s.z[sl][kb * 16 + h * 8 + j] = zf[kb * 8 + j];
+          s.h1[sl][chained_k(kb, h, j)] = h1[kb * 8 + j];
+          s.h2[sl][chained_k(kb, h, j)] = h2[kb * 8 + j];
+        }
+      if (h == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float r = y[q] - t[row * 4 + q] / nm->out_scale[q];
+          s.d3[sl][q] = valid ? inv * r : 0.0f;
+          if (valid) loss += double(r) * double(r);
+        }
+      }
+    }
+    __syncthreads();
+    // d2[s][j] = (W3 d3)_j (1 - h2^2): thread (col = j, half) takes 32 rows
+    for (int r = half * 32; r < half * 32 + 32; ++r) {
+      const float a = w3row[0] * s.d3[r][0] + w3row[1] * s.d3[r][1] + w3row[2] * s.d3[r][2] + w3row[3] * s.d3[r][3];
+      const float hv = s.h2[r][col];
+      s.d2[r][col] = a * (1.0f - hv * hv);
+    }
+    __syncthreads();
+    // d1[s][i] = (W2 d2)_i (1 - h1^2): thread (col = i, half)
+    for (int r = half * 32; r < half * 32 + 32; ++r) {
+      float a = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 64; ++j) a += w2row[j] * s.d2[r][j];
+      const float hv = s.h1[r][col];
+      s.d1[r][col] = a * (1.0f - hv * hv);
+    }
+    __syncthreads();
+    // gradients: g1[k][i] += z d1, g2[i][j] += h1 d2, g3[j][o] += h2 d3
+    for (int r = 0; r < kTrainChunk; ++r) {
+      const float d1v = s.d1[r][col], d2v = s.d2[r][col];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) {
+        g1[k] += s.z[r][half * 32 + k] * d1v;
+        g2[k] += s.h1[r][half * 32 + k] * d2v;
+      }
+      const float h2v = s.h2[r][col];
+      g3[0] += h2v * s.d3[r][half * 2];
+      g3[1] += h2v * s.d3[r][half * 2 + 1];
+      if (half == 0) {
+        gb1 += d1v;
+        gb2 += d2v;
+        if (col < 4) gb3 += s.d3[r][col];
+      }
+    }
+    __syncthreads();
+  }
+  float* out = partial + (int64_t)blockIdx.x * kGradStride;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    out[LBM_MLP_OFF_W1 + (half * 32 + k) * 64 + col] = g1[k];
+    out[LBM_MLP_OFF_W2 + (half * 32 + k) * 64 + col] = g2[k];
+  }
+  out[LBM_MLP_OFF_W3 + col * 4 + half * 2] = g3[0];
+  out[LBM_MLP_OFF_W3 + col * 4 + half * 2 + 1] = g3[1];
+  if (half == 0) {
+    out[LBM_MLP_OFF_B1 + col] = gb1;
+    out[LBM_MLP_OFF_B2 + col] = gb2;
+    if (col < 4) out[LBM_MLP_OFF_B3 + col] = gb3;
+  }
+  // loss: fixed-order sum over the 64 lanes that hold outputs
+  __shared__ double lred[128];
+  lred[tid] = loss;
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0;
+    for (int k = 0; k < 128; ++k) a += lred[k];
+    loss_part[blockIdx.x] = a;
+  }
+}
+
+// Sum of the partial gradients in workgroup order (and of the loss partials).
+__global__ void __launch_bounds__(256)
+k_mlp_reduce(const float* __restrict__ partial, int nparts, float* __restrict__ grad,
+             const double* __restrict__ loss_part, float* __restrict__ loss_out, float loss_norm) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < LBM_MLP_PARAMS) {
+    float g = 0.0f;
+    for (int b = 0; b < nparts; ++b) g += partial[(int64_t)b * kGradStride + i];
+    grad[i] = g;
+  }
+  if (i == 0 && loss_out) {
+    double a = 0.0;
+    for (int b = 0; b < nparts; ++b) a += loss_part[b];
+    *loss_out = float(a * double(loss_norm));
+  }
+}
+
+// Adam (Kingma & Ba 2015), bias corrections bc1 = 1 - beta1^t, bc2 = 1 - beta2^t.
+__global__ void __launch_bounds__(256)
+k_mlp_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ grad,
+           float lr, float bc1, float bc2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= LBM_MLP_PARAMS) return;
+  const float g = grad[i];
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float mi = b1 * m[i] + (1.0f - b1) * g;
+  const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Normalisation statistics: FP64 partial sums per workgroup, fixed-order
+// final pass.  Pass 1: sums of the seven centre features and of the squared
+// targets; pass 2: squared deviations from the means.
+// ---------------------------------------------------------------------------
+constexpr int kStatBlocks = 256;
+
+__device__ void block_sum11(double* acc, double* out) {
+  __shared__ double red[4][11];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 11; ++k) acc[k] += __shfl_down(acc[k], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 11; ++k) red[wid][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 11; ++k) out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256)
+k_stats_pass(const float* __restrict__ x, const float* __restrict__ t, int64_t n, const double* __restrict__ mean,
+             double* __restrict__ part) {
+  double acc[11];
+#pragma unroll
+  for (int k = 0; k < 11; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += stride) {
+#pragma unroll
+    for (int f = 0; f < 7; ++f) {
+      const double v = x[r * 64 + f * 9 + 4];
+      if (mean) {
+        const double d = v - mean[f];
+        acc[f] += d * d;
+      } else {
+        acc[f] += v;
+      }
+    }
+    if (!mean)
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        const double v = t[r * 4 + o];
+        acc[7 + o] += v * v;
+      }
+  }
+  block_sum11(acc, part + (int64_t)blockIdx.x * 11);
+}
+
+// mode 0: partial sums -> means (mean[0..6]) and target RMS; mode 1:
+// squared deviations -> norm.
+__global__ void __launch_bounds__(64)
+k_stats_final(const double* __restrict__ part, int nparts, int64_t n, double* __restrict__ mean, int mode,
+              lbm_mlp_norm* __restrict__ norm) {
+  if (threadIdx.x != 0) return;
+  double s[11];
+  for (int k = 0; k < 11; ++k) s[k] = 0.0;
+  for (int b = 0; b < nparts; ++b)
+    for (int k = 0; k < 11; ++k) s[k] += part[(int64_t)b * 11 + k];
+  const double dn = double(n);
+  if (mode == 0) {
+    for (int f = 0; f < 7; ++f) mean[f] = s[f] / dn;
+    for (int o = 0; o < 4; ++o) mean[7 + o] = sqrt(s[7 + o] / dn);
+    return;
+  }
+  lbm_mlp_norm nm;
+  for (int k = 0; k < 8; ++k) {
+    nm.shift[k] = 0.0f;
+    nm.scale[k] = 1.0f;
+  }
+  for (int f = 0; f < 7; ++f) {
+    const double sd = sqrt(s[f] / dn);
+    nm.shift[f] = float(mean[f]);
+    nm.scale[f] = sd > 0.0 ? float(1.0 / sd) : 1.0f;
+  }
+  for (int o = 0; o < 4; ++o) nm.out_scale[o] = mean[7 + o] > 0.0 ? float(mean[7 + o]) : 1.0f;
+  for (int k = 0; k < 12; ++k) nm.pad[k] = 0.0f;
+  *norm = nm;
+}
+
+// ---------------------------------------------------------------------------
+// Filtered DNS: Gaussian taps, x pass (12 products, subsampled columns), y
+// pass (subsampled rows).  FP64 throughout.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gauss_taps(double sigma2, int R, double* __restrict__ taps) {
+  __shared__ double wv[256];
+  const int r = threadIdx.x;
+  if (r <= 2 * R) {
+    const double d = double(r - R);
+    wv[r] = exp(-d * d / (2.0 * sigma2));
+  }
+  __syncthreads();
+  if (r == 0) {
+    double s = 0.0;
+    for (int k = 0; k <= 2 * R; ++k) s += wv[k];
+    wv[255] = s;
+  }
+  __syncthreads();
+  if (r <= 2 * R) taps[r] = wv[r] / wv[255];
+}
+
+__global__ void __launch_bounds__(64)
+k_filter_x(const double* __restrict__ mom, int nx, int ny, int factor, int R, const double* __restrict__ taps,
+           double* __restrict__ tmp) {
+  const int cx = nx / factor;
+  const int X = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y;
+  if (X >= cx) return;
+  const int64_t n = (int64_t)nx * ny;
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  for (int r = -R; r <= R; ++r) {
+    int xx = (X * factor + r) % nx;
+    if (xx < 0) xx += nx;
+    const int64_t c = (int64_t)y * nx + xx;
+    const double rho = mom[c], mx = mom[n + c], my = mom[2 * n + c], bx = mom[3 * n + c], by = mom[4 * n + c];
+    const double w = taps[r + R];
+    const double p[12] = {rho, mx, my, bx, by, mx * mx / rho, mx * my / rho, my * my / rho,
+                          bx * bx, bx * by, by * by, (mx * by - my * bx) / rho};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] += w * p[k];
+  }
+  const int64_t cn = (int64_t)cx * ny;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) tmp[k * cn + (int64_t)y * cx + X] = acc[k];
+}
+
+__global__ void __launch_bounds__(64)
+k_filter_y(const double* __restrict__ tmp, int nx, int ny, int factor, int R, const double* __restrict__ taps,
+           double* __restrict__ out) {
+  const int cx = nx / factor, cy = ny / factor;
+  const int X = blockIdx.x * 64 + threadIdx.x, Y = blockIdx.y, k = blockIdx.z;
+  if (X >= cx) return;
+  const int64_t cn = (int64_t)cx * ny;
+  double acc = 0.0;
+  for (int r = -R; r <= R; ++r) {
+    int yy = (Y * factor + r) % ny;
+    if (yy < 0) yy += ny;
+    acc += taps[r + R] * tmp[k * cn + (int64_t)yy * cx + X];
+  }
+  out[(int64_t)k * cx * cy + (int64_t)Y * cx + X] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Training samples on the coarse grid: inputs and exact-minus-analytic
+// targets of every cell (FP64 arithmetic, FP32 output).
+// ---------------------------------------------------------------------------
+template <int STENCIL>
+__global__ void __launch_bounds__(256)
+k_closure_samples(const double* __restrict__ c12, int nx, int ny, double k2, float* __restrict__ xo,
+                  float* __restrict__ to) {
+  const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const int64_t n = (int64_t)nx * ny;
+  auto at = [&](int k, int dx, int dy) {
+    int xx = (x + dx) % nx, yy = (y + dy) % ny;
+    if (xx < 0) xx += nx;
+    if (yy < 0) yy += ny;
+    return c12[k * n + (int64_t)yy * nx + xx];
+  };
+  auto field = [&](int f, int dx, int dy) -> double {
+    switch (f) {
+      case 0: return at(0, dx, dy);
+      case 1: return at(1, dx, dy) / at(0, dx, dy);
+      case 2: return at(2, dx, dy) / at(0, dx, dy);
+      case 3: return at(3, dx, dy);
+      default: return at(4, dx, dy);
+    }
+  };
+  const int64_t c = (int64_t)y * nx + x;
+  float* xr = xo + c * 64;
+  for (int f = 0; f < 7; ++f)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        double v;
+        if (f < 5) {
+          v = field(f, dx, dy);
+        } else {
+          const int a = f == 5 ? 2 : 4, b = f == 5 ? 1 : 3;  // w: (u_y, u_x); J_z: (B_y, B_x)
+          v = 0.5 * (field(a, dx + 1, dy) - field(a, dx - 1, dy)) - 0.5 * (field(b, dx, dy + 1) - field(b, dx, dy - 1));
+        }
+        xr[f * 9 + (dy + 1) * 3 + (dx + 1)] = float(v);
+      }
+  xr[63] = 0.0f;
+  // exact subgrid terms of the filtered products
+  const double rho = at(0, 0, 0), mx = at(1, 0, 0), my = at(2, 0, 0), bx = at(3, 0, 0), by = at(4, 0, 0);
+  const double rxx = at(5, 0, 0) - mx * mx / rho, rxy = at(6, 0, 0) - mx * my / rho, ryy = at(7, 0, 0) - my * my / rho;
+  const double qxx = at(8, 0, 0) - bx * bx, qxy = at(9, 0, 0) - bx * by, qyy = at(10, 0, 0) - by * by;
+  const double eps = at(11, 0, 0) - (mx * by - my * bx) / rho;
+  // analytic closure of the filtered fields
+  double g[4][2];
+  for (int k = 0; k < 4; ++k)
+    grad3x3<double, STENCIL>(at(1 + k, 1, 0), at(1 + k, -1, 0), at(1 + k, 0, 1), at(1 + k, 0, -1), at(1 + k, 1, 1),
+                             at(1 + k, -1, 1), at(1 + k, 1, -1), at(1 + k, -1, -1), g[k][0], g[k][1]);
+  const Closure<double> cl =
+      closure_terms(g[0][0], g[0][1], g[1][0], g[1][1], g[2][0], g[2][1], g[3][0], g[3][1], 1.0 / rho, k2);
+  const double a_xx = 0.5 * (cl.tau_s + cl.tau_d), a_yy = 0.5 * (cl.tau_s - cl.tau_d);
+  float* tr = to + c * 4;
+  tr[0] = float((rxx + 0.5 * (qyy - qxx)) - a_xx);
+  tr[1] = float((rxy - qxy) - cl.tau_xy);
+  tr[2] = float((ryy + 0.5 * (qxx - qyy)) - a_yy);
+  tr[3] = float(eps - cl.eps);
+}
+
+// ---------------------------------------------------------------------------
+// Spectra.  Two complex fields per state, z_u = u_x + i u_y and z_B = B_x + i
+// B_y: over a bin that contains -k with every k, sum |Z(k)|^2 equals
+// sum |A(k)|^2 + |B(k)|^2 of the real fields' transforms.  Row FFTs, then
+// column FFTs that bin |Z|^2 / n^4 per column (deterministic: one thread per
+// bin walks its k_y range in order), then a fixed-order sum over columns.
+// Radix-2 decimation in time in LDS (bit-reversed load), FP64 twiddles from
+// sincospi.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return __builtin_bitreverse32(v) >> (32 - bits); }
+
+// floor(sqrt(v)) and ceil(sqrt(v)) of a non-negative integer, exact.
+__device__ __forceinline__ int isqrt_floor(int64_t v) {
+  int64_t r = (int64_t)sqrt(double(v));
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return (int)r;
+}
+__device__ __forceinline__ int isqrt_ceil(int64_t v) {
+  const int r = isqrt_floor(v);
+  return (int64_t)r * r == v ? r : r + 1;
+}
+
+__device__ void fft_lds(double2* a, int n, int bits) {
+  for (int half = 1; half < n; half <<= 1) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < n / 2; j += blockDim.x) {
+      const int pos = j & (half - 1);
+      const int i0 = ((j - pos) << 1) + pos, i1 = i0 + half;
+      double s, c;
+      sincospi(-double(pos) / double(half), &s, &c);
+      const double2 u = a[i0], v = a[i1];
+      const double tr = c * v.x - s * v.y, ti = c * v.y + s * v.x;
+      a[i0] = make_double2(u.x + tr, u.y + ti);
+      a[i1] = make_double2(u.x - tr, u.y - ti);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256)
+k_fft_rows(const double* __restrict__ mom, int n, int bits, double2* __restrict__ work) {
+  extern __shared__ double2 a[];
+  const int y = blockIdx.x, pair = blockIdx.y;
+  const int64_t nn = (int64_t)n * n;
+  for (int x = threadIdx.x; x < n; x += blockDim.x) {
+    const int64_t c = (int64_t)y * n + x;
+    double re, im;
+    if (pair == 0) {
+      const double r = mom[c];
+      re = mom[nn + c] / r;
+      im = mom[2 * nn + c] / r;
+    } else {
+      re = mom[3 * nn + c];
+      im = mom[4 * nn + c];
+    }
+    a[bitrev(x, bits)] = make_double2(re, im);
+  }
+  fft_lds(a, n, bits);
+  for (int x = threadIdx.x; x < n; x += blockDim.x) work[pair * nn + (int64_t)y * n + x] = a[x];
+}
+
+__global__ void __launch_bounds__(256)
+k_fft_cols(const double2* __restrict__ work, int n, int bits, int nbins, double* __restrict__ part,
+           double* __restrict__ partx) {
+  extern __shared__ double2 a[];
+  const int kxi = blockIdx.x, pair = blockIdx.y;
+  const int64_t nn = (int64_t)n * n;
+  for (int y = threadIdx.x; y < n; y += blockDim.x) a[bitrev(y, bits)] = work[pair * nn + (int64_t)y * n + kxi];
+  fft_lds(a, n, bits);
+  const double inv = 1.0 / (double(n) * double(n));
+  const int kx = kxi < n / 2 ? kxi : kxi - n;
+  const int64_t kx2 = (int64_t)kx * kx;
+  double* out = part + ((int64_t)pair * n + kxi) * nbins;
+  // Bin b holds the k with floor(|k| + 1/2) = b, i.e. |k|^2 = 0 for b = 0 and
+  // b^2 - b + 1 <= |k|^2 <= b^2 + b for b >= 1 (exact in integers).  One
+  // thread per bin walks its |k_y| range upwards, +k_y before -k_y.
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    const int64_t lo = b == 0 ? 0 : (int64_t)b * b - b + 1 - kx2;
+    const int64_t hi = (int64_t)b * b + b - kx2;
+    double s = 0.0;
+    if (hi >= 0) {
+      const int a0 = lo <= 0 ? 0 : isqrt_ceil(lo);
+      int a1 = isqrt_floor(hi);
+      if (a1 > n / 2) a1 = n / 2;
+      for (int ay = a0; ay <= a1; ++ay) {
+        const int idx[2] = {ay == n / 2 ? n / 2 : ay, n - ay};
+        const int cnt = (ay == 0 || ay == n / 2) ? 1 : 2;
+        for (int u = 0; u < cnt; ++u) {
+          const double2 z = a[idx[u]];
+          s += (z.x * inv) * (z.x * inv) + (z.y * inv) * (z.y * inv);
+        }
+      }
+    }
+    out[b] = s;
+  }
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int yi = 0; yi < n; ++yi) {
+      const double2 z = a[yi];
+      s += (z.x * inv) * (z.x * inv) + (z.y * inv) * (z.y * inv);
+    }
+    partx[(int64_t)pair * n + kxi] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_spectra_final(const double* __restrict__ part, const double* __restrict__ partx, int n, int nbins,
+                double* __restrict__ ek, double* __restrict__ em, double* __restrict__ ekx) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b < nbins) {
+    double su = 0.0, sb = 0.0;
+    for (int k = 0; k < n; ++k) {
+      su += part[(int64_t)k * nbins + b];
+      sb += part[((int64_t)n + k) * nbins + b];
+    }
+    ek[b] = 0.5 * su;
+    em[b] = 0.5 * sb;
+  }
+  if (ekx && b <= n / 2) {
+    double s = partx[b];
+    if (b != 0 && b != n / 2) s += partx[n - b];
+    ekx[b] = 0.5 * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static int train_blocks(int batch) {
+  const int chunks = (batch + kTrainChunk - 1) / kTrainChunk;
+  return chunks < kTrainBlocksMax ? chunks : kTrainBlocksMax;
+}
+
+// Work of a training step: packed network, per-workgroup partial gradients,
+// loss partials, the reduced gradient.
+size_t mlp_train_work_bytes(int batch) {
+  const int blocks = train_blocks(batch);
+  return (size_t)LBM_MLP_PACKED_BYTES + (size_t)blocks * kGradStride * sizeof(float) +
+         ((size_t)blocks * sizeof(double) + 255) / 256 * 256 + (size_t)kGradStride * sizeof(float);
+}
+
+hipError_t launch_mlp_pack(const float* params, const lbm_mlp_norm* norm, void* packed, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((10240 + 64 + 32 + 255) / 256), dim3(256), 0, st, params, norm,
+                     static_cast<char*>(packed));
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const void* packed, const float* x, int64_t n, float* y, int32_t* ood, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int64_t groups = (n + 31) / 32;
+  int64_t blocks = (groups + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<const char*>(packed), x, n,
+                     y, ood);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_gradient(const float* params, const lbm_mlp_norm* norm, const float* x, const float* t,
+                               const int32_t* idx, int batch, void* work, float* grad, float* loss, hipStream_t st) {
+  char* w = static_cast<char*>(work);
+  const int blocks = train_blocks(batch);
+  float* partial = reinterpret_cast<float*>(w + LBM_MLP_PACKED_BYTES);
+  double* lpart = reinterpret_cast<double*>(w + LBM_MLP_PACKED_BYTES + (size_t)blocks * kGradStride * sizeof(float));
+  hipError_t e = launch_mlp_pack(params, norm, w, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(128), 0, st, w, params, x, t, idx, batch, partial, lpart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((LBM_MLP_PARAMS + 255) / 256), dim3(256), 0, st, partial, blocks, grad, lpart,
+                     loss, float(1.0 / (double(batch) * 4.0)));
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t step, double lr,
+                           hipStream_t st) {
+  const float bc1 = float(1.0 - pow(0.9, double(step)));
+  const float bc2 = float(1.0 - pow(0.999, double(step)));
+  hipLaunchKernelGGL(k_mlp_adam, dim3((LBM_MLP_PARAMS + 255) / 256), dim3(256), 0, st, params, m, v, grad, float(lr),
+                     bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_train(float* params, float* m, float* v, int64_t step, double lr, const lbm_mlp_norm* norm,
+                            const float* x, const float* t, const int32_t* idx, int batch, void* work,
+                            float* loss, hipStream_t st) {
+  const int blocks = train_blocks(batch);
+  float* grad = reinterpret_cast<float*>(static_cast<char*>(work) + LBM_MLP_PACKED_BYTES +
+                                         (size_t)blocks * kGradStride * sizeof(float) +
+                                         ((size_t)blocks * sizeof(double) + 255) / 256 * 256);
+  hipError_t e = launch_mlp_gradient(params, norm, x, t, idx, batch, work, grad, loss, st);
+  if (e != hipSuccess) return e;
+  return launch_mlp_adam(params, m, v, grad, step, lr, st);
+}
+
+size_t mlp_stats_work_bytes() { return (size_t)(kStatBlocks * 11 + 16) * sizeof(double); }
+
+hipError_t launch_mlp_stats(const float* x, const float* t, int64_t n, lbm_mlp_norm* norm, void* work,
+                            hipStream_t st) {
+  double* part = static_cast<double*>(work);
+  double* mean = part + kStatBlocks * 11;
+  int64_t want = (n + 255) / 256;
+  const int blocks = int(want < kStatBlocks ? want : kStatBlocks);
+  hipLaunchKernelGGL(k_stats_pass, dim3(blocks), dim3(256), 0, st, x, t, n, (const double*)nullptr, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, part, blocks, n, mean, 0, norm);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stats_pass, dim3(blocks), dim3(256), 0, st, x, t, n, (const double*)mean, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, part, blocks, n, mean, 1, norm);
+  return hipGetLastError();
+}
+
+int filter_radius(double delta) { return (int)ceil(5.0 * (delta / sqrt(12.0))); }
+
+size_t filter_work_bytes(int nx, int ny, int factor) {
+  return 256 * sizeof(double) + (size_t)12 * (size_t)(nx / factor) * (size_t)ny * sizeof(double);
+}
+
+hipError_t launch_filter(const double* mom, int nx, int ny, int factor, double delta, double* out, void* work,
+                         hipStream_t st) {
+  const int R = filter_radius(delta);
+  double* taps = static_cast<double*>(work);
+  double* tmp = taps + 256;
+  hipLaunchKernelGGL(k_gauss_taps, dim3(1), dim3(256), 0, st, delta * delta / 12.0, R, taps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int cx = nx / factor, cy = ny / factor;
+  hipLaunchKernelGGL(k_filter_x, dim3((cx + 63) / 64, ny), dim3(64), 0, st, mom, nx, ny, factor, R, taps, tmp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_filter_y, dim3((cx + 63) / 64, cy, 12), dim3(64), 0, st, tmp, nx, ny, factor, R, taps, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_closure_samples(const double* c12, int nx, int ny, double delta, int stencil, float* x, float* t,
+                                  hipStream_t st) {
+  const dim3 g((nx + 63) / 64, (ny + 3) / 4), b(64, 4);
+  const double k2 = delta * delta / 12.0;
+  if (stencil == LBM_STENCIL_ISO9)
+    hipLaunchKernelGGL(k_closure_samples<LBM_STENCIL_ISO9>, g, b, 0, st, c12, nx, ny, k2, x, t);
+  else
+    hipLaunchKernelGGL(k_closure_samples<LBM_STENCIL_CENTRAL5>, g, b, 0, st, c12, nx, ny, k2, x, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_correct(const float* mom5, const void* packed, float* corr, int nx, int ny, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_correct, dim3((nx + kCorrTX - 1) / kCorrTX, (ny + kCorrTY - 1) / kCorrTY), dim3(256), 0, st,
+                     mom5, static_cast<const char*>(packed), corr, nx, ny);
+  return hipGetLastError();
+}
+
+int spectra_bins(int n) { return (int)floor(sqrt(2.0) * double(n / 2) + 0.5) + 1; }
+
+size_t spectra_work_bytes(int n) {
+  const size_t nn = (size_t)n * n;
+  return 2 * nn * sizeof(double2) + (size_t)2 * n * spectra_bins(n) * sizeof(double) + (size_t)2 * n * sizeof(double);
+}
+
+hipError_t launch_spectra(const double* mom, int n, double* ek, double* em, double* ekx, void* work, hipStream_t st) {
+  int bits = 0;
+  while ((1 << bits) < n) ++bits;
+  const int nb = spectra_bins(n);
+  double2* cw = static_cast<double2*>(work);
+  double* part = reinterpret_cast<double*>(cw + (size_t)2 * n * n);
+  double* partx = part + (size_t)2 * n * nb;
+  const size_t lds = (size_t)n * sizeof(double2);
+  hipLaunchKernelGGL(k_fft_rows, dim3(n, 2), dim3(256), lds, st, mom, n, bits, cw);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fft_cols, dim3(n, 2), dim3(256), lds, st, cw, n, bits, nb, part, partx);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int fin = (nb > n / 2 + 1 ? nb : n / 2 + 1);
+  hipLaunchKernelGGL(k_spectra_final, dim3((fin + 255) / 256), dim3(256), 0, st, part, partx, n, nb, ek, em, ekx);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

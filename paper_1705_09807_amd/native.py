@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/lbmhd.h (liblbmhd.so).
+"""ctypes declarations of the C ABI in include/lbmhd.h and
+include/lbmhd_learned.h (liblbmhd.so).
 
 Loading fails loudly when the library has not been built: there is no
 fallback implementation.  torch is imported first so that the library binds
@@ -15,7 +16,7 @@ import re
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblbmhd.so")
-HEADER = os.path.join(os.path.dirname(PKG), "include", "lbmhd.h")
+HEADERS = [os.path.join(os.path.dirname(PKG), "include", h) for h in ("lbmhd.h", "lbmhd_learned.h")]
 
 LBM_OK = 0
 LBM_EINVAL = -1
@@ -31,6 +32,19 @@ LBM_STENCIL_ISO9 = 0
 LBM_STENCIL_CENTRAL5 = 1
 LBM_SCHED_FUSED = 0
 LBM_SCHED_AA = 1
+LBM_CLOSURE_ANALYTIC = 0
+LBM_CLOSURE_LEARNED = 1
+
+LBM_MLP_FEATURES = 64
+LBM_MLP_OUTPUTS = 4
+LBM_MLP_OFF_W1 = 0
+LBM_MLP_OFF_B1 = 4096
+LBM_MLP_OFF_W2 = 4160
+LBM_MLP_OFF_B2 = 8256
+LBM_MLP_OFF_W3 = 8320
+LBM_MLP_OFF_B3 = 8576
+LBM_MLP_PARAMS = 8580
+LBM_MLP_PACKED_BYTES = 21504
 
 
 class LbmParams(ctypes.Structure):
@@ -41,7 +55,7 @@ class LbmParams(ctypes.Structure):
         ("s7", ctypes.c_double), ("s8", ctypes.c_double),
         ("delta", ctypes.c_double), ("closure_scale", ctypes.c_double),
         ("grad_stencil", ctypes.c_int32), ("dtype", ctypes.c_int32),
-        ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("schedule", ctypes.c_int32), ("closure", ctypes.c_int32),
         ("rho0", ctypes.c_double),
         ("bref_x", ctypes.c_double), ("bref_y", ctypes.c_double),
     ]
@@ -68,7 +82,17 @@ class LbmDiag(ctypes.Structure):
     ]
 
 
+class LbmMlpNorm(ctypes.Structure):
+    _fields_ = [
+        ("shift", ctypes.c_float * 8), ("scale", ctypes.c_float * 8),
+        ("out_scale", ctypes.c_float * 4), ("pad", ctypes.c_float * 12),
+    ]
+
+
 _P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
 _SIGNATURES = {
     "lbm_state_bytes": (ctypes.c_size_t, [ctypes.POINTER(LbmParams)]),
     "lbm_work_bytes": (ctypes.c_size_t, [ctypes.POINTER(LbmParams)]),
@@ -83,6 +107,23 @@ _SIGNATURES = {
     "lbm_destroy": (ctypes.c_int, [_P]),
     "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lbm_last_error": (ctypes.c_char_p, []),
+    # lbmhd_learned.h
+    "lbm_mlp_pack": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lbm_mlp_forward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
+    "lbm_mlp_stats_work_bytes": (_SZ, [_I64]),
+    "lbm_mlp_feature_stats": (ctypes.c_int, [_P, _P, _I64, _P, _P, _SZ, _P]),
+    "lbm_mlp_train_work_bytes": (_SZ, [_I32]),
+    "lbm_mlp_gradient": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _SZ, _P, _P, _P]),
+    "lbm_mlp_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_double, _P]),
+    "lbm_mlp_train_step": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_double, _P, _P, _P, _P, _I32, _P, _SZ, _P, _P]),
+    "lbm_filter_work_bytes": (_SZ, [_I32, _I32, _I32, ctypes.c_double]),
+    "lbm_filter_subsample": (ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_double, _P, _P, _SZ, _P]),
+    "lbm_closure_samples": (ctypes.c_int, [_P, _I32, _I32, ctypes.c_double, _I32, _P, _P, _P]),
+    "lbm_set_closure_mlp": (ctypes.c_int, [_P, _P]),
+    "lbm_closure_correction": (ctypes.c_int, [_P, _P]),
+    "lbm_spectra_bins": (_I32, [_I32]),
+    "lbm_spectra_work_bytes": (_SZ, [_I32]),
+    "lbm_spectra": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _SZ, _P]),
 }
 
 _lib = None
@@ -95,11 +136,14 @@ class LbmError(RuntimeError):
 
 
 def header_functions() -> list[str]:
-    """Names of the functions declared in include/lbmhd.h."""
-    with open(HEADER) as fh:
-        text = fh.read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+    """Names of the functions declared in include/*.h."""
+    names = set()
+    for path in HEADERS:
+        with open(path) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def load():

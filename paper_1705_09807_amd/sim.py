@@ -13,16 +13,18 @@ from . import native as N
 _DTYPES = {"fp64": N.LBM_FP64, "fp32": N.LBM_FP32, "fp16": N.LBM_FP16, "bf16": N.LBM_BF16}
 _STENCILS = {"iso9": N.LBM_STENCIL_ISO9, "central5": N.LBM_STENCIL_CENTRAL5}
 _SCHEDULES = {"fused": N.LBM_SCHED_FUSED, "aa": N.LBM_SCHED_AA}
+_CLOSURES = {"analytic": N.LBM_CLOSURE_ANALYTIC, "learned": N.LBM_CLOSURE_LEARNED}
 
 
 def make_params(nx, ny, nu, eta, delta=0.0, closure_scale=1.0, s5=0.0, s6=0.0, s7=0.0, s8=0.0,
-                grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0, b_ref=(0.0, 0.0)) -> N.LbmParams:
+                grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0, b_ref=(0.0, 0.0),
+                closure="analytic") -> N.LbmParams:
     return N.LbmParams(
         nx=int(nx), ny=int(ny), nu=float(nu), eta=float(eta),
         s5=float(s5 or 0.0), s6=float(s6 or 0.0), s7=float(s7 or 0.0), s8=float(s8 or 0.0),
         delta=float(delta), closure_scale=float(closure_scale),
         grad_stencil=_STENCILS[grad_stencil], dtype=_DTYPES[dtype],
-        schedule=_SCHEDULES[schedule], reserved=0, rho0=float(rho0),
+        schedule=_SCHEDULES[schedule], closure=_CLOSURES[closure], rho0=float(rho0),
         bref_x=float(b_ref[0]), bref_y=float(b_ref[1]))
 
 
@@ -39,13 +41,13 @@ class Sim:
 
     def __init__(self, nx, ny, nu, eta, delta=0.0, closure_scale=1.0, s5=0.0, s6=0.0, s7=0.0, s8=0.0,
                  grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0, b_ref=(0.0, 0.0),
-                 device="cuda:0", stream=None):
+                 closure="analytic", device="cuda:0", stream=None):
         import torch
 
         lib = N.load()
         self._torch = torch
         self.params = make_params(nx, ny, nu, eta, delta, closure_scale, s5, s6, s7, s8,
-                                  grad_stencil, dtype, schedule, rho0, b_ref)
+                                  grad_stencil, dtype, schedule, rho0, b_ref, closure)
         self.nx, self.ny = int(nx), int(ny)
         self.device = torch.device(device)
         sb = lib.lbm_state_bytes(ctypes.byref(self.params))
@@ -109,6 +111,30 @@ class Sim:
         if rc != N.LBM_ENONFINITE or raise_nonfinite:
             N.check(rc, "lbm_diagnostics")
         return {name: getattr(d, name) for name, _ in N.LbmDiag._fields_}
+
+    def set_closure_mlp(self, packed):
+        """Install a packed network (a uint8 device tensor of LBM_MLP_PACKED_BYTES,
+        see learned.Mlp.packed) in a context created with closure="learned"."""
+        self._check_buf(packed, N.LBM_MLP_PACKED_BYTES)
+        N.check(self._lib.lbm_set_closure_mlp(self._ctx, ctypes.c_void_p(packed.data_ptr())), "lbm_set_closure_mlp")
+        self._stream_sync_keep = packed
+
+    def closure_correction(self, out=None):
+        """[4, ny, nx] float32 device tensor: the network's tau_xx, tau_xy, tau_yy,
+        eps corrections of the current state."""
+        torch = self._torch
+        if out is None:
+            out = torch.empty((4, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        if out.dtype != torch.float32 or tuple(out.shape) != (4, self.ny, self.nx) or not out.is_contiguous() \
+                or out.data_ptr() % 256:
+            raise ValueError("expected a contiguous aligned float32 tensor of shape (4, ny, nx)")
+        N.check(self._lib.lbm_closure_correction(self._ctx, ctypes.c_void_p(out.data_ptr())), "lbm_closure_correction")
+        return out
+
+    def _check_buf(self, t, nbytes):
+        if t.device != self.device or not t.is_contiguous() or t.numel() * t.element_size() < nbytes \
+                or t.data_ptr() % 256:
+            raise ValueError(f"expected a contiguous aligned device buffer of >= {nbytes} bytes on {self.device}")
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

@@ -1,5 +1,5 @@
 """Host-only checks of the C ABI: the library loads, exports every function
-include/lbmhd.h declares, validates parameters and enforces call order.
+include/*.h declares, validates parameters and enforces call order.
 Nothing here enqueues device work, so it runs without a GPU."""
 
 import ctypes
@@ -21,7 +21,7 @@ def lib():
 
 def _params(**kw):
     base = dict(nx=64, ny=48, nu=1e-3, eta=2e-3, s5=0.0, s6=0.0, s7=0.0, s8=0.0, delta=2.0,
-                closure_scale=1.0, grad_stencil=0, dtype=0, schedule=0, reserved=0, rho0=1.0,
+                closure_scale=1.0, grad_stencil=0, dtype=0, schedule=0, closure=0, rho0=1.0,
                 bref_x=0.01, bref_y=0.0)
     base.update(kw)
     return N.LbmParams(**base)
@@ -59,7 +59,7 @@ def test_buffer_sizes(lib):
 @pytest.mark.parametrize("field,value", [
     ("nx", 3), ("ny", 0), ("nx", 40000), ("nu", 0.0), ("nu", -1e-3), ("eta", float("nan")),
     ("s5", 2.0), ("s8", float("inf")), ("delta", -1.0), ("closure_scale", float("nan")),
-    ("grad_stencil", 2), ("dtype", 7), ("schedule", 3), ("reserved", 1), ("rho0", 0.0),
+    ("grad_stencil", 2), ("dtype", 7), ("schedule", 3), ("closure", 2), ("closure", -1), ("rho0", 0.0),
     ("bref_x", float("nan")), ("bref_y", float("inf")),
 ])
 def test_invalid_params_rejected(lib, field, value):
@@ -108,3 +108,70 @@ def test_strerror(lib):
     for code in (N.LBM_OK, N.LBM_EINVAL, N.LBM_ESTATE, N.LBM_EHIP, N.LBM_ENONFINITE):
         assert len(lib.lbm_strerror(code)) > 0
     assert lib.lbm_strerror(12345) == b"unknown error"
+
+
+def test_learned_closure_params_and_call_order(lib):
+    p = _params(closure=N.LBM_CLOSURE_LEARNED)
+    w_learned = lib.lbm_work_bytes(ctypes.byref(p))
+    p0 = _params()
+    n = 64 * 48
+    # the learned closure adds 5 + 4 FP32 planes and the packed network
+    assert w_learned >= lib.lbm_work_bytes(ctypes.byref(p0)) + 9 * n * 4 + N.LBM_MLP_PACKED_BYTES
+    # only with the fused schedule
+    p_aa = _params(closure=N.LBM_CLOSURE_LEARNED, schedule=N.LBM_SCHED_AA)
+    assert lib.lbm_work_bytes(ctypes.byref(p_aa)) == 0
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(1 << 20),
+                          ctypes.c_void_p(1 << 24), None) == N.LBM_OK
+    try:
+        assert lib.lbm_set_closure_mlp(ctx, None) == N.LBM_EINVAL
+        assert lib.lbm_closure_correction(ctx, ctypes.c_void_p(1 << 22)) == N.LBM_ESTATE  # no state yet
+    finally:
+        lib.lbm_destroy(ctx)
+    assert lib.lbm_create(ctypes.byref(ctx), ctypes.byref(p0), ctypes.c_void_p(1 << 20),
+                          ctypes.c_void_p(1 << 24), None) == N.LBM_OK
+    try:
+        # an analytic-closure context takes no network
+        assert lib.lbm_set_closure_mlp(ctx, ctypes.c_void_p(1 << 22)) == N.LBM_ESTATE
+    finally:
+        lib.lbm_destroy(ctx)
+
+
+def test_learned_sizes_and_argument_checks(lib):
+    from oracle import spectra as S
+    for n in (8, 64, 1024, 4096):
+        assert lib.lbm_spectra_bins(n) == S.nbins(n)
+        assert lib.lbm_spectra_work_bytes(n) > 2 * n * n * 16
+    for bad in (4, 1000, 8192):
+        assert lib.lbm_spectra_bins(bad) == 0 and lib.lbm_spectra_work_bytes(bad) == 0
+    assert lib.lbm_mlp_train_work_bytes(0) == 0 and lib.lbm_mlp_train_work_bytes((1 << 20) + 1) == 0
+    assert lib.lbm_mlp_train_work_bytes(4096) >= N.LBM_MLP_PACKED_BYTES + N.LBM_MLP_PARAMS * 4
+    assert lib.lbm_mlp_stats_work_bytes(1) == 0 and lib.lbm_mlp_stats_work_bytes(100) > 0
+    # filter: factor must divide, radius bounded
+    assert lib.lbm_filter_work_bytes(4096, 4096, 4, 16.0) == 256 * 8 + 12 * 1024 * 4096 * 8
+    assert lib.lbm_filter_work_bytes(4096, 4096, 3, 16.0) == 0
+    assert lib.lbm_filter_work_bytes(100, 100, 8, 4.0) == 0
+    assert lib.lbm_filter_work_bytes(64, 64, 4, 200.0) == 0
+    assert lib.lbm_filter_work_bytes(64, 64, 4, 0.0) == 0
+    fake = ctypes.c_void_p(1 << 22)
+    assert lib.lbm_filter_subsample(None, 64, 64, 4, 4.0, fake, fake, 1 << 20, None) == N.LBM_EINVAL
+    assert lib.lbm_filter_subsample(fake, 64, 64, 4, 4.0, fake, fake, 16, None) == N.LBM_EINVAL
+    assert lib.lbm_closure_samples(fake, 64, 64, 4.0, 2, fake, fake, None) == N.LBM_EINVAL
+    assert lib.lbm_mlp_forward(fake, None, 10, fake, None, None) == N.LBM_EINVAL
+    assert lib.lbm_mlp_forward(fake, fake, -1, fake, None, None) == N.LBM_EINVAL
+    assert lib.lbm_mlp_forward(None, None, 0, None, None, None) == N.LBM_OK   # nothing to do
+    assert lib.lbm_mlp_pack(fake, None, fake, None) == N.LBM_EINVAL
+    assert lib.lbm_mlp_train_step(fake, fake, fake, 0, 1e-3, fake, fake, fake, fake, 64, fake, 1 << 20,
+                                  None, None) == N.LBM_EINVAL
+    assert lib.lbm_mlp_train_step(fake, fake, fake, 1, -1.0, fake, fake, fake, fake, 64, fake, 1 << 20,
+                                  None, None) == N.LBM_EINVAL
+    assert lib.lbm_mlp_train_step(fake, fake, fake, 1, 1e-3, fake, fake, fake, fake, 64, fake, 16,
+                                  None, None) == N.LBM_EINVAL
+    assert lib.lbm_mlp_adam(fake, fake, fake, fake, 0, 1e-3, None) == N.LBM_EINVAL
+    assert lib.lbm_mlp_feature_stats(fake, fake, 1, fake, fake, 1 << 20, None) == N.LBM_EINVAL
+    assert lib.lbm_spectra(fake, 1000, fake, fake, None, fake, 1 << 30, None) == N.LBM_EINVAL
+    assert lib.lbm_spectra(fake, 64, fake, fake, None, fake, 16, None) == N.LBM_EINVAL
+
+
+def test_norm_struct_layout():
+    assert ctypes.sizeof(N.LbmMlpNorm) == 128

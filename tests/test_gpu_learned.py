@@ -1,0 +1,419 @@
+"""GPU parity of the learned closure, the filtered-DNS pipeline and the
+spectra against the FP64 oracle (oracle/learned.py, oracle/spectra.py).
+
+Tolerances.  FP64 paths (filter, spectra, the collision with a given
+correction) are held to round-off.  The network runs in bfloat16 with FP32
+accumulation on both sides' definitions, but the oracle accumulates in FP64
+and uses the exact tanh: a pre-activation that lands within ~1e-7 of a
+bfloat16 rounding boundary can round the other way, changing that
+activation by one bfloat16 step (2^-8 relative) and the output by at most
+about |w| 2^-8.  The tests bound the worst row by a few such steps and
+require the bulk of rows to agree to FP32 accumulation noise; measured
+errors are printed.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import learned as L
+from oracle import lbmhd_oracle as O
+from oracle import spectra as S
+from seeded_inputs import perturbed, offset_noise
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_09807_amd import learned as G
+    return G
+
+
+def _params(seed):
+    """Oracle parameter dict with nonzero biases, all values FP32."""
+    p = L.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.uniform(-0.2, 0.2, p[k].shape).astype(np.float32).astype(np.float64)
+    return p
+
+
+def _flat(p):
+    return np.concatenate([p["w1"].ravel(), p["b1"], p["w2"].ravel(), p["b2"], p["w3"].ravel(),
+                           p["b3"]]).astype(np.float32)
+
+
+def _unflat(v):
+    v = np.asarray(v, dtype=np.float64)
+    return {"w1": v[0:4096].reshape(64, 64), "b1": v[4096:4160], "w2": v[4160:8256].reshape(64, 64),
+            "b2": v[8256:8320], "w3": v[8320:8576].reshape(64, 4), "b3": v[8576:8580]}
+
+
+def _norm(seed):
+    rng = np.random.default_rng(seed)
+    shift = rng.normal(0, 0.1, 7).astype(np.float32)
+    scale = rng.uniform(0.5, 2.0, 7).astype(np.float32)
+    out_scale = rng.uniform(1e-5, 1e-4, 4).astype(np.float32)
+    s64 = np.zeros(64)
+    c64 = np.ones(64)
+    for f in range(7):
+        s64[9 * f: 9 * f + 9] = shift[f]
+        c64[9 * f: 9 * f + 9] = scale[f]
+    return shift, scale, out_scale, s64, c64
+
+
+def _features(n, seed, ood_rows=()):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0, 0.8, (n, 64)).astype(np.float32)
+    X[:, 63] = 0
+    for r in ood_rows:
+        X[r, rng.integers(0, 63)] = 40.0
+    return X
+
+
+def _mlp(G, p, shift, scale, out_scale):
+    m = G.Mlp(_flat(p))
+    m.set_norm(shift, scale, out_scale)
+    return m
+
+
+def _compare_rows(got, want, label):
+    d = np.abs(got - want).max(axis=1)
+    scale = np.abs(want).max()
+    print(f"{label}: max {d.max():.2e}, 99th pct {np.percentile(d, 99):.2e}, median {np.median(d):.2e}, "
+          f"|y| max {scale:.2e}", flush=True)
+    assert np.median(d) <= 2e-5 * max(scale, 1.0)
+    assert np.percentile(d, 95) <= 1e-4 * max(scale, 1.0)
+    assert d.max() <= 2e-2 * max(scale, 1.0)
+
+
+# ---------------------------------------------------------------------------
+# network
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("n", [1, 31, 1000, 70001])
+def test_forward_matches_oracle(n):
+    G = _gpu()
+    p = _params(1)
+    shift, scale, out_scale, s64, c64 = _norm(2)
+    ood_rows = [r for r in (0, n // 2, n - 1) if r < n] if n > 1 else []
+    X = _features(n, 3, ood_rows)
+    m = _mlp(G, p, shift, scale, out_scale)
+    y, ood = m.forward(torch.from_numpy(X).cuda())
+    y = y.cpu().numpy().astype(np.float64)
+    ood = ood.cpu().numpy()
+    yo, _ = L.forward(p, X.astype(np.float64), s64, c64)
+    oo = (np.abs(L.normalise(X, s64, c64)) > 6.0).any(axis=1)
+    assert np.array_equal(ood.astype(bool), oo)
+    if n > 1:
+        assert oo[ood_rows].all()          # planted rows (a few random rows may exceed 6 too)
+    _compare_rows(y, yo, f"forward n={n}")
+
+
+def test_feature_stats_match_oracle():
+    G = _gpu()
+    rng = np.random.default_rng(5)
+    n = 5003
+    X = (rng.normal(0, 1, (n, 64)) * rng.uniform(1e-3, 1, 64) + rng.normal(0, 1, 64)).astype(np.float32)
+    X[:, 5 * 9 + 4] = 0.125          # a constant field: scale 1
+    X[:, 63] = 0
+    T = (rng.normal(0, 1, (n, 4)) * [1e-5, 2e-5, 3e-6, 1e-6]).astype(np.float32)
+    m = G.Mlp(_flat(_params(1)))
+    m.fit_norm(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    nm = m.norm.cpu().numpy()
+    shift, scale, out_scale = L.feature_stats(X.astype(np.float64), T.astype(np.float64))
+    for f in range(7):
+        assert abs(nm[f] - shift[9 * f]) <= 2.4e-7 * abs(shift[9 * f]) + 1e-30, f
+        assert abs(nm[8 + f] - scale[9 * f]) <= 2.4e-7 * scale[9 * f], f
+    assert nm[8 + 5] == 1.0
+    assert np.all(np.abs(nm[16:20] - out_scale) <= 2.4e-7 * out_scale)
+
+
+@pytest.mark.parametrize("batch", [200, 5000])
+def test_gradient_matches_oracle(batch):
+    G = _gpu()
+    p = _params(7)
+    shift, scale, out_scale, s64, c64 = _norm(8)
+    n = 6000
+    X = _features(n, 9)
+    rng = np.random.default_rng(10)
+    T = (rng.normal(0, 1, (n, 4)) * out_scale).astype(np.float32)
+    idx = rng.permutation(n)[:batch].astype(np.int32)
+    m = _mlp(G, p, shift, scale, out_scale)
+    grad, loss = m.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), torch.from_numpy(idx).cuda())
+    g = _unflat(grad.cpu().numpy())
+    Tn = (T[idx] / out_scale).astype(np.float64)          # FP32 division, as the kernel
+    lo, go = L.loss_and_grads(p, X[idx].astype(np.float64), Tn, s64, c64)
+    print(f"batch {batch}: loss gpu {loss.item():.8e} oracle {lo:.8e}", flush=True)
+    assert abs(loss.item() - lo) <= 1e-5 * lo
+    for k in go:
+        err = np.linalg.norm(g[k] - go[k]) / np.linalg.norm(go[k])
+        print(f"  grad {k}: relative L2 error {err:.2e}", flush=True)
+        assert err <= 1e-3, k
+    assert np.all(g["w1"][63] == 0)          # the pad input carries no gradient
+
+
+def test_adam_and_train_step_match():
+    G = _gpu()
+    p = _params(11)
+    shift, scale, out_scale, s64, c64 = _norm(12)
+    n = 1000
+    X = _features(n, 13)
+    rng = np.random.default_rng(14)
+    T = (rng.normal(0, 1, (n, 4)) * out_scale).astype(np.float32)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    a = _mlp(G, p, shift, scale, out_scale)
+    b = _mlp(G, p, shift, scale, out_scale)
+    po = {k: v.copy() for k, v in p.items()}
+    mo = {k: np.zeros_like(v) for k, v in p.items()}
+    vo = {k: np.zeros_like(v) for k, v in p.items()}
+    for t in range(1, 4):
+        idx = torch.from_numpy(rng.permutation(n)[:256].astype(np.int32)).cuda()
+        grad, _ = a.gradient(Xd, Td, idx)
+        go = _unflat(grad.cpu().numpy())
+        a.adam(grad, 1e-3)
+        b.train_step(Xd, Td, idx, 1e-3)
+        po, mo, vo = L.adam_step(po, go, mo, vo, t, 1e-3)
+        # the composed entry point is the two halves, bit for bit
+        assert torch.equal(a.params, b.params) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
+        pa = _unflat(a.params.cpu().numpy())
+        for k in po:
+            err = np.abs(pa[k] - po[k]).max()
+            assert err <= 1e-6 * max(1.0, np.abs(po[k]).max()), (t, k, err)
+
+
+def test_training_reduces_loss():
+    """A few hundred steps fit a smooth function of the inputs (end-to-end
+    check of forward, backward and optimiser on the GPU)."""
+    G = _gpu()
+    rng = np.random.default_rng(15)
+    n = 8192
+    X = _features(n, 16)
+    w = rng.normal(0, 0.3, (63, 4))
+    T = np.tanh(X[:, :63].astype(np.float64) @ w).astype(np.float32) * 1e-4
+    m = G.Mlp(G.glorot_params(17))
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    m.fit_norm(Xd, Td)
+    gen = torch.Generator(device="cuda").manual_seed(18)
+    first = last = None
+    for step in range(400):
+        idx = torch.randperm(n, device="cuda", generator=gen)[:1024].to(torch.int32)
+        loss = m.train_step(Xd, Td, idx, 3e-3)
+        if step == 0:
+            first = loss.item()
+    last = m.train_step(Xd, Td, torch.arange(n, device="cuda", dtype=torch.int32), 1e-9).item()
+    print(f"loss {first:.4e} -> {last:.4e}", flush=True)
+    assert last < 0.1 * first
+
+
+# ---------------------------------------------------------------------------
+# filtered DNS pipeline
+# ---------------------------------------------------------------------------
+
+
+def _smooth_state(nx, ny, seed):
+    """A near-equilibrium state with smooth, large-scale momentum and field."""
+    y, x = np.mgrid[0:ny, 0:nx]
+    rng = np.random.default_rng(seed)
+    def mode():
+        kx, ky = rng.integers(1, 4, 2)
+        return np.sin(2 * np.pi * (kx * x / nx + ky * y / ny) + rng.uniform(0, 2 * np.pi))
+    rho = 1.0 + 0.01 * mode()
+    ux, uy = 0.04 * mode(), 0.03 * mode()
+    bx, by = 0.01 + 0.02 * mode(), 0.015 * mode()
+    f = O.f_equilibrium(rho, rho * ux, rho * uy, bx, by)
+    g = O.g_equilibrium(rho, rho * ux, rho * uy, bx, by)
+    f = f + offset_noise(np.zeros(9), (9, ny, nx), seed + 1, 1e-5)
+    return f, g
+
+
+def _sim_state(nx, ny, f, g, **kw):
+    from paper_1705_09807_amd import Sim
+    s = Sim(nx=nx, ny=ny, nu=0.02, eta=0.03, **kw)
+    s.set_state(torch.from_numpy(np.concatenate([f, g[:, 0], g[:, 1]], 0)))
+    return s
+
+
+@pytest.mark.parametrize("nx,ny,factor,delta", [(96, 80, 4, 8.0), (64, 48, 1, 4.0), (128, 128, 4, 16.0),
+                                                (40, 24, 8, 3.0)])
+def test_filter_subsample_matches_oracle(nx, ny, factor, delta):
+    G = _gpu()
+    f, g = _smooth_state(nx, ny, 21)
+    s = _sim_state(nx, ny, f, g)
+    mom = s.moments()
+    out = G.filter_subsample(mom, factor, delta).cpu().numpy()
+    rho, mx, my, bx, by = mom.cpu().numpy()
+    want = L.filtered_fields(rho, mx, my, bx, by, factor, delta)
+    for k in range(12):
+        err = np.abs(out[k] - want[k]).max() / np.abs(want[k]).max()
+        assert err <= 1e-13, (k, err)
+
+
+@pytest.mark.parametrize("stencil", ["iso9", "central5"])
+def test_closure_samples_match_oracle(stencil):
+    G = _gpu()
+    nx, ny, factor, delta = 128, 96, 4, 16.0
+    f, g = _smooth_state(nx, ny, 31)
+    s = _sim_state(nx, ny, f, g)
+    c12 = G.filter_subsample(s.moments(), factor, delta)
+    X, T = G.closure_samples(c12, delta / factor, stencil)
+    X, T = X.cpu().numpy(), T.cpu().numpy()
+    c = c12.cpu().numpy()
+    Xo = L.closure_features(c[0], c[1], c[2], c[3], c[4])
+    To = (L.exact_subgrid(c) - L.analytic_subgrid(c[0], c[1], c[2], c[3], c[4], delta / factor, stencil))
+    To = To.reshape(4, -1).T
+    # FP64 on both sides, stored FP32: within one FP32 rounding (plus FP64 noise)
+    assert np.all(np.abs(X - Xo) <= 1.2e-7 * np.abs(Xo) + 1e-12)
+    err = np.abs(T - To).max(axis=0) / np.abs(To).max(axis=0)
+    print(f"targets relative error per component {err}", flush=True)
+    assert np.all(err <= 1e-6)
+
+
+@pytest.mark.parametrize("n", [8, 64, 256])
+def test_spectra_match_oracle(n):
+    G = _gpu()
+    f, g = _smooth_state(n, n, 41 + n)
+    f = f + offset_noise(np.zeros(9), (9, n, n), 7, 1e-3)     # energy in every bin
+    s = _sim_state(n, n, f, g)
+    mom = s.moments()
+    ek, em, ekx = [a.cpu().numpy() for a in G.spectra(mom)]
+    rho, mx, my, bx, by = mom.cpu().numpy()
+    EK, EM = S.energy_spectra(rho, mx, my, bx, by)
+    EX = S.x_spectrum(mx / rho, my / rho)
+    assert np.abs(ek - EK).max() <= 1e-13 * EK.sum()
+    assert np.abs(em - EM).max() <= 1e-13 * EM.sum()
+    assert np.abs(ekx - EX).max() <= 1e-13 * EX.sum()
+
+
+# ---------------------------------------------------------------------------
+# the learned closure inside the timestep
+# ---------------------------------------------------------------------------
+
+
+def _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale, dtype="fp64", delta=2.0):
+    s = _sim_state(nx, ny, f, g, delta=delta, closure="learned", dtype=dtype, s5=1.3, s6=1.5, s7=1.7, s8=1.1,
+                   b_ref=(0.01, 0.0))
+    m = _mlp(G, p, shift, scale, out_scale)
+    s.set_closure_mlp(m.pack())
+    torch.cuda.synchronize()
+    return s
+
+
+def _state_norm(f, g):
+    rho, mx, my, bx, by = O.Oracle._moments(f, g)
+    X = L.closure_features(rho, mx, my, bx, by)
+    shift, scale, _ = L.feature_stats(X, np.ones((X.shape[0], 4)))
+    out_scale = np.array([3e-5, 2e-5, 3e-5, 1e-5], dtype=np.float32)
+    return shift[::9][:7].astype(np.float32), scale[::9][:7].astype(np.float32), out_scale, shift, scale
+
+
+def test_step_requires_a_network():
+    G = _gpu()
+    from paper_1705_09807_amd.native import LbmError
+    f, g = _smooth_state(32, 24, 51)
+    s = _sim_state(32, 24, f, g, delta=2.0, closure="learned")
+    with pytest.raises(LbmError):
+        s.step(1)
+
+
+@pytest.mark.parametrize("ood", [False, True])
+@pytest.mark.parametrize("nx,ny", [(96, 64), (70, 37)])
+def test_correction_of_state_matches_oracle(nx, ny, ood):
+    G = _gpu()
+    f, g = _smooth_state(nx, ny, 61)
+    p = _params(62)
+    shift, scale, out_scale, s64, c64 = _state_norm(f, g)
+    if ood:
+        # a narrow density scale: cells with |rho - mean| above ~60% of the
+        # largest deviation leave the training range and keep the analytic closure
+        rho = f.sum(axis=0)
+        scale[0] = np.float32(6.0 / (0.6 * np.abs(rho - shift[0]).max()))
+        c64[:9] = scale[0]
+    s = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale)
+    corr = s.closure_correction().cpu().numpy().astype(np.float64)
+    st = s.get_state().cpu().numpy()
+    fo, go = st[:9], np.stack([st[9:14], st[14:19]], axis=1)
+    rho, mx, my, bx, by = O.Oracle._moments(fo, go)
+    want = L.learned_correction(p, s64, c64, out_scale.astype(np.float64))(rho, mx, my, bx, by)
+    zmax = np.abs(L.normalise(L.closure_features(rho, mx, my, bx, by), s64, c64)).max(axis=1)
+    oo = zmax > 6.0
+    decided = np.abs(zmax - 6.0) > 1e-4          # both sides decide these cells the same way
+    got_ood = (corr == 0).all(axis=0).ravel()
+    assert np.array_equal(got_ood[decided], oo[decided])
+    if ood:
+        assert 0.05 < oo.mean() < 0.95
+    else:
+        assert not oo.any()
+    rows = lambda a: (a / out_scale[:, None, None]).reshape(4, -1).T[decided]
+    _compare_rows(rows(corr), rows(want), f"correction {nx}x{ny} ood={ood} ({oo.mean():.0%} out of range)")
+
+
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("nx,ny", [(64, 48), (67, 33)])
+def test_learned_step_matches_oracle_given_the_correction(dtype, tol, nx, ny):
+    """One learned-closure step from a given state equals the oracle step
+    whose closure_correction returns the correction the GPU used."""
+    G = _gpu()
+    f, g = _smooth_state(nx, ny, 71)
+    p = _params(72)
+    shift, scale, out_scale, _, _ = _state_norm(f, g)
+    s = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale, dtype=dtype)
+    st0 = s.get_state().cpu().numpy()
+    for t0 in (0, 1):
+        if t0 == 1:
+            s.set_state(torch.from_numpy(st0), 1)
+        corr = s.closure_correction().cpu().numpy().astype(np.float64)
+        assert np.abs(corr).max() > 0
+        s.step(1)
+        got = s.get_state().cpu().numpy()
+        o = O.Oracle(nx, ny, 0.02, 0.03, delta=2.0, s5=1.3, s6=1.5, s7=1.7, s8=1.1,
+                     closure_correction=lambda *a: corr)
+        o.set_state(st0[:9], np.stack([st0[9:14], st0[14:19]], axis=1))
+        o.step(1)
+        fo, go = o.state()[:2]
+        want = np.concatenate([fo, go[:, 0], go[:, 1]], 0)
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        # and the correction mattered at this tolerance
+        o2 = O.Oracle(nx, ny, 0.02, 0.03, delta=2.0, s5=1.3, s6=1.5, s7=1.7, s8=1.1)
+        o2.set_state(st0[:9], np.stack([st0[9:14], st0[14:19]], axis=1))
+        o2.step(1)
+        f2, g2 = o2.state()[:2]
+        effect = np.linalg.norm(np.concatenate([f2, g2[:, 0], g2[:, 1]], 0) - want) / np.linalg.norm(want)
+        print(f"{dtype} {nx}x{ny} t0={t0}: relative L2 {err:.2e} (correction's effect {effect:.2e})", flush=True)
+        assert err <= tol
+        if dtype == "fp64":
+            assert effect > 1e3 * tol
+        s.set_state(torch.from_numpy(st0), 0)
+
+
+# ---------------------------------------------------------------------------
+# what the trained network gains (a priori, held-out seed)
+# ---------------------------------------------------------------------------
+
+
+def test_trained_network_beats_the_analytic_closure_a_priori():
+    """Train on filtered DNS of two jets (256^2 DNS, Gaussian Delta = 16 fine
+    cells, 4x subsampled to 64^2) with the GPU's own kernels, then compare the
+    subgrid-term error on a held-out seed: analytic closure alone versus
+    analytic plus the network's correction."""
+    G = _gpu()
+    from paper_1705_09807_amd import training as TR
+    setup = TR.JetSetup(n_fine=256)
+    Xtr, Ttr = TR.samples(setup, seeds=[1, 2], les_times=[500, 750, 1000, 1250])
+    Xte, Tte = TR.samples(setup, seeds=[3], les_times=[750, 1000, 1250])
+    mlp = G.Mlp(G.glorot_params(4))
+    mlp.fit_norm(Xtr, Ttr)
+    losses = TR.train(mlp, Xtr, Ttr, steps=1500, batch=2048, lr=3e-3)
+    ana, lea, ood = TR.closure_errors(mlp, Xte, Tte)
+    ana, lea = ana.cpu().numpy(), lea.cpu().numpy()
+    ratio = lea / ana
+    print(f"train loss {losses[0].item():.3e} -> {losses[-100:].mean().item():.3e}; held-out MSE ratio "
+          f"learned/analytic per component {np.round(ratio, 3)}, total {lea.sum() / ana.sum():.3f}, "
+          f"out of range {ood.item():.2%}", flush=True)
+    assert np.isfinite(lea).all()
+    assert lea.sum() < 0.8 * ana.sum()
