@@ -156,6 +156,153 @@ def precision_study(steps: int, dev, stream) -> int:
     return 0
 
 
+def learned_study(args, dev, stream) -> int:
+    """A-posteriori test of the learned closure (filtered DNS -> 4x coarser LES).
+
+    DNS 4096^2 (FP32) of the jet at nu_DNS = 4 nu_LES (constant Reynolds
+    number), Gaussian filter of width 16 fine cells, 4x subsampled to 1024^2
+    (Delta = 4 LES cells).  The network is trained on two seeds with the
+    library's kernels; on a held-out seed the LES (analytic closure, and
+    analytic plus learned correction; FP32 and BF16 storage for the learned
+    one) starts from the filtered DNS initial state and runs alongside the
+    DNS.  Reported: the relative L2 error of the total-energy spectrum
+    E_K + E_M over the bins 1 .. N_LES/4 against the filtered DNS at several
+    times, the growth rate of the streamwise k_x = 1 mode, a-priori subgrid
+    errors, and wall-clock throughput of each run.  One JSON line on stdout.
+    """
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1705_09807_amd import Sim
+    from paper_1705_09807_amd import learned as G
+    from paper_1705_09807_amd import training as TR
+
+    setup = TR.JetSetup(n_fine=4096, factor=4, delta_fine=16.0, nu_les=NU, ghost=GHOST, U0=KH["U0"],
+                        delta_over_L=KH["delta_over_L"], B0=KH["B0"], pert_amp_over_U0=0.02, noise_amp=2e-3)
+    T_END = args.learned_study
+    train_times = [T_END * k // 6 for k in range(1, 7)]
+    t0 = time.perf_counter()
+    X, T = TR.samples(setup, seeds=[1, 2], les_times=train_times)
+    log(f"samples {tuple(X.shape)} in {time.perf_counter() - t0:.1f} s")
+    mlp = G.Mlp(G.glorot_params(0), device=dev, stream=stream)
+    mlp.fit_norm(X, T)
+    t1 = time.perf_counter()
+    losses = TR.train(mlp, X, T, steps=args.train_steps, batch=8192, lr=2e-3)
+    torch.cuda.synchronize(dev)
+    log(f"trained {args.train_steps} steps in {time.perf_counter() - t1:.1f} s: loss {losses[0].item():.3e} -> "
+        f"{losses[-200:].mean().item():.3e}")
+    del X, T
+    torch.cuda.empty_cache()
+
+    seed = 3
+    dns = TR.dns(setup, seed)
+    c0 = TR.filtered(setup, dns)
+    runs = {"analytic_fp32": ("analytic", "fp32"), "learned_fp32": ("learned", "fp32"),
+            "learned_bf16": ("learned", "bf16")}
+    les = {}
+    for name, (closure, dt) in runs.items():
+        g = setup.ghost
+        s = Sim(nx=setup.n_les, ny=setup.n_les, nu=setup.nu_les, eta=setup.nu_les, delta=setup.delta_les,
+                s5=g, s6=g, s7=g, s8=g, dtype=dt, b_ref=(setup.B0, 0.0), closure=closure, device=dev, stream=stream)
+        s.init_from_moments(c0[:5].contiguous())
+        if closure == "learned":
+            s.set_closure_mlp(mlp.pack())
+        les[name] = s
+    every = max(T_END // 40, 1)
+    n_cmp = setup.n_les // 4
+    series = {"t": [], "fdns": []}
+    for name in runs:
+        series[name] = []
+    spec_err = {name: [] for name in runs}
+    apriori = []
+    wall = {name: 0.0 for name in runs}
+    wall["dns"] = 0.0
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    t = 0
+    while True:
+        c = TR.filtered(setup, dns)
+        ek, em, ekx = G.spectra(c[:5].contiguous())
+        e_f = (ek + em)[1:n_cmp + 1]
+        series["t"].append(t)
+        series["fdns"].append(ekx[1].item())
+        for name, s in les.items():
+            mk, mm, mx_ = G.spectra(s.moments())
+            series[name].append(mx_[1].item())
+            if t > 0 and t % (T_END // 4) == 0:
+                e_l = (mk + mm)[1:n_cmp + 1]
+                spec_err[name].append((t, (torch.linalg.norm(e_l - e_f) / torch.linalg.norm(e_f)).item()))
+        if t > 0 and t % (T_END // 4) == 0:
+            Xs, Ts = G.closure_samples(c, setup.delta_les)
+            ana, lea, ood = TR.closure_errors(mlp, Xs, Ts)
+            apriori.append((t, (lea.sum() / ana.sum()).item(), ood.item()))
+        if t >= T_END:
+            break
+        if (t // every) % 10 == 0:
+            log(f"study t={t}: E_x(1) fdns {series['fdns'][-1]:.3e}, "
+                + ", ".join(f"{k} {series[k][-1]:.3e}" for k in runs))
+        a, b = ev(), ev()
+        a.record(stream)
+        dns.step(every * setup.factor)
+        b.record(stream)
+        for name, s in les.items():
+            x0, x1 = ev(), ev()
+            x0.record(stream)
+            s.step(every)
+            x1.record(stream)
+            torch.cuda.synchronize(dev)
+            wall[name] += x0.elapsed_time(x1)
+        torch.cuda.synchronize(dev)
+        wall["dns"] += a.elapsed_time(b)
+        t += every
+    finite = {name: s.diagnostics()["nonfinite"] == 0 for name, s in les.items()}
+
+    def growth(vals):
+        """Growth rate of the k_x = 1 amplitude, sqrt(E_x(1)), fitted over the
+        snapshots whose energy lies between 1e-3 and 1e-1 of the series peak."""
+        v = np.asarray(vals)
+        tt = np.asarray(series["t"], dtype=np.float64)
+        peak = v.max()
+        m = (v > 1e-3 * peak) & (v < 1e-1 * peak) & (tt > 0)
+        if m.sum() < 3:
+            m = (tt > 0) & (v < 0.3 * peak)
+        if m.sum() < 2:
+            return None
+        return float(0.5 * np.polyfit(tt[m], np.log(v[m]), 1)[0])
+
+    g_f = growth(series["fdns"])
+    res = {}
+    for name in runs:
+        g_l = growth(series[name])
+        res[name] = {
+            "spectrum_rel_l2": [(tt, round(e, 5)) for tt, e in spec_err[name]],
+            "growth_rate": g_l,
+            "growth_rate_rel_err": (None if g_l is None or not g_f else round(g_l / g_f - 1.0, 5)),
+            "finite": finite[name],
+            "les_ms_per_les_step": round(wall[name] / T_END, 4),
+            "fine_equivalent_mlups": round(setup.n_fine ** 2 * setup.factor * T_END / (wall[name] * 1e-3) / 1e6, 1),
+        }
+    out = {
+        "study": "learned closure vs analytic closure against filtered DNS (a posteriori)",
+        "dns": f"{setup.n_fine}^2 FP32, nu=eta={setup.nu_dns:g}, {T_END * setup.factor} steps",
+        "les": f"{setup.n_les}^2, Delta={setup.delta_les:g}, nu=eta={setup.nu_les:g}, {T_END} steps",
+        "filter": f"Gaussian width {setup.delta_fine:g} fine cells, every {setup.factor}th cell",
+        "jet": setup.kh(seed),
+        "train": {"seeds": [1, 2], "les_times": train_times, "steps": args.train_steps, "batch": 8192,
+                  "loss_first": losses[0].item(), "loss_last200": losses[-200:].mean().item()},
+        "held_out_seed": seed,
+        "spectrum_bins": [1, n_cmp],
+        "growth_rate_fdns": g_f,
+        "dns_fine_mlups": round(setup.n_fine ** 2 * setup.factor * T_END / (wall["dns"] * 1e-3) / 1e6, 1),
+        "apriori_mse_ratio_learned_over_analytic": [(tt, round(r, 4), round(o, 5)) for tt, r, o in apriori],
+        "runs": res,
+        "series_ex1": {k: [float(v) for v in vals] for k, vals in series.items()},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +313,8 @@ def main() -> int:
                     help="steps of a supplementary 4096^2 LES timing (0 = skip)")
     ap.add_argument("--lowprec-steps", type=int, default=50,
                     help="steps of the supplementary 8192^2 FP32/FP16/BF16 timings (0 = skip)")
+    ap.add_argument("--learned-steps", type=int, default=300,
+                    help="steps of the supplementary 1024^2 learned-closure LES timing (0 = skip)")
     ap.add_argument("--cpu-les-steps", type=int, default=15)
     ap.add_argument("--cpu-dns-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -173,6 +322,11 @@ def main() -> int:
                     help="instead of the benchmark: run the 8192^2 jet (nu = eta = 1e-4, B0 = 0.01) "
                          "for STEPS steps in FP64, FP32, FP16 and BF16 storage and print the per-field "
                          "relative L2 errors against the FP64 run as one JSON line")
+    ap.add_argument("--learned-study", type=int, default=0, metavar="LES_STEPS",
+                    help="instead of the benchmark: train the learned closure on filtered 4096^2 DNS and "
+                         "compare learned and analytic 1024^2 LES with the filtered DNS of a held-out seed "
+                         "over LES_STEPS steps (one JSON line)")
+    ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, run a plain device-to-device copy of this many bytes "
                          "(reference kernel for the HBM byte counters)")
@@ -196,6 +350,8 @@ def main() -> int:
     log(f"device: {torch.cuda.get_device_name(dev)}")
     if args.precision_study > 0:
         return precision_study(args.precision_study, dev, stream)
+    if args.learned_study > 0:
+        return learned_study(args, dev, stream)
 
     bref = (KH["B0"], 0.0)
     ghost = dict(s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
@@ -284,6 +440,42 @@ def main() -> int:
                             "kernel": "k_fused_les<float> (plain closure, Delta=4)"}
         log(f"les 4096^2: {ms * 1e3:.1f} us/step, {bw:.0f} GB/s algorithmic")
         del big
+
+    if args.learned_steps > 0:
+        # 1024^2 LES with the learned closure (moments -> network correction on
+        # the matrix cores -> fused collision), FP32 and BF16 storage.  The
+        # weights are an untrained Glorot draw: the work per cell does not
+        # depend on them.
+        from paper_1705_09807_amd import learned as G
+        mlp = G.Mlp(G.glorot_params(0), device=dev, stream=stream)
+        mlp.set_norm(shift=[1.0, 0.0, 0.0, KH["B0"], 0.0, 0.0, 0.0],
+                     scale=[1e3, 20.0, 20.0, 100.0, 100.0, 1e3, 1e3], out_scale=[1e-6] * 4)
+        packed = mlp.pack()
+        n_l = LES_N * LES_N
+        for dt in ("fp32", "bf16"):
+            sl = Sim(nx=LES_N, ny=LES_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype=dt, schedule="fused",
+                     b_ref=bref, closure="learned", device=dev, stream=stream, **ghost)
+            sl.init_kh_jet(seed=0, **KH)
+            sl.set_closure_mlp(packed)
+            sl.step(20)
+            a, b = ev(), ev()
+            a.record(stream)
+            sl.step(args.learned_steps)
+            b.record(stream)
+            torch.cuda.synchronize(dev)
+            ms = a.elapsed_time(b) / args.learned_steps
+            # matrix-core work of the network per cell: 63*64 + 64*64 + 64*4 multiply-adds
+            flops = 2 * (63 * 64 + 64 * 64 + 64 * 4) * n_l
+            extra[f"les1024_learned_{dt}"] = {
+                "mlups": round(n_l / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 2),
+                "network_tflops_per_step_time": round(flops / (ms * 1e-3) / 1e12, 1),
+                "fine_equivalent_mlups": round(64 * n_l / (ms * 1e-3) / 1e6, 1),
+                "note": "fine-equivalent: a 4x coarser grid (16x fewer cells) and 4x longer steps "
+                        "than the 4096^2 DNS it stands for",
+                "kernels": "k_moments5f + k_mlp_correct (bf16 MFMA) + k_fused_les<..., CORR>"}
+            log(f"learned les 1024^2 {dt}: {ms * 1e3:.1f} us/step")
+            del sl
+        del mlp, packed
 
     if args.lowprec_steps > 0:
         # 8192^2 jet, nu = eta = 1e-4: storage precision FP32 vs 16-bit deviations

@@ -136,6 +136,11 @@ int lbm_create(lbm_ctx** out, const lbm_params* p, void* state_dev, void* work_d
 /* Write the Kelvin-Helmholtz initial state (see lbm_kh_params); t = 0. */
 int lbm_init_kh_jet(lbm_ctx* ctx, const lbm_kh_params* kh);
 
+/* Replace the state by the unfiltered equilibria feq / geq (Sec. 2) of given
+ * fields: mom_dev = 5 FP64 planes rho (> 0), m_x = rho u_x, m_y, B_x, B_y in
+ * natural layout (e.g. filtered and subsampled DNS fields); time := t >= 0. */
+int lbm_init_from_moments(lbm_ctx* ctx, const double* mom_dev, int64_t t);
+
 /* Advance n >= 0 timesteps of Sec. 2 / Sec. 3 (collide in moment space,
  * stream).  Gradients of the closure are taken from the moments of the state
  * at the start of each step (synchronous). */

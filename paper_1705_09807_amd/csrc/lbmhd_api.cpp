@@ -151,6 +151,18 @@ int lbm_init_kh_jet(lbm_ctx* ctx, const lbm_kh_params* kh) {
   return LBM_OK;
 }
 
+int lbm_init_from_moments(lbm_ctx* ctx, const double* mom_dev, int64_t t) {
+  int rc = check_ctx(ctx, false);
+  if (rc != LBM_OK) return rc;
+  if (!mom_dev || !aligned(mom_dev)) return fail(LBM_EINVAL, "mom_dev must be a non-NULL 256-byte aligned pointer");
+  if (t < 0) return fail(LBM_EINVAL, "t must be >= 0");
+  hipError_t e = lbm::launch_init_moments(ctx->L, t, mom_dev);
+  if (e != hipSuccess) return hip_fail(e, "lbm_init_from_moments");
+  ctx->t = t;
+  ctx->initialized = true;
+  return LBM_OK;
+}
+
 int lbm_step(lbm_ctx* ctx, int64_t n) {
   int rc = check_ctx(ctx, true);
   if (rc != LBM_OK) return rc;

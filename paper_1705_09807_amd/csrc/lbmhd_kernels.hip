@@ -597,21 +597,12 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t counte
   return z ^ (z >> 31);
 }
 
-// Kelvin-Helmholtz double shear layer at the unfiltered equilibria feq / geq
-// (Sec. 2), evaluated in FP64 and rounded to the storage type.
+// Unfiltered equilibria feq / geq (Sec. 2) of one cell's fields, evaluated in
+// FP64 and rounded to the storage type.
 template <typename S>
-__global__ void __launch_bounds__(256)
-k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestRef ref, lbm_kh_params kh) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  if (x >= nx || y >= ny) return;
-  const double L = double(ny), d = kh.delta_over_L * L;
-  const double yy = double(y), xx = double(x);
-  const double ux = kh.U0 * (tanh((yy - 0.25 * L) / d) - tanh((yy - 0.75 * L) / d) - 1.0);
-  const uint64_t z = splitmix64_at(kh.seed, (uint64_t)y * (uint64_t)nx + (uint64_t)x);
-  const double xi = 2.0 * (double(z >> 11) * 0x1.0p-53) - 1.0;
-  const double uy = kh.pert_amp_over_U0 * kh.U0 * sin(2.0 * M_PI * xx / double(nx)) + kh.noise_amp * xi;
-  const double rho = kh.rho0, bx = kh.B0, by = 0.0;
+__device__ __forceinline__ void write_equilibrium(S* __restrict__ base, int x, int y, int nx, int ny, int64_t plane,
+                                                  int layout, const RestRef& ref, double rho, double ux, double uy,
+                                                  double bx, double by) {
   const double usq = ux * ux + uy * uy, bsq = bx * bx + by * by;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -630,6 +621,36 @@ k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestR
     base[natural_index(9 + i, x, y, nx, ny, plane, layout)] = encode<S>(gx - rest_value(9 + i, ref));
     base[natural_index(14 + i, x, y, nx, ny, plane, layout)] = encode<S>(gy - rest_value(14 + i, ref));
   }
+}
+
+// Kelvin-Helmholtz double shear layer at the unfiltered equilibria.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestRef ref, lbm_kh_params kh) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const double L = double(ny), d = kh.delta_over_L * L;
+  const double yy = double(y), xx = double(x);
+  const double ux = kh.U0 * (tanh((yy - 0.25 * L) / d) - tanh((yy - 0.75 * L) / d) - 1.0);
+  const uint64_t z = splitmix64_at(kh.seed, (uint64_t)y * (uint64_t)nx + (uint64_t)x);
+  const double xi = 2.0 * (double(z >> 11) * 0x1.0p-53) - 1.0;
+  const double uy = kh.pert_amp_over_U0 * kh.U0 * sin(2.0 * M_PI * xx / double(nx)) + kh.noise_amp * xi;
+  write_equilibrium<S>(base, x, y, nx, ny, plane, layout, ref, kh.rho0, ux, uy, kh.B0, 0.0);
+}
+
+// Equilibria of given fields: 5 FP64 planes rho, m_x, m_y, B_x, B_y.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_init_moments(S* __restrict__ base, const double* __restrict__ mom, int nx, int ny, int64_t plane, int layout,
+               RestRef ref) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const int64_t n = (int64_t)nx * ny, c = (int64_t)y * nx + x;
+  const double rho = mom[c];
+  write_equilibrium<S>(base, x, y, nx, ny, plane, layout, ref, rho, mom[n + c] / rho, mom[2 * n + c] / rho,
+                       mom[3 * n + c], mom[4 * n + c]);
 }
 
 template <typename S>
@@ -1019,6 +1040,22 @@ hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh) {
     case LBM_FP32: return init_typed<float>(L, kh);
     case LBM_FP16: return init_typed<_Float16>(L, kh);
     default: return init_typed<__bf16>(L, kh);
+  }
+}
+
+template <typename S>
+static hipError_t init_moments_typed(const Launch& L, int64_t t, const double* mom) {
+  hipLaunchKernelGGL((k_init_moments<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), mom, L.nx,
+                     L.ny, L.plane, layout_at(L, t), rest_ref(L));
+  return hipGetLastError();
+}
+
+hipError_t launch_init_moments(const Launch& L, int64_t t, const double* mom) {
+  switch (L.dtype) {
+    case LBM_FP64: return init_moments_typed<double>(L, t, mom);
+    case LBM_FP32: return init_moments_typed<float>(L, t, mom);
+    case LBM_FP16: return init_moments_typed<_Float16>(L, t, mom);
+    default: return init_moments_typed<__bf16>(L, t, mom);
   }
 }
 

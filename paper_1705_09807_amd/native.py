@@ -98,6 +98,7 @@ _SIGNATURES = {
     "lbm_work_bytes": (ctypes.c_size_t, [ctypes.POINTER(LbmParams)]),
     "lbm_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(LbmParams), _P, _P, _P]),
     "lbm_init_kh_jet": (ctypes.c_int, [_P, ctypes.POINTER(LbmKhParams)]),
+    "lbm_init_from_moments": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
     "lbm_step": (ctypes.c_int, [_P, ctypes.c_int64]),
     "lbm_get_time": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "lbm_moments": (ctypes.c_int, [_P, _P]),

@@ -73,6 +73,15 @@ class Sim:
                            pert_amp_over_U0=pert_amp_over_U0, noise_amp=noise_amp, seed=int(seed))
         N.check(self._lib.lbm_init_kh_jet(self._ctx, ctypes.byref(kh)), "lbm_init_kh_jet")
 
+    def init_from_moments(self, mom, t: int = 0):
+        """Equilibrium state of given fields mom [5, ny, nx] float64 (rho, m_x,
+        m_y, B_x, B_y; any device), time t."""
+        m = self._torch.as_tensor(mom, dtype=self._torch.float64).to(self.device).contiguous()
+        self._check_field(m, 5)
+        N.check(self._lib.lbm_init_from_moments(self._ctx, ctypes.c_void_p(m.data_ptr()), int(t)),
+                "lbm_init_from_moments")
+        self._keep = m
+
     def step(self, n: int = 1):
         N.check(self._lib.lbm_step(self._ctx, int(n)), "lbm_step")
 

@@ -92,6 +92,9 @@ def test_pointer_checks_and_call_order(lib):
         assert lib.lbm_get_state(ctx, ctypes.c_void_p(1 << 22)) == N.LBM_ESTATE
         assert lib.lbm_set_state(ctx, None, 0) == N.LBM_EINVAL
         assert lib.lbm_set_state(ctx, ctypes.c_void_p(1 << 22), -1) == N.LBM_EINVAL
+        assert lib.lbm_init_from_moments(ctx, None, 0) == N.LBM_EINVAL
+        assert lib.lbm_init_from_moments(ctx, ctypes.c_void_p(1 << 22), -1) == N.LBM_EINVAL
+        assert lib.lbm_init_from_moments(ctx, ctypes.c_void_p((1 << 22) + 8), 0) == N.LBM_EINVAL
         kh = N.LbmKhParams(U0=0.05, delta_over_L=0.0, B0=0.01, rho0=1.0, pert_amp_over_U0=1e-3,
                            noise_amp=1e-5, seed=0)
         assert lib.lbm_init_kh_jet(ctx, ctypes.byref(kh)) == N.LBM_EINVAL

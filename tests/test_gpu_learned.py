@@ -417,3 +417,25 @@ def test_trained_network_beats_the_analytic_closure_a_priori():
           f"out of range {ood.item():.2%}", flush=True)
     assert np.isfinite(lea).all()
     assert lea.sum() < 0.8 * ana.sum()
+
+
+@pytest.mark.parametrize("schedule", ["fused", "aa"])
+@pytest.mark.parametrize("t0", [0, 1])
+def test_init_from_moments_is_the_equilibrium(schedule, t0):
+    """lbm_init_from_moments writes feq / geq (Sec. 2) of the given fields."""
+    _gpu()
+    from paper_1705_09807_amd import Sim
+    nx, ny = 45, 31
+    f, g = _smooth_state(nx, ny, 81)
+    rho, mx, my, bx, by = O.Oracle._moments(f, g)
+    mom = np.stack([rho, mx, my, bx, by])
+    s = Sim(nx=nx, ny=ny, nu=0.02, eta=0.03, dtype="fp64", schedule=schedule)
+    s.init_from_moments(torch.from_numpy(mom), t0)
+    assert s.t == t0
+    got = s.get_state().cpu().numpy()
+    want = np.concatenate([O.f_equilibrium(rho, mx, my, bx, by),
+                           O.g_equilibrium(rho, mx, my, bx, by)[:, 0],
+                           O.g_equilibrium(rho, mx, my, bx, by)[:, 1]], 0)
+    assert np.abs(got - want).max() <= 4e-16 * np.abs(want).max()
+    back = s.moments().cpu().numpy()
+    assert np.abs(back - mom).max() <= 1e-15
