@@ -28,7 +28,7 @@
  *   z_k = (x_k - shift[field]) * scale[field]    (FP32 arithmetic),
  * then z, both hidden activations and all weights are rounded to bfloat16
  * (nearest even) and multiplied on the matrix cores with FP32 accumulation:
- *   h1 = tanh(W1^T z + b1), h2 = tanh(W2^T h1 + b2), y = W3^T h2 + b3,
+ *   h1 = relu(W1^T z + b1), h2 = relu(W2^T h1 + b2), y = W3^T h2 + b3,
  * 63 -> 64 -> 64 -> 4, and the correction is out_scale * y.  A cell with any
  * |z_k| > 6 is out of the training distribution and keeps the analytic
  * closure (correction 0).

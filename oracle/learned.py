@@ -21,7 +21,7 @@ The learned network predicts exact minus analytic.  Inputs: the 3x3 patch of
 (rho, u_x, u_y, B_x, B_y, w, J_z) around a coarse cell (w, J_z by central
 differences), index = field * 9 + (dy + 1) * 3 + (dx + 1), padded to 64.
 
-MLP 63 -> 64 -> 64 -> 4, tanh hidden activations, inputs normalised as
+MLP 63 -> 64 -> 64 -> 4, ReLU hidden activations, inputs normalised as
 z = (x - shift) * scale with one shift and scale per input field (the mean
 and inverse standard deviation of the field's centre feature), outputs
 multiplied by out_scale (the root mean square of each target).  The GPU
@@ -180,9 +180,9 @@ def forward(p: dict, X: np.ndarray, shift: np.ndarray, scale: np.ndarray, rnd=bf
     rounding applied where the GPU rounds to bfloat16 (identity: exact math)."""
     z = rnd(normalise(X, shift, scale))
     a1 = z @ rnd(p["w1"]) + p["b1"]
-    h1 = rnd(np.tanh(a1))
+    h1 = rnd(np.maximum(a1, 0.0))
     a2 = h1 @ rnd(p["w2"]) + p["b2"]
-    h2 = rnd(np.tanh(a2))
+    h2 = rnd(np.maximum(a2, 0.0))
     y = h2 @ rnd(p["w3"]) + p["b3"]
     return y, (z, h1, h2)
 
@@ -197,9 +197,9 @@ def loss_and_grads(p: dict, X, T, shift, scale, rnd=bf16):
     loss = float(np.mean(r * r))
     dy = 2.0 * r / (n * N_OUT)
     g = {"w3": h2.T @ dy, "b3": dy.sum(0)}
-    d2 = (dy @ rnd(p["w3"]).T) * (1.0 - h2 * h2)
+    d2 = (dy @ rnd(p["w3"]).T) * (h2 > 0)
     g["w2"], g["b2"] = h1.T @ d2, d2.sum(0)
-    d1 = (d2 @ rnd(p["w2"]).T) * (1.0 - h1 * h1)
+    d1 = (d2 @ rnd(p["w2"]).T) * (h1 > 0)
     g["w1"], g["b1"] = z.T @ d1, d1.sum(0)
     return loss, g
 

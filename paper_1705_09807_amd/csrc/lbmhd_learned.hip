@@ -4,7 +4,7 @@
 // Method: Flint & Vahala, arXiv 1705.09807.  The analytic closure (Sec. 2.1
 // FilterExampleSmall, Sec. 3) keeps the Delta^2/12 term of the filtered
 // products; the learned closure adds a per-cell correction of the same four
-// subgrid terms (tau_xx, tau_xy, tau_yy, eps), predicted by a 63-64-64-4
+// subgrid terms (tau_xx, tau_xy, tau_yy, eps), predicted by a 63-64-64-4 ReLU
 // network trained on filtered DNS (the convolution of Sec. 1, VelFilter, with
 // a Gaussian of variance Delta^2/12).  The spectra are the radially binned
 // kinetic and magnetic energies compared in Sec. 4.
@@ -31,6 +31,20 @@ namespace lbm {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Eight floats rounded to bfloat16 (nearest even), two per conversion.
+__device__ __forceinline__ unsigned pack2_bf16(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+__device__ __forceinline__ bf16x8 to_bf16x8(const f32x8& v) {
+  const u32x4 u = {pack2_bf16(v[0], v[1]), pack2_bf16(v[2], v[3]), pack2_bf16(v[4], v[5]), pack2_bf16(v[6], v[7])};
+  return __builtin_bit_cast(bf16x8, u);
+}
 
 // Packed network (LBM_MLP_PACKED_BYTES): bfloat16 A operands in lane order,
 // FP32 biases, the normalisation.
@@ -57,18 +71,6 @@ static_assert(chained_k(1, 0, 0) == 16 && chained_k(0, 1, 4) == 12 && chained_k(
 
 // Field of feature k < 63 (k / 9) and its 3x3 offset, by multiply-shift.
 __device__ __forceinline__ int feat_field(int k) { return (k * 57) >> 9; }
-
-// tanh in FP32: odd Taylor polynomial through x^9 for |x| < 0.3 (truncation
-// below 2e-8 relative), else (1 - e^{-2|x|}) / (1 + e^{-2|x|}) with the
-// hardware exp2 and reciprocal (about 1e-7 relative).
-__device__ __forceinline__ float tanh_f(float x) {
-  const float a = fabsf(x);
-  const float x2 = x * x;
-  const float p = x * (1.0f + x2 * (-1.0f / 3.0f + x2 * (2.0f / 15.0f + x2 * (-17.0f / 315.0f + x2 * (62.0f / 2835.0f)))));
-  const float t = __builtin_amdgcn_exp2f(-2.885390081777927f * a);  // e^{-2a}
-  const float q = copysignf((1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t), x);
-  return a < 0.3f ? p : q;
-}
 
 __device__ __forceinline__ float bf16_round(float v) { return float(__bf16(v)); }
 
@@ -105,17 +107,27 @@ __device__ __forceinline__ f32x16 bias_tile(const float* __restrict__ b, int ot,
   return acc;
 }
 
-// tanh of two accumulator tiles, rounded to bfloat16, as the four B operands
-// of the next layer.  The rounded values go to hout (as floats) when given.
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+// ReLU of two accumulator tiles, rounded to bfloat16, as the four B operands
+// of the next layer.  Rounding is monotonic and keeps the sign, so the ReLU
+// is taken after it, on the packed bfloat16 bit patterns read as int16
+// (negative values, -0 included, are negative int16 and become +0).  The
+// rounded values go to hout (as floats) when given.
 __device__ __forceinline__ void activate(const f32x16 acc[2], bf16x8 hb[4], float* hout) {
 #pragma unroll
-  for (int kb = 0; kb < 4; ++kb)
+  for (int kb = 0; kb < 4; ++kb) {
+    f32x8 a;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const __bf16 v = __bf16(tanh_f(acc[kb / 2][(kb % 2) * 8 + j]));
-      hb[kb][j] = v;
-      if (hout) hout[kb * 8 + j] = float(v);
+    for (int j = 0; j < 8; ++j) a[j] = acc[kb / 2][(kb % 2) * 8 + j];
+    const bf16x8 v = to_bf16x8(a);
+    const i16x8 bits = __builtin_elementwise_max(__builtin_bit_cast(i16x8, v), i16x8(0));
+    hb[kb] = __builtin_bit_cast(bf16x8, bits);
+    if (hout) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) hout[kb * 8 + j] = float(hb[kb][j]);
     }
+  }
 }
 
 // The network on the 32 cells of a wave: zb = layer-1 B operands of this lane
@@ -123,12 +135,14 @@ __device__ __forceinline__ void activate(const f32x16 acc[2], bf16x8 hb[4], floa
 // (components 0..3).  h1, h2 (32 floats each, may be null) receive the
 // bfloat16 activations held by this lane, element kb*8 + j = hidden
 // chained_k(kb, lane/32, j).
-__device__ __forceinline__ f32x4 mlp_wave(const MlpA& w, const bf16x8 zb[4], const char* __restrict__ pk, int lane,
+// Biases: b points at b1 (64 floats), b2 (64) and b3 (4) back to back, in
+// LDS or global memory.
+__device__ __forceinline__ f32x4 mlp_wave(const MlpA& w, const bf16x8 zb[4], const float* __restrict__ b, int lane,
                                           float* h1, float* h2) {
   const int h = lane >> 5;
-  const float* b1 = reinterpret_cast<const float*>(pk + kPkB1);
-  const float* b2 = reinterpret_cast<const float*>(pk + kPkB2);
-  const float* b3 = reinterpret_cast<const float*>(pk + kPkB3);
+  const float* b1 = b;
+  const float* b2 = b + 64;
+  const float* b3 = b + 128;
   f32x16 acc[2];
   bf16x8 hb[4];
 #pragma unroll
@@ -241,7 +255,7 @@ k_mlp_forward(const char* __restrict__ pk, const float* __restrict__ x, int64_t 
     bf16x8 zb[4];
     bool o;
     row_operands(x, rr, nm, h, zb, &o, nullptr);
-    const f32x4 v = mlp_wave(w, zb, pk, lane, nullptr, nullptr);
+    const f32x4 v = mlp_wave(w, zb, reinterpret_cast<const float*>(pk + kPkB1), lane, nullptr, nullptr);
     // every lane takes part in the exchange (a short-circuit would leave the
     // flagged lane inactive and its partner would read nothing from it)
     const int partner = __shfl_xor(int(o), 32, 64);
@@ -255,83 +269,132 @@ k_mlp_forward(const char* __restrict__ pk, const float* __restrict__ x, int64_t 
 
 // ---------------------------------------------------------------------------
 // Correction of a simulation state.  Input: five FP32 planes rho, m_x, m_y,
-// B_x, B_y.  A workgroup stages a 64 x 16 tile with a two-cell halo in LDS,
-// forms u = m / rho, the central-difference vorticity and current on the
-// one-cell halo, normalises the seven fields, and evaluates the network for
-// its 1024 cells (each wave 8 groups of 32).  Output: four FP32 planes
-// tau_xx, tau_xy, tau_yy, eps = out_scale * y, 0 where a cell's inputs are
-// out of distribution.
+// B_x, B_y.  A workgroup stages a 64 x 16 tile with a two-cell halo in LDS
+// (all loads of a thread issued before any is used), forms u = m / rho, the
+// central-difference vorticity and current on the one-cell halo, normalises
+// the seven fields and flags cells with any |z| > 6, then evaluates the
+// network for its 1024 cells (each wave 8 groups of 32).  A cell is out of
+// distribution when a flagged cell lies in its 3x3 neighbourhood (its 63
+// inputs are exactly the seven fields there).  Output: four FP32 planes
+// tau_xx, tau_xy, tau_yy, eps = out_scale * y, 0 for out-of-distribution cells.
 // ---------------------------------------------------------------------------
 constexpr int kCorrTX = 64, kCorrTY = 16;
-constexpr int kCorrLX = kCorrTX + 4, kCorrLY = kCorrTY + 4;
+constexpr int kCorrLX = kCorrTX + 4, kCorrLY = kCorrTY + 4, kCorrPL = kCorrLX * kCorrLY;
 
-__global__ void __launch_bounds__(256)
+// LDS offset of feature k (< 63) from the patch corner of cell (ty, tx):
+// plane k / 9, row (k % 9) / 3, column (k % 9) % 3, corner at (ty + 1, tx + 1).
+__host__ __device__ constexpr int corr_feature_offset(int k) {
+  return (k / 9) * kCorrPL + ((k % 9) / 3) * kCorrLX + (k % 9) % 3 + kCorrLX + 1;
+}
+
+// Periodic wrap of v in [-2, n + kCorrLX) into [0, n).
+__device__ __forceinline__ int wrap_halo(int v, int n, bool wide) {
+  if (wide) {
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
+  }
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+__global__ void __launch_bounds__(256, 2)
 k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float* __restrict__ corr, int nx, int ny) {
-  __shared__ float fld[7][kCorrLY][kCorrLX];
+  constexpr int LX = kCorrLX, PL = kCorrPL;
+  __shared__ float fld[7 * PL];
+  __shared__ unsigned char bad[PL];
+  __shared__ __attribute__((aligned(16))) float bias[132];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, h = lane >> 5;
+  if (tid < 132) bias[tid] = reinterpret_cast<const float*>(pk + kPkB1)[tid];
   const int x0 = blockIdx.x * kCorrTX, y0 = blockIdx.y * kCorrTY;
   const int64_t n = (int64_t)nx * ny;
   const lbm_mlp_norm* nm = reinterpret_cast<const lbm_mlp_norm*>(pk + kPkNorm);
   // 1. primary fields on the tile and its two-cell halo
-  for (int e = tid; e < kCorrLX * kCorrLY; e += 256) {
-    const int ly = e / kCorrLX, lx = e - ly * kCorrLX;
-    int gx = (x0 + lx - 2) % nx, gy = (y0 + ly - 2) % ny;
-    if (gx < 0) gx += nx;
-    if (gy < 0) gy += ny;
-    const int64_t c = (int64_t)gy * nx + gx;
-    const float r = mom[c];
-    fld[0][ly][lx] = r;
-    fld[1][ly][lx] = mom[n + c] / r;
-    fld[2][ly][lx] = mom[2 * n + c] / r;
-    fld[3][ly][lx] = mom[3 * n + c];
-    fld[4][ly][lx] = mom[4 * n + c];
+  constexpr int PER = (PL + 255) / 256;
+  float vr[PER], vmx[PER], vmy[PER], vbx[PER], vby[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + 256 * i;
+    if (e < PL) {
+      const int ly = e / LX, lx = e - ly * LX;
+      const int gx = wrap_halo(x0 + lx - 2, nx, nx >= LX), gy = wrap_halo(y0 + ly - 2, ny, ny >= kCorrLY);
+      const int64_t c = (int64_t)gy * nx + gx;
+      vr[i] = mom[c];
+      vmx[i] = mom[n + c];
+      vmy[i] = mom[2 * n + c];
+      vbx[i] = mom[3 * n + c];
+      vby[i] = mom[4 * n + c];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + 256 * i;
+    if (e < PL) {
+      fld[e] = vr[i];
+      fld[PL + e] = vmx[i] / vr[i];
+      fld[2 * PL + e] = vmy[i] / vr[i];
+      fld[3 * PL + e] = vbx[i];
+      fld[4 * PL + e] = vby[i];
+    }
   }
   __syncthreads();
   // 2. vorticity and current on the tile and its one-cell halo
-  for (int e = tid; e < (kCorrLX - 2) * (kCorrLY - 2); e += 256) {
-    const int ly = e / (kCorrLX - 2) + 1, lx = e % (kCorrLX - 2) + 1;
-    fld[5][ly][lx] = 0.5f * (fld[2][ly][lx + 1] - fld[2][ly][lx - 1]) - 0.5f * (fld[1][ly + 1][lx] - fld[1][ly - 1][lx]);
-    fld[6][ly][lx] = 0.5f * (fld[4][ly][lx + 1] - fld[4][ly][lx - 1]) - 0.5f * (fld[3][ly + 1][lx] - fld[3][ly - 1][lx]);
+  constexpr int RX = LX - 2, RN = RX * (kCorrLY - 2), PER2 = (RN + 255) / 256;
+#pragma unroll
+  for (int i = 0; i < PER2; ++i) {
+    const int e = tid + 256 * i;
+    if (e < RN) {
+      const int ly = e / RX + 1, p = ly * LX + (e - (ly - 1) * RX) + 1;
+      fld[5 * PL + p] = 0.5f * (fld[2 * PL + p + 1] - fld[2 * PL + p - 1]) - 0.5f * (fld[PL + p + LX] - fld[PL + p - LX]);
+      fld[6 * PL + p] = 0.5f * (fld[4 * PL + p + 1] - fld[4 * PL + p - 1]) - 0.5f * (fld[3 * PL + p + LX] - fld[3 * PL + p - LX]);
+    }
   }
   __syncthreads();
-  // 3. normalise the one-cell-halo region of every field
-  for (int e = tid; e < 7 * (kCorrLX - 2) * (kCorrLY - 2); e += 256) {
-    const int f = e / ((kCorrLX - 2) * (kCorrLY - 2));
-    const int r = e - f * (kCorrLX - 2) * (kCorrLY - 2);
-    const int ly = r / (kCorrLX - 2) + 1, lx = r % (kCorrLX - 2) + 1;
-    fld[f][ly][lx] = (fld[f][ly][lx] - nm->shift[f]) * nm->scale[f];
+  // 3. normalise the one-cell-halo region of every field; flag |z| > 6
+#pragma unroll
+  for (int i = 0; i < PER2; ++i) {
+    const int e = tid + 256 * i;
+    if (e < RN) {
+      const int ly = e / RX + 1, p = ly * LX + (e - (ly - 1) * RX) + 1;
+      bool b = false;
+#pragma unroll
+      for (int f = 0; f < 7; ++f) {
+        const float z = (fld[f * PL + p] - nm->shift[f]) * nm->scale[f];
+        fld[f * PL + p] = z;
+        b = b || fabsf(z) > kOodLimit;
+      }
+      bad[p] = b ? 1 : 0;
+    }
   }
   __syncthreads();
+  // 4. the network, 32 cells per wave at a time (operands and biases held in
+  // registers for the whole loop)
   MlpA w;
   load_mlp(pk, lane, w);
   for (int g = wid; g < kCorrTX * kCorrTY / 32; g += 4) {
-    const int ty = g >> 1, tx = (g & 1) * 32 + (lane & 31);
+    const int ty = g >> 1, tx = (g & 1) * 32 + (lane & 31), base = ty * LX + tx;
     bf16x8 zb[4];
-    bool o = false;
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
+    for (int kb = 0; kb < 4; ++kb) {
+      f32x8 zf;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int k = kb * 16 + h * 8 + j;
-        float z = 0.0f;
-        if (k < 63) {
-          const int f = feat_field(k), d = k - 9 * f;
-          const int dy = (d * 11) >> 5, dx = d - 3 * dy;  // d / 3, d % 3
-          z = fld[f][ty + 1 + dy][tx + 1 + dx];
-        }
-        o = o || fabsf(z) > kOodLimit;
-        zb[kb][j] = __bf16(z);
+        const int k0 = kb * 16 + j, k1 = kb * 16 + 8 + j;  // this lane's input: k0 (h = 0) or k1 (h = 1)
+        if (k1 == 63)
+          zf[j] = h ? 0.0f : fld[base + corr_feature_offset(k0)];
+        else
+          zf[j] = fld[base + (h ? corr_feature_offset(k1) : corr_feature_offset(k0))];
       }
-    const f32x4 v = mlp_wave(w, zb, pk, lane, nullptr, nullptr);
-    // every lane takes part in the exchange (a short-circuit would leave the
-    // flagged lane inactive and its partner would read nothing from it)
-    const int partner = __shfl_xor(int(o), 32, 64);
-    const bool oo = o || partner != 0;
+      zb[kb] = to_bf16x8(zf);
+    }
+    int o = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) o |= bad[base + (q / 3) * LX + q % 3 + LX + 1];
+    const f32x4 v = mlp_wave(w, zb, bias, lane, nullptr, nullptr);
     const int gx = x0 + tx, gy = y0 + ty;
     if (h == 0 && gx < nx && gy < ny) {
       const int64_t c = (int64_t)gy * nx + gx;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) corr[q * n + c] = oo ? 0.0f : v[q] * nm->out_scale[q];
+      for (int q = 0; q < 4; ++q) corr[q * n + c] = o ? 0.0f : v[q] * nm->out_scale[q];
     }
   }
 }
@@ -389,7 +452,7 @@ k_mlp_train(const char* __restrict__ pk, const float* __restrict__ p, const floa
       float zf[32], h1[32], h2[32];
       bool o;
       row_operands(x, row, nm, h, zb, &o, zf);
-      const f32x4 y = mlp_wave(w, zb, pk, lane, h1, h2);
+      const f32x4 y = mlp_wave(w, zb, reinterpret_cast<const float*>(pk + kPkB1), lane, h1, h2);
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
@@ -408,20 +471,18 @@ k_mlp_train(const char* __restrict__ pk, const float* __restrict__ p, const floa
       }
     }
     __syncthreads();
-    // d2[s][j] = (W3 d3)_j (1 - h2^2): thread (col = j, half) takes 32 rows
+    // d2[s][j] = (W3 d3)_j [h2 > 0]: thread (col = j, half) takes 32 rows
     for (int r = half * 32; r < half * 32 + 32; ++r) {
       const float a = w3row[0] * s.d3[r][0] + w3row[1] * s.d3[r][1] + w3row[2] * s.d3[r][2] + w3row[3] * s.d3[r][3];
-      const float hv = s.h2[r][col];
-      s.d2[r][col] = a * (1.0f - hv * hv);
+      s.d2[r][col] = s.h2[r][col] > 0.0f ? a : 0.0f;
     }
     __syncthreads();
-    // d1[s][i] = (W2 d2)_i (1 - h1^2): thread (col = i, half)
+    // d1[s][i] = (W2 d2)_i [h1 > 0]: thread (col = i, half)
     for (int r = half * 32; r < half * 32 + 32; ++r) {
       float a = 0.0f;
 #pragma unroll
       for (int j = 0; j < 64; ++j) a += w2row[j] * s.d2[r][j];
-      const float hv = s.h1[r][col];
-      s.d1[r][col] = a * (1.0f - hv * hv);
+      s.d1[r][col] = s.h1[r][col] > 0.0f ? a : 0.0f;
     }
     __syncthreads();
     // gradients: g1[k][i] += z d1, g2[i][j] += h1 d2, g3[j][o] += h2 d3

@@ -3,9 +3,9 @@ spectra against the FP64 oracle (oracle/learned.py, oracle/spectra.py).
 
 Tolerances.  FP64 paths (filter, spectra, the collision with a given
 correction) are held to round-off.  The network runs in bfloat16 with FP32
-accumulation on both sides' definitions, but the oracle accumulates in FP64
-and uses the exact tanh: a pre-activation that lands within ~1e-7 of a
-bfloat16 rounding boundary can round the other way, changing that
+accumulation on both sides' definitions, but the oracle accumulates in FP64:
+a pre-activation that lands within ~1e-7 of a bfloat16 rounding boundary can
+round the other way, changing that
 activation by one bfloat16 step (2^-8 relative) and the output by at most
 about |w| 2^-8.  The tests bound the worst row by a few such steps and
 require the bulk of rows to agree to FP32 accumulation noise; measured

@@ -230,8 +230,8 @@ def test_mlp_forward_against_torch():
             * torch.from_numpy(scale.astype(np.float32))
         z32[:, 63] = 0
         z = r(z32.to(torch.float64))
-        h = r(torch.tanh(z @ r(tb(p["w1"])) + tb(p["b1"])))
-        h = r(torch.tanh(h @ r(tb(p["w2"])) + tb(p["b2"])))
+        h = r(torch.relu(z @ r(tb(p["w1"])) + tb(p["b1"])))
+        h = r(torch.relu(h @ r(tb(p["w2"])) + tb(p["b2"])))
         want = (h @ r(tb(p["w3"])) + tb(p["b3"])).numpy()
         assert np.max(np.abs(y - want)) < 1e-12
 
