@@ -31,7 +31,7 @@
  *   h1 = relu(W1^T z + b1), h2 = relu(W2^T h1 + b2), y = W3^T h2 + b3,
  * 63 -> 64 -> 64 -> 4, and the correction is out_scale * y.  A cell with any
  * |z_k| > 6 is out of the training distribution and keeps the analytic
- * closure (correction 0).
+ * closure (correction 0); so does a cell with a non-finite input or output.
  */
 #ifndef LBMHD_LEARNED_H
 #define LBMHD_LEARNED_H
@@ -80,7 +80,7 @@ int lbm_mlp_pack(const float* params_dev, const lbm_mlp_norm* norm_dev, void* pa
 
 /* Network on n >= 0 feature rows x_dev[n][64] (FP32; column 63 ignored):
  * y_dev[n][4] = y (before out_scale); ood_dev[n] (may be NULL) = 1 where any
- * |z_k| > 6, else 0. */
+ * |z_k| > 6 or is not finite, else 0. */
 int lbm_mlp_forward(const void* packed_dev, const float* x_dev, int64_t n, float* y_dev, int32_t* ood_dev,
                     void* hip_stream);
 

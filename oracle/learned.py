@@ -207,13 +207,15 @@ def loss_and_grads(p: dict, X, T, shift, scale, rnd=bf16):
 def learned_correction(p: dict, shift, scale, out_scale, ood: float = 6.0):
     """Closure correction for ``Oracle(closure_correction=...)``: the network's
     (tau_xx, tau_xy, tau_yy, eps) corrections from the current moments; cells
-    with any normalised input beyond `ood` fall back to the analytic closure
-    (correction 0)."""
+    with any normalised input beyond `ood` (or not finite), or a non-finite
+    output, fall back to the analytic closure (correction 0)."""
     def corr(rho, mx, my, bx, by):
         X = closure_features(rho, mx, my, bx, by)
-        y, _ = forward(p, X, shift, scale)
-        zn = np.abs(normalise(X, shift, scale))
-        y = np.where((zn > ood).any(axis=1, keepdims=True), 0.0, y * out_scale)
+        with np.errstate(invalid="ignore", over="ignore"):
+            y, _ = forward(p, X, shift, scale)
+            zn = np.abs(normalise(X, shift, scale))
+            out = ~(zn <= ood).all(axis=1, keepdims=True) | ~np.isfinite(y).all(axis=1, keepdims=True)
+            y = np.where(out, 0.0, y * out_scale)
         return y.T.reshape((N_OUT,) + rho.shape)
     return corr
 

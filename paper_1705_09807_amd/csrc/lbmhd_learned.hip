@@ -232,7 +232,7 @@ __device__ __forceinline__ void row_operands(const float* __restrict__ x, int64_
         const int f = feat_field(k);
         z = (xv - nm->shift[f]) * nm->scale[f];
       }
-      o = o || fabsf(z) > kOodLimit;
+      o = o || !(fabsf(z) <= kOodLimit);  // NaN counts as out of range
       zb[kb][j] = __bf16(z);
       if (zf) zf[kb * 8 + j] = float(zb[kb][j]);
     }
@@ -272,11 +272,12 @@ k_mlp_forward(const char* __restrict__ pk, const float* __restrict__ x, int64_t 
 // B_x, B_y.  A workgroup stages a 64 x 16 tile with a two-cell halo in LDS
 // (all loads of a thread issued before any is used), forms u = m / rho, the
 // central-difference vorticity and current on the one-cell halo, normalises
-// the seven fields and flags cells with any |z| > 6, then evaluates the
+// the seven fields and flags cells with any |z| > 6 (or NaN), then evaluates the
 // network for its 1024 cells (each wave 8 groups of 32).  A cell is out of
 // distribution when a flagged cell lies in its 3x3 neighbourhood (its 63
 // inputs are exactly the seven fields there).  Output: four FP32 planes
-// tau_xx, tau_xy, tau_yy, eps = out_scale * y, 0 for out-of-distribution cells.
+// tau_xx, tau_xy, tau_yy, eps = out_scale * y, 0 for out-of-distribution cells
+// and cells whose output is not finite.
 // ---------------------------------------------------------------------------
 constexpr int kCorrTX = 64, kCorrTY = 16;
 constexpr int kCorrLX = kCorrTX + 4, kCorrLY = kCorrTY + 4, kCorrPL = kCorrLX * kCorrLY;
@@ -360,7 +361,7 @@ k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float*
       for (int f = 0; f < 7; ++f) {
         const float z = (fld[f * PL + p] - nm->shift[f]) * nm->scale[f];
         fld[f * PL + p] = z;
-        b = b || fabsf(z) > kOodLimit;
+        b = b || !(fabsf(z) <= kOodLimit);  // NaN counts as out of range
       }
       bad[p] = b ? 1 : 0;
     }
@@ -390,6 +391,7 @@ k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float*
 #pragma unroll
     for (int q = 0; q < 9; ++q) o |= bad[base + (q / 3) * LX + q % 3 + LX + 1];
     const f32x4 v = mlp_wave(w, zb, bias, lane, nullptr, nullptr);
+    o = o || !(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]));
     const int gx = x0 + tx, gy = y0 + ty;
     if (h == 0 && gx < nx && gy < ny) {
       const int64_t c = (int64_t)gy * nx + gx;

@@ -439,3 +439,21 @@ def test_init_from_moments_is_the_equilibrium(schedule, t0):
     assert np.abs(got - want).max() <= 4e-16 * np.abs(want).max()
     back = s.moments().cpu().numpy()
     assert np.abs(back - mom).max() <= 1e-15
+
+
+def test_non_finite_network_output_keeps_the_analytic_closure():
+    """A network whose output is NaN leaves every cell on the analytic closure:
+    the learned step then equals the analytic LES step."""
+    _gpu()
+    from paper_1705_09807_amd import learned as G
+    nx, ny = 48, 40
+    f, g = _smooth_state(nx, ny, 91)
+    p = _params(92)
+    p["b3"] = np.array([np.nan, 0.0, 0.0, 0.0])
+    shift, scale, out_scale, s64, c64 = _state_norm(f, g)
+    s = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale)
+    assert np.all(s.closure_correction().cpu().numpy() == 0)
+    s.step(2)
+    a = _sim_state(nx, ny, f, g, delta=2.0, s5=1.3, s6=1.5, s7=1.7, s8=1.1, b_ref=(0.01, 0.0))
+    a.step(2)
+    assert torch.equal(s.get_state(), a.get_state())

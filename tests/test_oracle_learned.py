@@ -372,6 +372,12 @@ def test_learned_correction_zero_network_and_ood():
     ood = rho * scale2[4] > 6.0
     assert ood.any() and (~ood).any()
     assert np.all(corr2[:, ood] == 0) and np.all(corr2[:, ~ood] == corr[:, ~ood])
+    # a non-finite output (NaN bias) or input (NaN shift) falls back everywhere
+    p_nan = dict(p, b3=np.array([np.nan, 0.0, 0.0, 0.0]))
+    assert np.all(L.learned_correction(p_nan, shift, scale, out_scale)(rho, mx, my, bx, by) == 0)
+    shift_nan = shift.copy()
+    shift_nan[0] = np.nan
+    assert np.all(L.learned_correction(p, shift_nan, scale, out_scale)(rho, mx, my, bx, by) == 0)
 
 
 # ---------------------------------------------------------------------------
