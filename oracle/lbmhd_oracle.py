@@ -316,7 +316,7 @@ class Oracle:
 
     def __init__(self, nx: int, ny: int, nu: float, eta: float, delta: float = 0.0,
                  closure_scale: float = 1.0, s5=None, s6=None, s7=None, s8=None,
-                 grad_stencil: str = "iso9", closure_correction=None):
+                 grad_stencil: str = "iso9", closure_correction=None, closure_time: str = "sync"):
         if nx < 4 or ny < 4:
             raise ValueError("grid must be at least 4 x 4")
         self.nx, self.ny = int(nx), int(ny)
@@ -332,6 +332,15 @@ class Oracle:
         # optional learned correction: (rho, m_x, m_y, B_x, B_y) -> [4, ny, nx] of
         # (tau_xx, tau_xy, tau_yy, eps) added to the analytic closure terms
         self.closure_correction = closure_correction
+        # "sync": gradients of the moments of the state being collided (Sec. 2.1,
+        # Sec. 3).  "lagged": gradients of the previous step's moments (the
+        # single-sweep variant of the in-place schedule); the first step after
+        # an initial or injected state uses that state's own moments.  The 1/rho
+        # of the closure is always the current density.
+        if closure_time not in ("sync", "lagged"):
+            raise ValueError("closure_time must be 'sync' or 'lagged'")
+        self.closure_time = closure_time
+        self._prev = None
         self.f = np.zeros((9, self.ny, self.nx))
         self.g = np.zeros((5, 2, self.ny, self.nx))
         self.t = 0
@@ -346,11 +355,13 @@ class Oracle:
         self.f, self.g = kh_jet_populations(x, y, self.nx, self.ny, U0, delta_over_L, B0, rho0,
                                             pert_amp_over_U0, noise_amp, seed)
         self.t = 0
+        self._prev = None
 
     def set_state(self, f, g, t: int = 0):
         self.f = np.array(f, dtype=np.float64).reshape(9, self.ny, self.nx)
         self.g = np.array(g, dtype=np.float64).reshape(5, 2, self.ny, self.nx)
         self.t = int(t)
+        self._prev = None
 
     def state(self):
         """(f, g, t): copies of the post-streaming populations at time t."""
@@ -371,7 +382,7 @@ class Oracle:
         """(rho, m_x, m_y, B_x, B_y) at the current time, each [ny, nx]."""
         return self._moments(self.f, self.g)
 
-    def collide(self, f, g):
+    def collide(self, f, g, grad_fields=None):
         """One collision (Sec. 2 ``LBKinEqn``/``LBMagEqn``, Sec. 3): moments,
         synchronous gradients, filtered equilibria, MRT relaxation of f in
         moment space (``Transformation``), SRT relaxation of g.  Returns the
@@ -380,9 +391,11 @@ class Oracle:
         The f collision is the right-hand side of ``LBKinEqn`` with the rate
         tensor s' = T^-1 S T:  f* = f + s' (f^eq - f) = f - T^-1 S (M - M^eq),
         M = T f.  Relaxation acts on the moments; conserved moments (rate 0)
-        contribute nothing."""
+        contribute nothing.  `grad_fields` (m_x, m_y, B_x, B_y), when given,
+        are the fields the closure differentiates instead of the current ones."""
         rho, mx, my, Bx, By = self._moments(f, g)
-        P, Q, R = closure_terms(rho, mx, my, Bx, By, self.k2, self.grad_stencil)
+        gm = (mx, my, Bx, By) if grad_fields is None else grad_fields
+        P, Q, R = closure_terms(rho, gm[0], gm[1], gm[2], gm[3], self.k2, self.grad_stencil)
         meq = filtered_equilibrium_moments(rho, mx, my, Bx, By, P, Q)
         lam = filtered_induction(rho, mx, my, Bx, By, R)
         if self.closure_correction is not None:
@@ -414,7 +427,13 @@ class Oracle:
 
     def step(self, n: int = 1):
         for _ in range(int(n)):
-            fstar, gstar = self.collide(self.f, self.g)
+            if self.closure_time == "lagged":
+                cur = self._moments(self.f, self.g)[1:]
+                src = cur if self._prev is None else self._prev
+                fstar, gstar = self.collide(self.f, self.g, grad_fields=src)
+                self._prev = cur
+            else:
+                fstar, gstar = self.collide(self.f, self.g)
             self.f, self.g = self.stream(fstar, gstar)
             self.t += 1
 
