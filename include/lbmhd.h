@@ -67,6 +67,16 @@ extern "C" {
 #define LBM_SCHED_FUSED 0  /* two population buffers, one fused sweep per step */
 #define LBM_SCHED_AA 1     /* one buffer updated in place (AA pattern); with the
                               closure on, a moment sweep precedes the collide sweep */
+#define LBM_SCHED_AA_LAGGED 2  /* in place, one sweep per step: the closure
+                              differentiates the moments of the previous step
+                              (written by the previous sweep into a second set of
+                              moment planes) instead of the current ones.  A
+                              different result from the synchronous closure: the
+                              gradients lag by one step.  The first step after
+                              lbm_init_kh_jet, lbm_set_state or
+                              lbm_init_from_moments is synchronous, so a run
+                              resumed from a saved state is not bit-identical to
+                              an uninterrupted one. */
 
 /* Subgrid closure of the LES (Delta > 0). */
 #define LBM_CLOSURE_ANALYTIC 0  /* the Delta^2/12 closure of Sec. 2.1 / Sec. 3      */

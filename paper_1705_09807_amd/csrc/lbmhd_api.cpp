@@ -21,6 +21,7 @@ struct lbm_ctx {
   int64_t t = 0;
   bool initialized = false;
   bool mlp_set = false;  // learned closure: a network has been installed
+  bool lag_ready = false;  // lagged schedule: moment set t & 1 holds step t - 1
 };
 
 namespace {
@@ -57,8 +58,8 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
   if (!std::isfinite(p->closure_scale)) return fail(LBM_EINVAL, "closure_scale must be finite");
   if (p->grad_stencil != LBM_STENCIL_ISO9 && p->grad_stencil != LBM_STENCIL_CENTRAL5)
     return fail(LBM_EINVAL, "grad_stencil must be LBM_STENCIL_ISO9 or LBM_STENCIL_CENTRAL5");
-  if (p->schedule != LBM_SCHED_FUSED && p->schedule != LBM_SCHED_AA)
-    return fail(LBM_EINVAL, "schedule must be LBM_SCHED_FUSED or LBM_SCHED_AA");
+  if (p->schedule != LBM_SCHED_FUSED && p->schedule != LBM_SCHED_AA && p->schedule != LBM_SCHED_AA_LAGGED)
+    return fail(LBM_EINVAL, "schedule must be LBM_SCHED_FUSED, LBM_SCHED_AA or LBM_SCHED_AA_LAGGED");
   if (p->closure != LBM_CLOSURE_ANALYTIC && p->closure != LBM_CLOSURE_LEARNED)
     return fail(LBM_EINVAL, "closure must be LBM_CLOSURE_ANALYTIC or LBM_CLOSURE_LEARNED");
   if (p->closure == LBM_CLOSURE_LEARNED && p->schedule != LBM_SCHED_FUSED)
@@ -148,6 +149,7 @@ int lbm_init_kh_jet(lbm_ctx* ctx, const lbm_kh_params* kh) {
   if (e != hipSuccess) return hip_fail(e, "lbm_init_kh_jet");
   ctx->t = 0;
   ctx->initialized = true;
+  ctx->lag_ready = false;
   return LBM_OK;
 }
 
@@ -160,6 +162,7 @@ int lbm_init_from_moments(lbm_ctx* ctx, const double* mom_dev, int64_t t) {
   if (e != hipSuccess) return hip_fail(e, "lbm_init_from_moments");
   ctx->t = t;
   ctx->initialized = true;
+  ctx->lag_ready = false;
   return LBM_OK;
 }
 
@@ -169,6 +172,11 @@ int lbm_step(lbm_ctx* ctx, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   if (ctx->L.learned && !ctx->mlp_set)
     return fail(LBM_ESTATE, "learned closure: install a network with lbm_set_closure_mlp first");
+  if (n > 0 && ctx->L.schedule == LBM_SCHED_AA_LAGGED && ctx->L.k2 != 0.0 && !ctx->lag_ready) {
+    hipError_t e = lbm::launch_lag_prime(ctx->L, ctx->t);
+    if (e != hipSuccess) return hip_fail(e, "lbm_step");
+    ctx->lag_ready = true;
+  }
   for (int64_t k = 0; k < n; ++k) {
     hipError_t e = lbm::launch_step(ctx->L, ctx->t);
     if (e != hipSuccess) return hip_fail(e, "lbm_step");
@@ -210,6 +218,7 @@ int lbm_set_state(lbm_ctx* ctx, const double* in_dev, int64_t t) {
   if (e != hipSuccess) return hip_fail(e, "lbm_set_state");
   ctx->t = t;
   ctx->initialized = true;
+  ctx->lag_ready = false;
   return LBM_OK;
 }
 

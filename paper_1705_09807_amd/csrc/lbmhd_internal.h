@@ -30,6 +30,8 @@ struct Launch {
   void* state = nullptr;          // caller-owned population storage
   void* work = nullptr;           // caller-owned work buffer
   size_t off_mb = 0;              // moment planes for the in-place closure sweep
+                                  // (two sets for the lagged schedule, set t & 1
+                                  // holding the moments of step t - 1)
   size_t off_diag = 0;            // 5 FP64 moment planes for the diagnostics
   size_t off_part = 0;            // per-block reduction partials
   size_t off_final = 0;           // final reduction values
@@ -52,6 +54,8 @@ size_t work_layout(Launch& L);
 hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh);
 hipError_t launch_init_moments(const Launch& L, int64_t t, const double* mom);
 hipError_t launch_step(const Launch& L, int64_t t);  // state at time t -> t + 1
+// Lagged schedule: moments of the state at time t into moment set t & 1.
+hipError_t launch_lag_prime(const Launch& L, int64_t t);
 hipError_t launch_get_state(const Launch& L, int64_t t, double* out);
 hipError_t launch_set_state(const Launch& L, int64_t t, const double* in);
 hipError_t launch_moments(const Launch& L, int64_t t, double* out, bool mark_nonfinite);

@@ -560,6 +560,56 @@ k_aa_les(S* __restrict__ A, const C* __restrict__ mb, int nx, int ny, int64_t pl
   aa_store<S, C, ODD>(A, plane, nx, x, xe, xw, y, yn, ys, v);
 }
 
+// Single-sweep in-place closure schedule (lagged gradients): the 66 x 6 halo
+// tile of the previous step's moment planes mb_prev is staged in LDS for the
+// gradient stencil, while the cell's own moments go to mb_next for the next
+// step.  19 + 4 values read, 19 + 4 written per cell.
+template <typename S, typename C, bool ODD, int STENCIL>
+__global__ void __launch_bounds__(256)
+k_aa_les_lagged(S* __restrict__ A, const C* __restrict__ mb_prev, C* __restrict__ mb_next, int nx, int ny,
+                int64_t plane, Rates<C> r) {
+  __shared__ C tile[4][6][66];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int bx0 = blockIdx.x * 64, by0 = blockIdx.y * 4;
+  const int64_t n = (int64_t)nx * ny;
+  for (int idx = ty * 64 + tx; idx < 6 * 66; idx += 256) {
+    const int ly = idx / 66, lx = idx % 66;
+    int gx = (bx0 + lx - 1) % nx;
+    if (gx < 0) gx += nx;
+    int gy = (by0 + ly - 1) % ny;
+    if (gy < 0) gy += ny;
+    const int64_t c = (int64_t)gy * nx + gx;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tile[k][ly][lx] = mb_prev[k * n + c];
+  }
+  __syncthreads();
+  const int x = bx0 + tx, y = by0 + ty;
+  if (x >= nx || y >= ny) return;
+  const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+  const int yn = y + 1 == ny ? 0 : y + 1, ys = y == 0 ? ny - 1 : y - 1;
+  C v[kQ];
+  aa_load<S, C, ODD>(A, plane, nx, x, xe, xw, y, yn, ys, v);
+  const Mom<C> m = moments19(v);
+  const int64_t c0 = (int64_t)y * nx + x;
+  mb_next[c0] = m.mx;
+  mb_next[n + c0] = m.my;
+  mb_next[2 * n + c0] = m.dbx;
+  mb_next[3 * n + c0] = m.dby;
+  const int lx = tx + 1, ly = ty + 1;
+  C gr[4][2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    grad3x3<C, STENCIL>(tile[k][ly][lx + 1], tile[k][ly][lx - 1], tile[k][ly + 1][lx], tile[k][ly - 1][lx],
+                        tile[k][ly + 1][lx + 1], tile[k][ly + 1][lx - 1], tile[k][ly - 1][lx + 1],
+                        tile[k][ly - 1][lx - 1], gr[k][0], gr[k][1]);
+  }
+  const C ir = C(1) / (r.rho0 + m.drho);
+  const Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
+                                      gr[3][1], ir, r.k2);
+  collide19(v, m, cl, r);
+  aa_store<S, C, ODD>(A, plane, nx, x, xe, xw, y, yn, ys, v);
+}
+
 // ---------------------------------------------------------------------------
 // Natural-layout access for initial state, state IO, moments and diagnostics.
 // `base` is the buffer holding the state at time t and `layout` says where
@@ -843,6 +893,7 @@ size_t work_layout(Launch& L) {
   size_t off = 0;
   L.off_mb = off;
   if (L.schedule == LBM_SCHED_AA) off += align256(4 * n * cbytes);
+  if (L.schedule == LBM_SCHED_AA_LAGGED) off += 2 * align256(4 * n * cbytes);
   L.off_diag = off;
   off += align256(5 * n * sizeof(double));
   const int64_t want = ((int64_t)n + 255) / 256;
@@ -877,6 +928,14 @@ static RestRef rest_ref(const Launch& L) { return RestRef{L.rho0, L.bref[0], L.b
 static int layout_at(const Launch& L, int64_t t) {
   if (L.schedule == LBM_SCHED_FUSED) return kLayoutPull;
   return (t & 1) ? kLayoutAAOdd : kLayoutNatural;
+}
+
+// Moment set k (0 or 1) of the lagged schedule.
+template <typename C>
+static C* moment_set(const Launch& L, int k) {
+  const size_t n = (size_t)L.nx * (size_t)L.ny;
+  const size_t stride = (4 * n * sizeof(C) + 255) / 256 * 256;
+  return reinterpret_cast<C*>(static_cast<char*>(L.work) + L.off_mb + (size_t)k * stride);
 }
 
 // Rows per workgroup of the fused closure kernel: long strips (the two halo
@@ -986,6 +1045,26 @@ static hipError_t step_typed(const Launch& L, int64_t t) {
   }
   S* A = static_cast<S*>(L.state);
   const bool odd = t & 1;
+  if (les && L.schedule == LBM_SCHED_AA_LAGGED) {
+    const C* prev = moment_set<C>(L, int(t & 1));
+    C* next = moment_set<C>(L, int((t + 1) & 1));
+    if (L.stencil == LBM_STENCIL_ISO9) {
+      if (odd)
+        hipLaunchKernelGGL((k_aa_les_lagged<S, C, true, LBM_STENCIL_ISO9>), grid, kTile, 0, L.stream, A, prev, next,
+                           L.nx, L.ny, L.plane, r);
+      else
+        hipLaunchKernelGGL((k_aa_les_lagged<S, C, false, LBM_STENCIL_ISO9>), grid, kTile, 0, L.stream, A, prev, next,
+                           L.nx, L.ny, L.plane, r);
+    } else {
+      if (odd)
+        hipLaunchKernelGGL((k_aa_les_lagged<S, C, true, LBM_STENCIL_CENTRAL5>), grid, kTile, 0, L.stream, A, prev,
+                           next, L.nx, L.ny, L.plane, r);
+      else
+        hipLaunchKernelGGL((k_aa_les_lagged<S, C, false, LBM_STENCIL_CENTRAL5>), grid, kTile, 0, L.stream, A, prev,
+                           next, L.nx, L.ny, L.plane, r);
+    }
+    return hipGetLastError();
+  }
   if (!les) {
     if (odd)
       hipLaunchKernelGGL((k_aa_dns<S, C, true>), grid, kTile, 0, L.stream, A, L.nx, L.ny, L.plane, r);
@@ -1016,6 +1095,29 @@ static hipError_t step_typed(const Launch& L, int64_t t) {
                          L.ny, L.plane, r);
   }
   return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t lag_prime_typed(const Launch& L, int64_t t) {
+  using C = typename ComputeOf<S>::type;
+  S* A = static_cast<S*>(L.state);
+  C* mb = moment_set<C>(L, int(t & 1));
+  if (t & 1)
+    hipLaunchKernelGGL((k_aa_moments<S, C, true>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, A, mb, L.nx, L.ny,
+                       L.plane);
+  else
+    hipLaunchKernelGGL((k_aa_moments<S, C, false>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, A, mb, L.nx, L.ny,
+                       L.plane);
+  return hipGetLastError();
+}
+
+hipError_t launch_lag_prime(const Launch& L, int64_t t) {
+  switch (L.dtype) {
+    case LBM_FP64: return lag_prime_typed<double>(L, t);
+    case LBM_FP32: return lag_prime_typed<float>(L, t);
+    case LBM_FP16: return lag_prime_typed<_Float16>(L, t);
+    default: return lag_prime_typed<__bf16>(L, t);
+  }
 }
 
 hipError_t launch_step(const Launch& L, int64_t t) {

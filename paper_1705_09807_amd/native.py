@@ -32,6 +32,7 @@ LBM_STENCIL_ISO9 = 0
 LBM_STENCIL_CENTRAL5 = 1
 LBM_SCHED_FUSED = 0
 LBM_SCHED_AA = 1
+LBM_SCHED_AA_LAGGED = 2
 LBM_CLOSURE_ANALYTIC = 0
 LBM_CLOSURE_LEARNED = 1
 

@@ -52,6 +52,9 @@ def test_buffer_sizes(lib):
     assert lib.lbm_state_bytes(ctypes.byref(p)) == 19 * n_plane * 4
     w = lib.lbm_work_bytes(ctypes.byref(p))
     assert w >= 4 * 64 * 48 * 4 + 5 * 64 * 48 * 8
+    p.schedule = N.LBM_SCHED_AA_LAGGED
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 19 * n_plane * 4
+    assert lib.lbm_work_bytes(ctypes.byref(p)) >= w + 4 * 64 * 48 * 4   # two sets of moment planes
     p.schedule = N.LBM_SCHED_FUSED
     assert lib.lbm_work_bytes(ctypes.byref(p)) < w  # no moment planes without the in-place closure sweep
 
@@ -59,7 +62,8 @@ def test_buffer_sizes(lib):
 @pytest.mark.parametrize("field,value", [
     ("nx", 3), ("ny", 0), ("nx", 40000), ("nu", 0.0), ("nu", -1e-3), ("eta", float("nan")),
     ("s5", 2.0), ("s8", float("inf")), ("delta", -1.0), ("closure_scale", float("nan")),
-    ("grad_stencil", 2), ("dtype", 7), ("schedule", 3), ("closure", 2), ("closure", -1), ("rho0", 0.0),
+    ("grad_stencil", 2), ("dtype", 7), ("schedule", 3), ("schedule", -1), ("closure", 2), ("closure", -1),
+    ("rho0", 0.0),
     ("bref_x", float("nan")), ("bref_y", float("inf")),
 ])
 def test_invalid_params_rejected(lib, field, value):
