@@ -169,6 +169,54 @@ GRADIENTS = {"iso9": grad_iso9, "central5": grad_central}
 # ---------------------------------------------------------------------------
 
 
+def closure_terms_from_gradients(rho, gm, gb, k2: float):
+    """The P, Q, R dictionaries of ``closure_terms`` from given gradients
+    gm[a][b] = D_b m_a and gb[a][b] = D_b B_a."""
+    P, Q, R = {}, {}, {}
+    for a in range(2):
+        for c in range(2):
+            P[a, c] = k2 / rho * (gm[a][0] * gm[c][0] + gm[a][1] * gm[c][1])
+            Q[a, c] = k2 * (gb[a][0] * gb[c][0] + gb[a][1] * gb[c][1])
+            R[a, c] = k2 / rho * (gm[a][0] * gb[c][0] + gm[a][1] * gb[c][1])
+    return P, Q, R
+
+
+def local_gradients(f, g, rates, s_m: float, stencil: str = "iso9"):
+    """Closure gradients from local non-equilibrium moments, with a stencil
+    only for the vorticity (Sec. 3 notes that D2Q9 cannot give every
+    derivative locally).  First-order Chapman-Enskog for the pre-collision
+    populations, f^neq = -(1/s) (d_t + c.grad) f^eq:
+      * M3 - M3^eq = -(2 rho / (3 s3)) S_xy and M4 - M4^eq = -(2 rho / (3 s4))
+        (S_xx - S_yy), S the strain rate of u, with the unfiltered equilibria
+        of ``KinMomentEq``; incompressibility closes S_xx = -S_yy;
+      * Lam_ba - Lam^eq_ba = -(1 / (3 s_m)) D_b B_a (the O(Ma^2) time derivative
+        of Lam^eq dropped), Lam_ba = sum_i c_ib g_ia, Lam^eq_ba = u_b B_a - B_b u_a;
+      * the vorticity w_m = D_x m_y - D_y m_x from the stencil;
+    and D m = rho D u (density gradients dropped, as in Sec. 3).  Returns
+    (gm, gb) with gm[a][b] = D_b m_a, gb[a][b] = D_b B_a."""
+    rho = f.sum(axis=0)
+    mx = np.tensordot(CX.astype(np.float64), f, axes=(0, 0))
+    my = np.tensordot(CY.astype(np.float64), f, axes=(0, 0))
+    Bx = g[:, 0].sum(axis=0)
+    By = g[:, 1].sum(axis=0)
+    M = np.tensordot(T, f, axes=(1, 0))
+    m3eq = mx * my / rho - Bx * By
+    m4eq = (mx * mx - my * my) / rho - Bx * Bx + By * By
+    sxy = -1.5 * rates[3] / rho * (M[3] - m3eq)
+    sd = -1.5 * rates[4] / rho * (M[4] - m4eq)
+    sxx, syy = 0.5 * sd, -0.5 * sd
+    grad = GRADIENTS[stencil]
+    dmx, dmy = grad(mx), grad(my)
+    wm = dmy[0] - dmx[1]
+    gm = [(rho * sxx, rho * sxy - 0.5 * wm), (rho * sxy + 0.5 * wm, rho * syy)]
+    c = (CX[:5].astype(np.float64), CY[:5].astype(np.float64))
+    lam = [[np.tensordot(c[b], g[:, a], axes=(0, 0)) for a in range(2)] for b in range(2)]   # lam[b][a]
+    ux, uy = mx / rho, my / rho
+    lam_eq = [[np.zeros_like(rho), ux * By - Bx * uy], [uy * Bx - By * ux, np.zeros_like(rho)]]
+    gb = [[-3.0 * s_m * (lam[b][a] - lam_eq[b][a]) for b in range(2)] for a in range(2)]
+    return gm, gb
+
+
 def closure_terms(rho, mx, my, Bx, By, k2: float, stencil: str = "iso9"):
     """Delta^2 corrections of the nonlinear equilibrium products.
 
@@ -185,13 +233,7 @@ def closure_terms(rho, mx, my, Bx, By, k2: float, stencil: str = "iso9"):
     grad = GRADIENTS[stencil]
     gm = [grad(mx), grad(my)]       # gm[a][b] = D_b m_a
     gb = [grad(Bx), grad(By)]       # gb[a][b] = D_b B_a
-    P, Q, R = {}, {}, {}
-    for a in range(2):
-        for c in range(2):
-            P[a, c] = k2 / rho * (gm[a][0] * gm[c][0] + gm[a][1] * gm[c][1])
-            Q[a, c] = k2 * (gb[a][0] * gb[c][0] + gb[a][1] * gb[c][1])
-            R[a, c] = k2 / rho * (gm[a][0] * gb[c][0] + gm[a][1] * gb[c][1])
-    return P, Q, R
+    return closure_terms_from_gradients(rho, gm, gb, k2)
 
 
 def filtered_equilibrium_moments(rho, mx, my, Bx, By, P, Q) -> np.ndarray:
@@ -339,6 +381,14 @@ class Oracle:
         # of the closure is always the current density.
         if closure_time not in ("sync", "lagged"):
             raise ValueError("closure_time must be 'sync' or 'lagged'")
+        # grad_stencil "local_iso9" / "local_central5": strain and grad B from
+        # local non-equilibrium moments, vorticity from the named stencil
+        self.local = grad_stencil.startswith("local_")
+        self.stencil = grad_stencil[6:] if self.local else grad_stencil
+        if self.stencil not in GRADIENTS:
+            raise ValueError("unknown gradient stencil")
+        if self.local and closure_time != "sync":
+            raise ValueError("local gradients are taken from the current populations (closure_time='sync')")
         self.closure_time = closure_time
         self._prev = None
         self.f = np.zeros((9, self.ny, self.nx))
@@ -394,8 +444,12 @@ class Oracle:
         contribute nothing.  `grad_fields` (m_x, m_y, B_x, B_y), when given,
         are the fields the closure differentiates instead of the current ones."""
         rho, mx, my, Bx, By = self._moments(f, g)
-        gm = (mx, my, Bx, By) if grad_fields is None else grad_fields
-        P, Q, R = closure_terms(rho, gm[0], gm[1], gm[2], gm[3], self.k2, self.grad_stencil)
+        if self.local:
+            gm_loc, gb_loc = local_gradients(f, g, self.rates, self.s_m, self.stencil)
+            P, Q, R = closure_terms_from_gradients(rho, gm_loc, gb_loc, self.k2)
+        else:
+            gm = (mx, my, Bx, By) if grad_fields is None else grad_fields
+            P, Q, R = closure_terms(rho, gm[0], gm[1], gm[2], gm[3], self.k2, self.stencil)
         meq = filtered_equilibrium_moments(rho, mx, my, Bx, By, P, Q)
         lam = filtered_induction(rho, mx, my, Bx, By, R)
         if self.closure_correction is not None:

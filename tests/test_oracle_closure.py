@@ -186,3 +186,70 @@ def test_lagged_uses_the_previous_moments():
     fs, gs = s.collide(f1, g1, grad_fields=O.Oracle._moments(f0, g0)[1:])
     f2, g2 = O.Oracle.stream(fs, gs)
     assert np.array_equal(f2, lag.f) and np.array_equal(g2, lag.g)
+
+
+# ---------------------------------------------------------------------------
+# Closure gradients from local non-equilibrium moments (vorticity by stencil)
+# ---------------------------------------------------------------------------
+
+
+def _solenoidal_state(n=64):
+    """rho = 1 and divergence-free m and B from stream/flux functions."""
+    y, x = np.mgrid[0:n, 0:n]
+    q = 2 * np.pi / n
+    mx = 0.02 * np.cos(q * y) - 0.01 * np.sin(q * (x + y))
+    my = 0.01 * np.sin(q * (x + y)) - 0.015 * np.cos(q * x)
+    bx = 0.01 + 0.01 * np.cos(q * y) + 0.005 * np.cos(q * (x - y))
+    by = 0.005 * np.cos(q * (x - y))
+    rho = np.ones((n, n))
+    return O.f_equilibrium(rho, mx, my, bx, by), O.g_equilibrium(rho, mx, my, bx, by)
+
+
+@pytest.mark.parametrize("nu", [0.02, 0.05])
+def test_local_gradients_match_spectral_derivatives(nu):
+    """After the non-equilibrium parts have formed (60 steps of a smooth,
+    divergence-free flow), the gradients read off M3, M4 (strain), the g
+    first moments (grad B) and the stencil vorticity equal the exact
+    derivatives to first-order Chapman-Enskog accuracy: a wrong rate factor,
+    sign or index shows up as an O(1) error."""
+    n = 64
+    o = O.Oracle(n, n, nu, nu)
+    o.set_state(*_solenoidal_state(n))
+    o.step(60)
+    f, g, _ = o.state()
+    gm, gb = O.local_gradients(f, g, o.rates, o.s_m, "iso9")
+    _, mx, my, bx, by = o.moments()
+    k = 2 * np.pi * np.fft.fftfreq(n)
+
+    def d(a):
+        A = np.fft.fft2(a)
+        return np.real(np.fft.ifft2(1j * k[None, :] * A)), np.real(np.fft.ifft2(1j * k[:, None] * A))
+
+    em = [d(mx), d(my)]
+    eb = [d(bx), d(by)]
+    scale_m = max(np.abs(em[a][b]).max() for a in range(2) for b in range(2))
+    scale_b = max(np.abs(eb[a][b]).max() for a in range(2) for b in range(2))
+    for a in range(2):
+        for b in range(2):
+            assert np.abs(gm[a][b] - em[a][b]).max() < 0.03 * scale_m, (a, b)
+            assert np.abs(gb[a][b] - eb[a][b]).max() < 0.005 * scale_b, (a, b)
+
+
+def test_local_gradient_les_step_conserves_and_is_close_to_the_stencil_les():
+    n = 48
+    f, g = _solenoidal_state(n)
+    runs = {}
+    for st, d in (("iso9", 3.0), ("local_iso9", 3.0), ("iso9", 0.0)):
+        o = O.Oracle(n, n, 0.02, 0.02, delta=d, grad_stencil=st)
+        o.set_state(f, g)
+        o.step(30)
+        runs[(st, d)] = o
+    loc = runs[("local_iso9", 3.0)]
+    m0 = [a.sum() for a in O.Oracle._moments(f, g)]
+    m1 = [a.sum() for a in loc.moments()]
+    assert all(abs(a - b) <= 1e-12 * max(1.0, abs(a)) for a, b in zip(m0, m1))
+    d_loc = np.linalg.norm(loc.f - runs[("iso9", 3.0)].f)
+    d_closure = np.linalg.norm(runs[("iso9", 3.0)].f - runs[("iso9", 0.0)].f)
+    assert 0 < d_loc < 0.1 * d_closure
+    with pytest.raises(ValueError):
+        O.Oracle(n, n, 0.02, 0.02, delta=3.0, grad_stencil="local_iso9", closure_time="lagged")
