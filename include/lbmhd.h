@@ -59,9 +59,16 @@ extern "C" {
 #define LBM_FP16 2
 #define LBM_BF16 3
 
-/* Discrete gradient used by the closure. */
+/* Gradients used by the closure.  The LOCAL variants (fused and synchronous
+ * in-place schedules) take the strain rate from the non-equilibrium parts of
+ * M3 and M4 and grad B from those of the first moments of g (first-order
+ * Chapman-Enskog of the pre-collision populations, divergence-free strain),
+ * and use the named stencil only for the vorticity D_x m_y - D_y m_x
+ * (Sec. 3: not every derivative is available locally on D2Q9). */
 #define LBM_STENCIL_ISO9 0      /* (a_E-a_W)/3 + (a_NE+a_SE-a_NW-a_SW)/12 */
 #define LBM_STENCIL_CENTRAL5 1  /* (a_E-a_W)/2                             */
+#define LBM_STENCIL_LOCAL_ISO9 2
+#define LBM_STENCIL_LOCAL_CENTRAL5 3
 
 /* Memory schedule of the timestep. */
 #define LBM_SCHED_FUSED 0  /* two population buffers, one fused sweep per step */

@@ -56,8 +56,10 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
   }
   if (!std::isfinite(p->delta) || p->delta < 0.0) return fail(LBM_EINVAL, "delta must be finite and >= 0");
   if (!std::isfinite(p->closure_scale)) return fail(LBM_EINVAL, "closure_scale must be finite");
-  if (p->grad_stencil != LBM_STENCIL_ISO9 && p->grad_stencil != LBM_STENCIL_CENTRAL5)
-    return fail(LBM_EINVAL, "grad_stencil must be LBM_STENCIL_ISO9 or LBM_STENCIL_CENTRAL5");
+  if (p->grad_stencil < LBM_STENCIL_ISO9 || p->grad_stencil > LBM_STENCIL_LOCAL_CENTRAL5)
+    return fail(LBM_EINVAL, "grad_stencil must be one of LBM_STENCIL_*");
+  if (p->grad_stencil >= LBM_STENCIL_LOCAL_ISO9 && p->schedule == LBM_SCHED_AA_LAGGED)
+    return fail(LBM_EINVAL, "local gradients need the current populations: not with LBM_SCHED_AA_LAGGED");
   if (p->schedule != LBM_SCHED_FUSED && p->schedule != LBM_SCHED_AA && p->schedule != LBM_SCHED_AA_LAGGED)
     return fail(LBM_EINVAL, "schedule must be LBM_SCHED_FUSED, LBM_SCHED_AA or LBM_SCHED_AA_LAGGED");
   if (p->closure != LBM_CLOSURE_ANALYTIC && p->closure != LBM_CLOSURE_LEARNED)

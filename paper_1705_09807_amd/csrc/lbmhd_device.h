@@ -47,7 +47,7 @@ __device__ __forceinline__ Closure<C> closure_terms(C gxx, C gxy, C gyx, C gyy, 
 // symmetry), i.e. 3 sum_i w_i c_i a(x + c_i); central5: (a_E - a_W)/2.
 template <typename C, int STENCIL>
 __device__ __forceinline__ void grad3x3(C e, C w, C n, C s, C ne, C nw, C se, C sw, C& dx, C& dy) {
-  if (STENCIL == LBM_STENCIL_ISO9) {
+  if ((STENCIL & 1) == LBM_STENCIL_ISO9) {  // the LOCAL variants use the same two stencils
     const C third = C(1.0 / 3.0), twelfth = C(1.0 / 12.0);
     dx = (e - w) * third + ((ne + se) - (nw + sw)) * twelfth;
     dy = (n - s) * third + ((ne + nw) - (se + sw)) * twelfth;

@@ -207,6 +207,39 @@ __device__ __forceinline__ void collide19(C v[kQ], const Mom<C>& m, const Closur
   }
 }
 
+// Closure gradients from local non-equilibrium moments (LOCAL stencils),
+// with the stencil vorticity wm = D_x m_y - D_y m_x.  First-order
+// Chapman-Enskog of the pre-collision populations: M3 - M3^eq =
+// -(2 rho / (3 s3)) S_xy, M4 - M4^eq = -(2 rho / (3 s4)) (S_xx - S_yy) with the
+// unfiltered equilibria, S_xx = -S_yy (incompressible), D m = rho D u; and
+// D_b B_a = -3 s_m (Lam_ba - Lam^eq_ba), Lam_ba = sum_i c_ib g_ia, Lam^eq_xy =
+// E, Lam^eq_yx = -E.  The stored deviations have the same M3, M4 and Lam
+// (the rest state has none).  gr[k] = (D_x, D_y) of m_x, m_y, B_x, B_y.
+template <typename C>
+__device__ __forceinline__ void local_gradients(const C v[kQ], const Mom<C>& m, const Rates<C>& r, C wm,
+                                                C gr[4][2]) {
+  const C rho = r.rho0 + m.drho;
+  const C ir = C(1) / rho;
+  const C bx = r.bx0 + m.dbx, by = r.by0 + m.dby;
+  const C M3 = (v[5] - v[6]) + (v[7] - v[8]);
+  const C M4 = (v[1] + v[3]) - (v[2] + v[4]);
+  const C e3 = m.mx * m.my * ir - bx * by;
+  const C e4 = (m.mx * m.mx - m.my * m.my) * ir - (bx * bx - by * by);
+  // rho S: s3 = 4 s3q and s4 = 4 s4q exactly
+  const C rsxy = C(-6) * r.s3q * (M3 - e3);
+  const C rsxx = C(-3) * r.s4q * (M4 - e4);
+  gr[0][0] = rsxx;
+  gr[0][1] = rsxy - C(0.5) * wm;
+  gr[1][0] = rsxy + C(0.5) * wm;
+  gr[1][1] = -rsxx;
+  const C E = (m.mx * by - m.my * bx) * ir;
+  const C k = C(-3) * r.sm;
+  gr[2][0] = k * (v[10] - v[12]);
+  gr[2][1] = k * ((v[11] - v[13]) + E);
+  gr[3][0] = k * ((v[15] - v[17]) - E);
+  gr[3][1] = k * (v[16] - v[18]);
+}
+
 // ---------------------------------------------------------------------------
 // Fused schedule (two buffers, pull streaming).  A buffer holds the
 // post-collision populations of the previous step at their source cell, so
@@ -423,6 +456,7 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
       }
       const Mom<C> m = moments19(cur);
       const C ir = C(1) / (r.rho0 + m.drho);
+      if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9) local_gradients(cur, m, r, gr[1][0] - gr[0][1], gr);
       Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
                                     gr[3][1], ir, r.k2);
       if constexpr (CORR) {
@@ -554,6 +588,7 @@ k_aa_les(S* __restrict__ A, const C* __restrict__ mb, int nx, int ny, int64_t pl
                         tile[k][ly - 1][lx - 1], gr[k][0], gr[k][1]);
   }
   const C ir = C(1) / (r.rho0 + m.drho);
+  if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9) local_gradients(v, m, r, gr[1][0] - gr[0][1], gr);
   const Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
                                       gr[3][1], ir, r.k2);
   collide19(v, m, cl, r);
@@ -960,12 +995,23 @@ template <typename S, typename C, int W, bool NT, bool CORR>
 static void launch_les_k(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
   const int ry = fused_rows(L.nx, L.ny, W);
   const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
-  if (L.stencil == LBM_STENCIL_ISO9)
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT, CORR>), g, dim3(W + 64), 0, L.stream, src, dst,
-                       L.nx, L.ny, L.plane, ry, r, corr);
-  else
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT, CORR>), g, dim3(W + 64), 0, L.stream, src,
-                       dst, L.nx, L.ny, L.plane, ry, r, corr);
+  switch (L.stencil) {
+    case LBM_STENCIL_ISO9:
+      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT, CORR>), g, dim3(W + 64), 0, L.stream, src, dst,
+                         L.nx, L.ny, L.plane, ry, r, corr);
+      break;
+    case LBM_STENCIL_CENTRAL5:
+      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT, CORR>), g, dim3(W + 64), 0, L.stream, src,
+                         dst, L.nx, L.ny, L.plane, ry, r, corr);
+      break;
+    case LBM_STENCIL_LOCAL_ISO9:
+      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_ISO9, NT, CORR>), g, dim3(W + 64), 0, L.stream, src,
+                         dst, L.nx, L.ny, L.plane, ry, r, corr);
+      break;
+    default:
+      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_CENTRAL5, NT, CORR>), g, dim3(W + 64), 0, L.stream,
+                         src, dst, L.nx, L.ny, L.plane, ry, r, corr);
+  }
 }
 
 template <typename S, typename C, int W, bool NT>
@@ -1019,6 +1065,16 @@ hipError_t launch_correction(const Launch& L, int64_t t, float* out) {
   }
   if (e != hipSuccess) return e;
   return launch_mlp_correct(mom5, static_cast<char*>(L.work) + L.off_mlp, out, L.nx, L.ny, L.stream);
+}
+
+template <typename S, typename C, int STENCIL>
+static void launch_aa_les(const Launch& L, S* A, const C* mb, const Rates<C>& r, bool odd) {
+  if (odd)
+    hipLaunchKernelGGL((k_aa_les<S, C, true, STENCIL>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, A, mb, L.nx, L.ny,
+                       L.plane, r);
+  else
+    hipLaunchKernelGGL((k_aa_les<S, C, false, STENCIL>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, A, mb, L.nx,
+                       L.ny, L.plane, r);
 }
 
 template <typename S>
@@ -1079,20 +1135,11 @@ static hipError_t step_typed(const Launch& L, int64_t t) {
     hipLaunchKernelGGL((k_aa_moments<S, C, false>), grid, kTile, 0, L.stream, A, mb, L.nx, L.ny, L.plane);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (L.stencil == LBM_STENCIL_ISO9) {
-    if (odd)
-      hipLaunchKernelGGL((k_aa_les<S, C, true, LBM_STENCIL_ISO9>), grid, kTile, 0, L.stream, A, mb, L.nx, L.ny,
-                         L.plane, r);
-    else
-      hipLaunchKernelGGL((k_aa_les<S, C, false, LBM_STENCIL_ISO9>), grid, kTile, 0, L.stream, A, mb, L.nx, L.ny,
-                         L.plane, r);
-  } else {
-    if (odd)
-      hipLaunchKernelGGL((k_aa_les<S, C, true, LBM_STENCIL_CENTRAL5>), grid, kTile, 0, L.stream, A, mb, L.nx,
-                         L.ny, L.plane, r);
-    else
-      hipLaunchKernelGGL((k_aa_les<S, C, false, LBM_STENCIL_CENTRAL5>), grid, kTile, 0, L.stream, A, mb, L.nx,
-                         L.ny, L.plane, r);
+  switch (L.stencil) {
+    case LBM_STENCIL_ISO9: launch_aa_les<S, C, LBM_STENCIL_ISO9>(L, A, mb, r, odd); break;
+    case LBM_STENCIL_CENTRAL5: launch_aa_les<S, C, LBM_STENCIL_CENTRAL5>(L, A, mb, r, odd); break;
+    case LBM_STENCIL_LOCAL_ISO9: launch_aa_les<S, C, LBM_STENCIL_LOCAL_ISO9>(L, A, mb, r, odd); break;
+    default: launch_aa_les<S, C, LBM_STENCIL_LOCAL_CENTRAL5>(L, A, mb, r, odd);
   }
   return hipGetLastError();
 }

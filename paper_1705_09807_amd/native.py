@@ -30,6 +30,8 @@ LBM_FP16 = 2
 LBM_BF16 = 3
 LBM_STENCIL_ISO9 = 0
 LBM_STENCIL_CENTRAL5 = 1
+LBM_STENCIL_LOCAL_ISO9 = 2
+LBM_STENCIL_LOCAL_CENTRAL5 = 3
 LBM_SCHED_FUSED = 0
 LBM_SCHED_AA = 1
 LBM_SCHED_AA_LAGGED = 2

@@ -11,7 +11,8 @@ import ctypes
 from . import native as N
 
 _DTYPES = {"fp64": N.LBM_FP64, "fp32": N.LBM_FP32, "fp16": N.LBM_FP16, "bf16": N.LBM_BF16}
-_STENCILS = {"iso9": N.LBM_STENCIL_ISO9, "central5": N.LBM_STENCIL_CENTRAL5}
+_STENCILS = {"iso9": N.LBM_STENCIL_ISO9, "central5": N.LBM_STENCIL_CENTRAL5,
+             "local_iso9": N.LBM_STENCIL_LOCAL_ISO9, "local_central5": N.LBM_STENCIL_LOCAL_CENTRAL5}
 _SCHEDULES = {"fused": N.LBM_SCHED_FUSED, "aa": N.LBM_SCHED_AA, "aa_lagged": N.LBM_SCHED_AA_LAGGED}
 _CLOSURES = {"analytic": N.LBM_CLOSURE_ANALYTIC, "learned": N.LBM_CLOSURE_LEARNED}
 

@@ -62,7 +62,8 @@ def test_buffer_sizes(lib):
 @pytest.mark.parametrize("field,value", [
     ("nx", 3), ("ny", 0), ("nx", 40000), ("nu", 0.0), ("nu", -1e-3), ("eta", float("nan")),
     ("s5", 2.0), ("s8", float("inf")), ("delta", -1.0), ("closure_scale", float("nan")),
-    ("grad_stencil", 2), ("dtype", 7), ("schedule", 3), ("schedule", -1), ("closure", 2), ("closure", -1),
+    ("grad_stencil", 4), ("grad_stencil", -1), ("dtype", 7), ("schedule", 3), ("schedule", -1), ("closure", 2),
+    ("closure", -1),
     ("rho0", 0.0),
     ("bref_x", float("nan")), ("bref_y", float("inf")),
 ])
@@ -115,6 +116,13 @@ def test_strerror(lib):
     for code in (N.LBM_OK, N.LBM_EINVAL, N.LBM_ESTATE, N.LBM_EHIP, N.LBM_ENONFINITE):
         assert len(lib.lbm_strerror(code)) > 0
     assert lib.lbm_strerror(12345) == b"unknown error"
+
+
+def test_local_gradients_not_with_the_lagged_schedule(lib):
+    ok = _params(grad_stencil=N.LBM_STENCIL_LOCAL_ISO9, schedule=N.LBM_SCHED_AA)
+    assert lib.lbm_work_bytes(ctypes.byref(ok)) > 0
+    bad = _params(grad_stencil=N.LBM_STENCIL_LOCAL_CENTRAL5, schedule=N.LBM_SCHED_AA_LAGGED)
+    assert lib.lbm_work_bytes(ctypes.byref(bad)) == 0
 
 
 def test_learned_closure_params_and_call_order(lib):
