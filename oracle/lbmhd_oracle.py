@@ -343,6 +343,27 @@ def kh_jet_populations(x, y, nx, ny, U0=0.05, delta_over_L=0.05, B0=0.01, rho0=1
             g_equilibrium(rho, rho * ux, rho * uy, bx, by))
 
 
+def sech2_jet_populations(x, y, nx, ny, U0=4.88e-2, B0=0.005 * 4.88e-2, pert=0.01, k=4, rho0=1.0):
+    """The magnetized Kelvin-Helmholtz jet of Sec. 4 at integer nodes (x, y):
+    u_y = U0 sech^2(2 pi k d / nx) + pert U0 sin(2 pi k x / nx),
+    u_x = pert U0 sin(2 pi k y / ny),
+    B_x = pert B0 sin(2 pi k y / ny),  B_y = B0 + pert B0 sin(2 pi k x / nx),
+    rho = rho0, with d the periodic distance of x from 0 (the printed profile
+    sech^2(8 pi x / L) centred on x = 0 of the periodic box) and the mean field
+    along the jet.  The paper: k = 4, pert = 0.01, U0 = 4.88e-2, B0 = 0.005 U0,
+    nu = eta = 1e-3 at 1024^2.  Populations are the unfiltered equilibria."""
+    xf = np.asarray(x, dtype=np.float64)
+    yf = np.asarray(y, dtype=np.float64)
+    d = np.minimum(xf, nx - xf)
+    uy = U0 / np.cosh(2.0 * math.pi * k * d / nx) ** 2 + pert * U0 * np.sin(2.0 * math.pi * k * xf / nx)
+    ux = pert * U0 * np.sin(2.0 * math.pi * k * yf / ny)
+    bx = pert * B0 * np.sin(2.0 * math.pi * k * yf / ny)
+    by = B0 + pert * B0 * np.sin(2.0 * math.pi * k * xf / nx)
+    rho = np.full(xf.shape, float(rho0))
+    return (f_equilibrium(rho, rho * ux, rho * uy, bx, by),
+            g_equilibrium(rho, rho * ux, rho * uy, bx, by))
+
+
 # ---------------------------------------------------------------------------
 # The oracle
 # ---------------------------------------------------------------------------
@@ -404,6 +425,15 @@ class Oracle:
         y = np.arange(self.ny, dtype=np.int64)[:, None] * np.ones((1, self.nx), dtype=np.int64)
         self.f, self.g = kh_jet_populations(x, y, self.nx, self.ny, U0, delta_over_L, B0, rho0,
                                             pert_amp_over_U0, noise_amp, seed)
+        self.t = 0
+        self._prev = None
+
+    def init_sech2_jet(self, U0=4.88e-2, B0=0.005 * 4.88e-2, pert=0.01, k=4, rho0=1.0):
+        """The magnetized jet of Sec. 4 on the whole grid at t = 0 (see
+        ``sech2_jet_populations``)."""
+        x = np.arange(self.nx, dtype=np.int64)[None, :] * np.ones((self.ny, 1), dtype=np.int64)
+        y = np.arange(self.ny, dtype=np.int64)[:, None] * np.ones((1, self.nx), dtype=np.int64)
+        self.f, self.g = sech2_jet_populations(x, y, self.nx, self.ny, U0, B0, pert, k, rho0)
         self.t = 0
         self._prev = None
 

@@ -279,3 +279,27 @@ def test_kh_initial_state_fields():
     assert abs(noise[5, 7] - expect) < 1e-16
     # the profile is periodic in y to round-off level relative to U0
     assert abs(ux[0, 0] - U0 * (np.tanh((ny - ny / 4) / d) - np.tanh((ny - 3 * ny / 4) / d) - 1)) < 1e-12 * U0
+
+
+def test_sech2_jet_fields():
+    """The jet of Sec. 4: profile, perturbations, Re = U0 L / nu = 50k at 1024^2
+    with nu = 1e-3, solenoidal u and B, and the periodic centring."""
+    n = 64
+    o = O.Oracle(n, n, 1e-3, 1e-3)
+    o.init_sech2_jet()
+    rho, mx, my, bx, by = o.moments()
+    U0, B0 = 4.88e-2, 0.005 * 4.88e-2
+    x = np.arange(n)
+    d = np.minimum(x, n - x)
+    want_uy = U0 / np.cosh(8 * np.pi * d / n) ** 2 + 0.01 * U0 * np.sin(8 * np.pi * x / n)
+    assert np.allclose(my[0] / rho[0], want_uy, rtol=0, atol=1e-15)
+    assert np.allclose(mx[:, 0] / rho[:, 0], 0.01 * U0 * np.sin(8 * np.pi * x / n), rtol=0, atol=1e-15)
+    assert np.allclose(by[0], B0 + 0.01 * B0 * np.sin(8 * np.pi * x / n), rtol=0, atol=1e-17)
+    assert np.allclose(bx[:, 0], 0.01 * B0 * np.sin(8 * np.pi * x / n), rtol=0, atol=1e-17)
+    # u_x depends on y only and u_y on x only: both fields are divergence-free
+    assert np.allclose(mx / rho, (mx / rho)[:, :1]) and np.allclose(my / rho, (my / rho)[:1, :])
+    assert np.allclose(bx, bx[:, :1]) and np.allclose(by, by[:1, :])
+    # symmetric about x = 0 of the periodic box (the sech^2 part)
+    jet = want_uy - 0.01 * U0 * np.sin(8 * np.pi * x / n)
+    assert np.allclose(jet[1:], jet[1:][::-1])
+    assert abs(U0 * 1024 / 1e-3 - 5e4) < 1e3     # Re quoted in Sec. 4
