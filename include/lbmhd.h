@@ -123,6 +123,20 @@ typedef struct {
   uint64_t seed;
 } lbm_kh_params;
 
+/* The magnetized Kelvin-Helmholtz jet of Sec. 4:
+ * u_y = U0 sech^2(2 pi k d / nx) + pert U0 sin(2 pi k x / nx), u_x = pert U0 sin(2 pi k y / ny),
+ * B_x = pert B0 sin(2 pi k y / ny), B_y = B0 + pert B0 sin(2 pi k x / nx), rho = rho0,
+ * with d = min(x, nx - x) (the printed profile sech^2(8 pi x / L) centred on
+ * x = 0 of the periodic box) and the mean field along the jet.  The paper:
+ * U0 = 4.88e-2, B0 = 0.005 U0, pert = 0.01, k = 4, nu = eta = 1e-3 at 1024^2
+ * (Re = U0 L / nu = 50k, scaled with the grid).  Populations start at the
+ * unfiltered equilibria feq / geq. */
+typedef struct {
+  double U0, B0, pert, rho0;
+  int32_t k;               /* >= 1 */
+  int32_t reserved;        /* must be 0 */
+} lbm_sech2_params;
+
 /* Scalar diagnostics, FP64 on the device.  Domain means: e_kin = <|m|^2/(2 rho)>,
  * e_mag = <|B|^2/2>, enstrophy = <w^2/2> with w = D_x u_y - D_y u_x,
  * j2 = <J_z^2> with J_z = D_x B_y - D_y B_x; D = central differences.
@@ -152,6 +166,9 @@ int lbm_create(lbm_ctx** out, const lbm_params* p, void* state_dev, void* work_d
 
 /* Write the Kelvin-Helmholtz initial state (see lbm_kh_params); t = 0. */
 int lbm_init_kh_jet(lbm_ctx* ctx, const lbm_kh_params* kh);
+
+/* Write the magnetized jet of Sec. 4 (see lbm_sech2_params); t = 0. */
+int lbm_init_sech2_jet(lbm_ctx* ctx, const lbm_sech2_params* jet);
 
 /* Replace the state by the unfiltered equilibria feq / geq (Sec. 2) of given
  * fields: mom_dev = 5 FP64 planes rho (> 0), m_x = rho u_x, m_y, B_x, B_y in

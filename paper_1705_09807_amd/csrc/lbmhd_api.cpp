@@ -155,6 +155,23 @@ int lbm_init_kh_jet(lbm_ctx* ctx, const lbm_kh_params* kh) {
   return LBM_OK;
 }
 
+int lbm_init_sech2_jet(lbm_ctx* ctx, const lbm_sech2_params* jet) {
+  int rc = check_ctx(ctx, false);
+  if (rc != LBM_OK) return rc;
+  if (!jet) return fail(LBM_EINVAL, "jet params are NULL");
+  const double vals[4] = {jet->U0, jet->B0, jet->pert, jet->rho0};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(LBM_EINVAL, "jet params must be finite");
+  if (!(jet->rho0 > 0.0) || jet->k < 1 || jet->reserved != 0)
+    return fail(LBM_EINVAL, "rho0 must be > 0, k >= 1 and reserved 0");
+  hipError_t e = lbm::launch_init_sech2(ctx->L, *jet);
+  if (e != hipSuccess) return hip_fail(e, "lbm_init_sech2_jet");
+  ctx->t = 0;
+  ctx->initialized = true;
+  ctx->lag_ready = false;
+  return LBM_OK;
+}
+
 int lbm_init_from_moments(lbm_ctx* ctx, const double* mom_dev, int64_t t) {
   int rc = check_ctx(ctx, false);
   if (rc != LBM_OK) return rc;

@@ -52,6 +52,7 @@ size_t work_layout(Launch& L);
 
 // Launchers: enqueue on L.stream, return the first HIP error.
 hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh);
+hipError_t launch_init_sech2(const Launch& L, const lbm_sech2_params& jet);
 hipError_t launch_init_moments(const Launch& L, int64_t t, const double* mom);
 hipError_t launch_step(const Launch& L, int64_t t);  // state at time t -> t + 1
 // Lagged schedule: moments of the state at time t into moment set t & 1.

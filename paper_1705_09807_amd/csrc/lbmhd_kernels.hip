@@ -724,6 +724,23 @@ k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestR
   write_equilibrium<S>(base, x, y, nx, ny, plane, layout, ref, kh.rho0, ux, uy, kh.B0, 0.0);
 }
 
+// The magnetized jet of Sec. 4 at the unfiltered equilibria.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_init_sech2(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestRef ref, lbm_sech2_params jet) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const double xf = double(x), yf = double(y), d = fmin(xf, double(nx) - xf);
+  const double kx = 2.0 * M_PI * double(jet.k) / double(nx), ky = 2.0 * M_PI * double(jet.k) / double(ny);
+  const double ch = cosh(kx * d);
+  const double uy = jet.U0 / (ch * ch) + jet.pert * jet.U0 * sin(kx * xf);
+  const double ux = jet.pert * jet.U0 * sin(ky * yf);
+  const double bx = jet.pert * jet.B0 * sin(ky * yf);
+  const double by = jet.B0 + jet.pert * jet.B0 * sin(kx * xf);
+  write_equilibrium<S>(base, x, y, nx, ny, plane, layout, ref, jet.rho0, ux, uy, bx, by);
+}
+
 // Equilibria of given fields: 5 FP64 planes rho, m_x, m_y, B_x, B_y.
 template <typename S>
 __global__ void __launch_bounds__(256)
@@ -1189,6 +1206,22 @@ hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh) {
     case LBM_FP32: return init_typed<float>(L, kh);
     case LBM_FP16: return init_typed<_Float16>(L, kh);
     default: return init_typed<__bf16>(L, kh);
+  }
+}
+
+template <typename S>
+static hipError_t init_sech2_typed(const Launch& L, const lbm_sech2_params& jet) {
+  hipLaunchKernelGGL((k_init_sech2<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, 0), L.nx, L.ny,
+                     L.plane, layout_at(L, 0), rest_ref(L), jet);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_sech2(const Launch& L, const lbm_sech2_params& jet) {
+  switch (L.dtype) {
+    case LBM_FP64: return init_sech2_typed<double>(L, jet);
+    case LBM_FP32: return init_sech2_typed<float>(L, jet);
+    case LBM_FP16: return init_sech2_typed<_Float16>(L, jet);
+    default: return init_sech2_typed<__bf16>(L, jet);
   }
 }
 

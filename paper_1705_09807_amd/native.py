@@ -73,6 +73,13 @@ class LbmKhParams(ctypes.Structure):
     ]
 
 
+class LbmSech2Params(ctypes.Structure):
+    _fields_ = [
+        ("U0", ctypes.c_double), ("B0", ctypes.c_double), ("pert", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("k", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
 class LbmDiag(ctypes.Structure):
     _fields_ = [
         ("t", ctypes.c_int64),
@@ -101,6 +108,7 @@ _SIGNATURES = {
     "lbm_work_bytes": (ctypes.c_size_t, [ctypes.POINTER(LbmParams)]),
     "lbm_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(LbmParams), _P, _P, _P]),
     "lbm_init_kh_jet": (ctypes.c_int, [_P, ctypes.POINTER(LbmKhParams)]),
+    "lbm_init_sech2_jet": (ctypes.c_int, [_P, ctypes.POINTER(LbmSech2Params)]),
     "lbm_init_from_moments": (ctypes.c_int, [_P, _P, ctypes.c_int64]),
     "lbm_step": (ctypes.c_int, [_P, ctypes.c_int64]),
     "lbm_get_time": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
@@ -146,7 +154,7 @@ def header_functions() -> list[str]:
         with open(path) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names.update(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text))
+        names.update(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text))
     return sorted(names)
 
 

@@ -74,6 +74,11 @@ class Sim:
                            pert_amp_over_U0=pert_amp_over_U0, noise_amp=noise_amp, seed=int(seed))
         N.check(self._lib.lbm_init_kh_jet(self._ctx, ctypes.byref(kh)), "lbm_init_kh_jet")
 
+    def init_sech2_jet(self, U0=4.88e-2, B0=0.005 * 4.88e-2, pert=0.01, k=4, rho0=1.0):
+        """The magnetized Kelvin-Helmholtz jet of Sec. 4 (lbm_init_sech2_jet)."""
+        jet = N.LbmSech2Params(U0=U0, B0=B0, pert=pert, rho0=rho0, k=int(k), reserved=0)
+        N.check(self._lib.lbm_init_sech2_jet(self._ctx, ctypes.byref(jet)), "lbm_init_sech2_jet")
+
     def init_from_moments(self, mom, t: int = 0):
         """Equilibrium state of given fields mom [5, ny, nx] float64 (rho, m_x,
         m_y, B_x, B_y; any device), time t."""

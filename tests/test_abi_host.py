@@ -190,3 +190,19 @@ def test_learned_sizes_and_argument_checks(lib):
 
 def test_norm_struct_layout():
     assert ctypes.sizeof(N.LbmMlpNorm) == 128
+
+
+def test_sech2_params(lib):
+    assert ctypes.sizeof(N.LbmSech2Params) == 4 * 8 + 2 * 4
+    p = _params()
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(1 << 20),
+                          ctypes.c_void_p(1 << 21), None) == N.LBM_OK
+    try:
+        assert lib.lbm_init_sech2_jet(ctx, None) == N.LBM_EINVAL
+        for bad in (dict(k=0), dict(rho0=0.0), dict(U0=float("nan")), dict(reserved=1)):
+            kw = dict(U0=0.05, B0=2e-4, pert=0.01, rho0=1.0, k=4, reserved=0)
+            kw.update(bad)
+            assert lib.lbm_init_sech2_jet(ctx, ctypes.byref(N.LbmSech2Params(**kw))) == N.LBM_EINVAL
+    finally:
+        lib.lbm_destroy(ctx)

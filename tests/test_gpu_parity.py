@@ -366,3 +366,24 @@ def test_benchmark_workload_stays_finite():
         assert d["nonfinite"] == 0 and math.isfinite(d["e_kin"])
     assert abs(d["mass"] - d0["mass"]) <= 1e-8 * d0["mass"]
     assert abs(d["e_kin"] - d0["e_kin"]) <= 0.01 * d0["e_kin"]
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_sech2_jet_matches_oracle(dtype):
+    """The paper's magnetized jet (Sec. 4) on 64^2 with Delta = 2: initial
+    state and 200 steps against the oracle (FP64 <= 1e-12, FP32 <= 1e-5)."""
+    n = 64
+    _say("sech2 jet", dtype)
+    U0, B0 = 4.88e-2, 0.005 * 4.88e-2
+    s = _sim(nx=n, ny=n, nu=1e-3 * 64 / 1024, eta=1e-3 * 64 / 1024, delta=2.0, dtype=dtype, b_ref=(0.0, B0))
+    o = O.Oracle(n, n, 1e-3 * 64 / 1024, 1e-3 * 64 / 1024, delta=2.0)
+    s.init_sech2_jet()
+    o.init_sech2_jet()
+    e0 = rel(s.get_state().cpu().numpy(), pack(*o.state()[:2]))
+    assert e0 <= (1e-15 if dtype == "fp64" else 1e-6), e0
+    s.step(200)
+    o.step(200)
+    e = field_errors(s.moments().cpu().numpy(), o.moments())
+    _say("sech2 jet", dtype, "after 200 steps:", e)
+    for key, v in e.items():
+        assert v <= (1e-12 if dtype == "fp64" else 1e-5), (key, v)
