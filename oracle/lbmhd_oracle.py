@@ -27,6 +27,8 @@ Readings of the paper used here (each is also listed in the design notes):
   equilibrium moment with filtered-density gradients dropped, as Sec. 3 does
   for M3; the closure strength is Delta^2/12 times ``closure_scale`` (1 =
   as printed in Sec. 3).
+* ``density_gradients=True`` keeps the filtered-density terms of
+  ``FilterExampleLarge`` (Z = rho) in the Reynolds and induction products.
 * Gradients are synchronous (taken from the current post-streaming moments)
   with a 3x3 isotropic stencil by default; diagnostics use central
   differences.
@@ -236,6 +238,43 @@ def closure_terms(rho, mx, my, Bx, By, k2: float, stencil: str = "iso9"):
     return closure_terms_from_gradients(rho, gm, gb, k2)
 
 
+def closure_terms_full_from_gradients(rho, m, B, gm, gb, grho, k2: float):
+    """``FilterExampleLarge`` with Z = rho, density gradients kept:
+
+        bar(XY/Z) - bar X bar Y / bar Z
+          = Delta^2/(12 Z) [ (d_b X)(d_b Y)
+                             - (d_b Z / Z) (X d_b Y + Y d_b X - X Y d_b Z / Z) ],
+
+    applied to the Reynolds product m_a m_c / rho (P) and the induction
+    product m_a B_c / rho (R); the Maxwell product B_a B_c has no divisor and
+    keeps ``FilterExampleSmall`` (Q).  m = (m_x, m_y), B = (B_x, B_y),
+    gm[a][b] = D_b m_a, gb[a][b] = D_b B_a, grho[b] = D_b rho; k2 = closure
+    strength times Delta^2/12.  Same dictionaries as ``closure_terms``."""
+    P, Q, R = {}, {}, {}
+    for a in range(2):
+        for c in range(2):
+            pp = np.zeros_like(rho)
+            rr = np.zeros_like(rho)
+            qq = np.zeros_like(rho)
+            for b in range(2):
+                lr = grho[b] / rho
+                pp = pp + gm[a][b] * gm[c][b] - lr * (m[a] * gm[c][b] + m[c] * gm[a][b] - m[a] * m[c] * lr)
+                rr = rr + gm[a][b] * gb[c][b] - lr * (m[a] * gb[c][b] + B[c] * gm[a][b] - m[a] * B[c] * lr)
+                qq = qq + gb[a][b] * gb[c][b]
+            P[a, c] = k2 / rho * pp
+            Q[a, c] = k2 * qq
+            R[a, c] = k2 / rho * rr
+    return P, Q, R
+
+
+def closure_terms_full(rho, mx, my, Bx, By, k2: float, stencil: str = "iso9"):
+    """``closure_terms_full_from_gradients`` with every gradient (of m, B and
+    rho) from the named 3x3 stencil."""
+    grad = GRADIENTS[stencil]
+    return closure_terms_full_from_gradients(rho, (mx, my), (Bx, By), [grad(mx), grad(my)], [grad(Bx), grad(By)],
+                                             grad(rho), k2)
+
+
 def filtered_equilibrium_moments(rho, mx, my, Bx, By, P, Q) -> np.ndarray:
     """Filtered M_i^(eq), i = 0..8: the ``KinMomentEq`` table evaluated on the
     filtered invariants (Sec. 2.1, filtered equilibrium moments) plus the
@@ -379,7 +418,8 @@ class Oracle:
 
     def __init__(self, nx: int, ny: int, nu: float, eta: float, delta: float = 0.0,
                  closure_scale: float = 1.0, s5=None, s6=None, s7=None, s8=None,
-                 grad_stencil: str = "iso9", closure_correction=None, closure_time: str = "sync"):
+                 grad_stencil: str = "iso9", closure_correction=None, closure_time: str = "sync",
+                 density_gradients: bool = False):
         if nx < 4 or ny < 4:
             raise ValueError("grid must be at least 4 x 4")
         self.nx, self.ny = int(nx), int(ny)
@@ -411,6 +451,11 @@ class Oracle:
         if self.local and closure_time != "sync":
             raise ValueError("local gradients are taken from the current populations (closure_time='sync')")
         self.closure_time = closure_time
+        # density_gradients: the full ``FilterExampleLarge`` closure (filtered
+        # density gradients kept), synchronous stencil gradients only
+        self.density_gradients = bool(density_gradients)
+        if self.density_gradients and (self.local or closure_time != "sync"):
+            raise ValueError("the density-gradient closure takes synchronous stencil gradients")
         self._prev = None
         self.f = np.zeros((9, self.ny, self.nx))
         self.g = np.zeros((5, 2, self.ny, self.nx))
@@ -477,6 +522,8 @@ class Oracle:
         if self.local:
             gm_loc, gb_loc = local_gradients(f, g, self.rates, self.s_m, self.stencil)
             P, Q, R = closure_terms_from_gradients(rho, gm_loc, gb_loc, self.k2)
+        elif self.density_gradients:
+            P, Q, R = closure_terms_full(rho, mx, my, Bx, By, self.k2, self.stencil)
         else:
             gm = (mx, my, Bx, By) if grad_fields is None else grad_fields
             P, Q, R = closure_terms(rho, gm[0], gm[1], gm[2], gm[3], self.k2, self.stencil)

@@ -253,3 +253,121 @@ def test_local_gradient_les_step_conserves_and_is_close_to_the_stencil_les():
     assert 0 < d_loc < 0.1 * d_closure
     with pytest.raises(ValueError):
         O.Oracle(n, n, 0.02, 0.02, delta=3.0, grad_stencil="local_iso9", closure_time="lagged")
+
+
+# ---------------------------------------------------------------------------
+# The density-gradient closure (FilterExampleLarge with Z = rho)
+# ---------------------------------------------------------------------------
+
+def _errors_varying_density(delta, full):
+    """Residual ratios (closure vs brute force) / (no closure vs brute force)
+    of the quotient moments M3, M4, M7, M8 and the induction moments, with a
+    density that varies by +-20 %."""
+    rho = RHO + smooth_field(N, N, 9, kmax=2, amp=0.25)
+    mx, my, bx, by = _fields()
+    exact = np.tensordot(O.T, O.f_equilibrium(rho, mx, my, bx, by), axes=(1, 0))
+    exact = np.array([_gauss(exact[k], delta) for k in range(9)])
+    u = (mx / rho, my / rho)
+    b = (bx, by)
+    lam_exact = np.array([[_gauss(u[p] * b[a] - b[p] * u[a], delta) for a in range(2)] for p in range(2)])
+    fr = _gauss(rho, delta)
+    fm = [_gauss(a, delta) for a in (mx, my, bx, by)]
+    k2 = delta * delta / 12.0
+    P, Q, R = (O.closure_terms_full if full else O.closure_terms)(fr, *fm, k2)
+    zero = {(a, c): 0.0 * rho for a in range(2) for c in range(2)}
+    with_c = O.filtered_equilibrium_moments(fr, *fm, P, Q)
+    without = O.filtered_equilibrium_moments(fr, *fm, zero, zero)
+    lam_c = O.filtered_induction(fr, *fm, R)
+    lam_0 = O.filtered_induction(fr, *fm, zero)
+    ratios = {}
+    for k in (3, 4, 7, 8):
+        ratios[k] = np.abs(with_c[k] - exact[k]).max() / np.abs(without[k] - exact[k]).max()
+    for p, a, key in ((0, 1, "lam_xy"), (1, 0, "lam_yx")):
+        ratios[key] = np.abs(lam_c[p, a] - lam_exact[p, a]).max() / np.abs(lam_0[p, a] - lam_exact[p, a]).max()
+    return ratios
+
+
+def test_density_gradient_closure_matches_bruteforce_filter():
+    """With a varying density the full closure leaves an O(Delta^4) residual
+    (ratio to the O(Delta^2) no-closure error grows ~4x per doubling of Delta
+    and is below 1 % at Delta = 4), while the closure with density gradients
+    dropped keeps an O(Delta^2) residual: a dropped or sign-flipped term of
+    the bracket, or X and Y swapped in the induction product, fails."""
+    full4, simple4 = _errors_varying_density(4.0, True), _errors_varying_density(4.0, False)
+    for key, r in full4.items():
+        assert r < 0.01, (key, r)
+        assert simple4[key] > 5 * r, (key, r, simple4[key])
+    f8, f16 = _errors_varying_density(8.0, True), _errors_varying_density(16.0, True)
+    s8 = _errors_varying_density(8.0, False)
+    for key in f8:
+        assert 3.0 < f16[key] / f8[key] < 5.0, (key, f8[key], f16[key])
+        # dropping the density terms leaves a residual of the closure's own order
+        assert 0.7 < s8[key] / simple4[key] < 1.4 and s8[key] > 0.03, (key, simple4[key], s8[key])
+
+
+def test_density_gradient_closure_closed_forms():
+    """Exact derivatives of analytic fields: the bracket of FilterExampleLarge
+    equals Z d(X/Z).d(Y/Z) (quotient rule), and with uniform density the full
+    closure equals the simplified one."""
+    n = 64
+    x = np.arange(n)[None, :] * np.ones((n, 1)) * 2 * np.pi / n
+    y = np.arange(n)[:, None] * np.ones((1, n)) * 2 * np.pi / n
+    rho = 1.2 + 0.3 * np.sin(x + 2 * y)
+    grho = (0.3 * np.cos(x + 2 * y), 0.6 * np.cos(x + 2 * y))
+    m = (0.1 * np.cos(2 * x) * np.sin(y), 0.05 * np.sin(x - y))
+    gm = [(-0.2 * np.sin(2 * x) * np.sin(y), 0.1 * np.cos(2 * x) * np.cos(y)),
+          (0.05 * np.cos(x - y), -0.05 * np.cos(x - y))]
+    B = (0.02 + 0.01 * np.sin(3 * y), 0.03 * np.cos(x))
+    gb = [(0 * x, 0.03 * np.cos(3 * y)), (-0.03 * np.sin(x), 0 * x)]
+    k2 = 0.7
+    P, Q, R = O.closure_terms_full_from_gradients(rho, m, B, gm, gb, grho, k2)
+
+    def dq(a, ga):   # gradient of a / rho
+        return [(ga[b] - a * grho[b] / rho) / rho for b in range(2)]
+
+    for a in range(2):
+        for c in range(2):
+            pa, pc, bc = dq(m[a], gm[a]), dq(m[c], gm[c]), dq(B[c], gb[c])
+            assert np.allclose(P[a, c], k2 * rho * (pa[0] * pc[0] + pa[1] * pc[1]), rtol=1e-12, atol=1e-18)
+            assert np.allclose(R[a, c], k2 * rho * (pa[0] * bc[0] + pa[1] * bc[1]), rtol=1e-12, atol=1e-18)
+            assert np.allclose(Q[a, c], k2 * (gb[a][0] * gb[c][0] + gb[a][1] * gb[c][1]), rtol=1e-14, atol=0)
+    flat = np.full((n, n), 1.3)
+    P1, Q1, R1 = O.closure_terms_full(flat, m[0], m[1], B[0], B[1], k2)
+    P0, Q0, R0 = O.closure_terms(flat, m[0], m[1], B[0], B[1], k2)
+    for key in P0:
+        assert np.array_equal(Q1[key], Q0[key])
+        assert np.allclose(P1[key], P0[key], rtol=1e-14, atol=1e-20)
+        assert np.allclose(R1[key], R0[key], rtol=1e-14, atol=1e-20)
+
+
+def test_density_gradient_oracle_step():
+    """A step of the density-gradient oracle: uniform density gives the
+    simplified closure's step, varying density a different one that still
+    conserves mass and momentum; local or lagged gradients are rejected."""
+    nx, ny = 24, 16
+    f = O.f_equilibrium(np.full((ny, nx), 1.0), 0.02 + 0.01 * smooth_field(nx, ny, 3),
+                        0.01 * smooth_field(nx, ny, 4), 0.01 + 0 * smooth_field(nx, ny, 5),
+                        0.01 * smooth_field(nx, ny, 6))
+    g = offset_noise(np.zeros(10), (10, ny, nx), 7, 1e-3).reshape(5, 2, ny, nx) + \
+        np.repeat(O.W5[:, None, None, None] * 0.01, 2, axis=1)
+    runs = {}
+    for full in (False, True):
+        o = O.Oracle(nx, ny, 0.01, 0.02, delta=3.0, density_gradients=full)
+        o.set_state(f, g)
+        o.step(1)
+        runs[full] = o.state()
+    assert np.allclose(runs[True][0], runs[False][0], rtol=0, atol=1e-16)
+    fv = perturbed(O.W9, (9, ny, nx), 8, 0.1)
+    runs = {}
+    for full in (False, True):
+        o = O.Oracle(nx, ny, 0.01, 0.02, delta=3.0, density_gradients=full)
+        o.set_state(fv, g)
+        m0 = [a.sum() for a in o.moments()[:3]]
+        o.step(3)
+        m1 = [a.sum() for a in o.moments()[:3]]
+        assert np.allclose(m0, m1, rtol=1e-13, atol=1e-13)
+        runs[full] = o.state()
+    assert np.abs(runs[True][0] - runs[False][0]).max() > 1e-9
+    for kw in (dict(grad_stencil="local_iso9"), dict(closure_time="lagged")):
+        with pytest.raises(ValueError):
+            O.Oracle(nx, ny, 0.01, 0.02, delta=3.0, density_gradients=True, **kw)
