@@ -463,6 +463,25 @@ def main() -> int:
                             "kernel": "k_fused_les<float> (plain closure, Delta=4)"}
         log(f"les 4096^2: {ms * 1e3:.1f} us/step, {bw:.0f} GB/s algorithmic")
         del big
+        # closure variants of the same fused sweep (same 152 B per update):
+        # filtered-density gradient terms kept, and gradients from local
+        # non-equilibrium moments
+        for key, kw in (("les4096_full", dict(closure="full")), ("les4096_local_iso9", dict(grad_stencil="local_iso9"))):
+            sv = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype="fp32", schedule="fused",
+                     b_ref=bref, device=dev, stream=stream, **ghost, **kw)
+            sv.init_kh_jet(seed=0, **KH)
+            sv.step(20)
+            a, b = ev(), ev()
+            a.record(stream)
+            sv.step(args.les4096_steps)
+            b.record(stream)
+            torch.cuda.synchronize(dev)
+            ms = a.elapsed_time(b) / args.les4096_steps
+            bw = BYTES_PER_LUP_FP32 * dns_lups / (ms * 1e-3) / 1e9
+            extra[key] = {"mlups": round(dns_lups / (ms * 1e-3) / 1e6, 1), "avg_launch_us": round(ms * 1e3, 2),
+                          "achieved_GBps": round(bw, 1), "frac": round(bw / HBM_PEAK_GBS, 4)}
+            log(f"{key}: {ms * 1e3:.1f} us/step, {bw:.0f} GB/s algorithmic")
+            del sv
         # in-place schedules at 4096^2: synchronous (moment sweep + collide sweep,
         # 65 values per update) and lagged (one sweep, 46 values per update)
         for sched, vals in (("aa", 65), ("aa_lagged", 46)):

@@ -89,6 +89,11 @@ extern "C" {
 #define LBM_CLOSURE_ANALYTIC 0  /* the Delta^2/12 closure of Sec. 2.1 / Sec. 3      */
 #define LBM_CLOSURE_LEARNED 1   /* analytic plus a learned per-cell correction
                                    (lbmhd_learned.h); LBM_SCHED_FUSED only        */
+#define LBM_CLOSURE_FULL 2      /* the closure before Sec. 3's simplification: the
+                                   filtered-density terms of FilterExampleLarge
+                                   (Z = rho) kept in the Reynolds and induction
+                                   products; LBM_SCHED_FUSED with LBM_STENCIL_ISO9
+                                   or LBM_STENCIL_CENTRAL5 only                   */
 
 typedef struct lbm_ctx lbm_ctx;
 

@@ -62,8 +62,11 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     return fail(LBM_EINVAL, "local gradients need the current populations: not with LBM_SCHED_AA_LAGGED");
   if (p->schedule != LBM_SCHED_FUSED && p->schedule != LBM_SCHED_AA && p->schedule != LBM_SCHED_AA_LAGGED)
     return fail(LBM_EINVAL, "schedule must be LBM_SCHED_FUSED, LBM_SCHED_AA or LBM_SCHED_AA_LAGGED");
-  if (p->closure != LBM_CLOSURE_ANALYTIC && p->closure != LBM_CLOSURE_LEARNED)
-    return fail(LBM_EINVAL, "closure must be LBM_CLOSURE_ANALYTIC or LBM_CLOSURE_LEARNED");
+  if (p->closure != LBM_CLOSURE_ANALYTIC && p->closure != LBM_CLOSURE_LEARNED && p->closure != LBM_CLOSURE_FULL)
+    return fail(LBM_EINVAL, "closure must be one of LBM_CLOSURE_*");
+  if (p->closure == LBM_CLOSURE_FULL &&
+      (p->schedule != LBM_SCHED_FUSED || p->grad_stencil >= LBM_STENCIL_LOCAL_ISO9))
+    return fail(LBM_EINVAL, "the density-gradient closure runs with LBM_SCHED_FUSED and a stencil gradient only");
   if (p->closure == LBM_CLOSURE_LEARNED && p->schedule != LBM_SCHED_FUSED)
     return fail(LBM_EINVAL, "the learned closure runs with LBM_SCHED_FUSED only");
   if (!finite_pos(p->rho0)) return fail(LBM_EINVAL, "rho0 must be finite and > 0");
@@ -78,6 +81,7 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     L->schedule = p->schedule;
     L->stencil = p->grad_stencil;
     L->learned = p->closure == LBM_CLOSURE_LEARNED;
+    L->full = p->closure == LBM_CLOSURE_FULL;
     for (double& r : L->rate) r = 0.0;
     L->rate[3] = s;
     L->rate[4] = s;

@@ -22,9 +22,13 @@ struct Closure {
   C tau_xy, tau_d, tau_s, eps;
 };
 
+// g = D m, h = D B (gxy = D_y m_x), k2 = closure strength x Delta^2 / 12.
+// Reynolds P_ac = k2/rho (D m_a).(D m_c), Maxwell Q_ac = k2 (D B_a).(D B_c),
+// induction R_ac = k2/rho (D m_a).(D' B_c); the induction product takes its
+// B gradients from h' (equal to h except in the density-gradient closure).
 template <typename C>
-__device__ __forceinline__ Closure<C> closure_terms(C gxx, C gxy, C gyx, C gyy, C hxx, C hxy, C hyx,
-                                                    C hyy, C inv_rho, C k2) {
+__device__ __forceinline__ Closure<C> closure_terms(C gxx, C gxy, C gyx, C gyy, C hxx, C hxy, C hyx, C hyy,
+                                                    C pxx_, C pxy_, C pyx_, C pyy_, C inv_rho, C k2) {
   const C kr = k2 * inv_rho;
   const C pxx = kr * (gxx * gxx + gxy * gxy);
   const C pyy = kr * (gyx * gyx + gyy * gyy);
@@ -32,14 +36,34 @@ __device__ __forceinline__ Closure<C> closure_terms(C gxx, C gxy, C gyx, C gyy, 
   const C qxx = k2 * (hxx * hxx + hxy * hxy);
   const C qyy = k2 * (hyx * hyx + hyy * hyy);
   const C qxy = k2 * (hxx * hyx + hxy * hyy);
-  const C rxy = kr * (gxx * hyx + gxy * hyy);
-  const C ryx = kr * (gyx * hxx + gyy * hxy);
+  const C rxy = kr * (gxx * pyx_ + gxy * pyy_);
+  const C ryx = kr * (gyx * pxx_ + gyy * pxy_);
   Closure<C> c;
   c.tau_xy = pxy - qxy;
   c.tau_d = (pxx - pyy) - (qxx - qyy);
   c.tau_s = pxx + pyy;
   c.eps = rxy - ryx;
   return c;
+}
+
+template <typename C>
+__device__ __forceinline__ Closure<C> closure_terms(C gxx, C gxy, C gyx, C gyy, C hxx, C hxy, C hyx,
+                                                    C hyy, C inv_rho, C k2) {
+  return closure_terms(gxx, gxy, gyx, gyy, hxx, hxy, hyx, hyy, hxx, hxy, hyx, hyy, inv_rho, k2);
+}
+
+// FilterExampleLarge with Z = rho: the bracket of the expansion of
+// bar(XY/rho) factors as (D X - X a).(D Y - Y a), a = D rho / rho, so every
+// quotient product (Reynolds and induction) takes gradients corrected by
+// their field times a, while the Maxwell product B_a B_c (no divisor)
+// keeps the plain B gradients.  gr[k][b] = D_b of (m_x, m_y, B_x, B_y, rho).
+template <typename C>
+__device__ __forceinline__ Closure<C> closure_terms_full(const C gr[5][2], C mx, C my, C bx, C by, C inv_rho,
+                                                         C k2) {
+  const C ax = gr[4][0] * inv_rho, ay = gr[4][1] * inv_rho;
+  return closure_terms(gr[0][0] - mx * ax, gr[0][1] - mx * ay, gr[1][0] - my * ax, gr[1][1] - my * ay,
+                       gr[2][0], gr[2][1], gr[3][0], gr[3][1],
+                       gr[2][0] - bx * ax, gr[2][1] - bx * ay, gr[3][0] - by * ax, gr[3][1] - by * ay, inv_rho, k2);
 }
 
 // Discrete gradient from a 3x3 neighbourhood (value at offset (dx, dy)).

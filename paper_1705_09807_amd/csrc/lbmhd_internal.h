@@ -37,6 +37,7 @@ struct Launch {
   size_t off_final = 0;           // final reduction values
   int diag_blocks = 0;
   bool learned = false;           // analytic closure plus the network's correction
+  bool full = false;              // closure with the filtered-density gradient terms
   size_t off_mom5 = 0;            // 5 FP32 moment planes (network input)
   size_t off_corr = 0;            // 4 FP32 correction planes
   size_t off_mlp = 0;             // packed network

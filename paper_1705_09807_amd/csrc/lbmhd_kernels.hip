@@ -398,13 +398,18 @@ k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
 // before row y is collided.  A ring slot is rewritten only after the barrier
 // that follows its last read.
 //
-// With CORR, four FP32 planes (tau_xx, tau_xy, tau_yy, eps) of a learned
-// correction are added to the analytic subgrid terms of every cell.
-template <typename S, typename C, int W, int STENCIL, bool NT, bool CORR>
+// MODE kClosureCorr: four FP32 planes (tau_xx, tau_xy, tau_yy, eps) of a
+// learned correction are added to the analytic subgrid terms of every cell.
+// MODE kClosureFull: the ring carries rho - rho0 as a fifth field and the
+// closure keeps the filtered-density gradient terms.
+enum { kClosurePlain = 0, kClosureCorr = 1, kClosureFull = 2 };
+
+template <typename S, typename C, int W, int STENCIL, bool NT, int MODE>
 __global__ void __launch_bounds__(W + 64)
 k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry, Rates<C> r,
             const float* __restrict__ corr) {
-  __shared__ C ring[4][4][W + 2];
+  constexpr int NF = MODE == kClosureFull ? 5 : 4;
+  __shared__ C ring[4][NF][W + 2];
   const int tid = threadIdx.x;
   const bool halo_wave = tid >= W;
   const int x0 = blockIdx.x * W;
@@ -428,6 +433,7 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
     ring[slot][1][widx] = m.my;
     ring[slot][2][widx] = m.dbx;
     ring[slot][3][widx] = m.dby;
+    if constexpr (NF == 5) ring[slot][4][widx] = m.drho;
   };
   auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
 
@@ -447,19 +453,24 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
     if (more && loader) pull_cell<S, C>(src, plane, rows_of<S>(wrapy(y + 2), nx, ny), cx, nn);
     if (valid) {
       const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
-      C gr[4][2];
+      C gr[NF][2];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < NF; ++k) {
         grad3x3<C, STENCIL>(ring[sc][k][l + 1], ring[sc][k][l - 1], ring[sn][k][l], ring[ss][k][l],
                             ring[sn][k][l + 1], ring[sn][k][l - 1], ring[ss][k][l + 1], ring[ss][k][l - 1], gr[k][0],
                             gr[k][1]);
       }
       const Mom<C> m = moments19(cur);
       const C ir = C(1) / (r.rho0 + m.drho);
-      if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9) local_gradients(cur, m, r, gr[1][0] - gr[0][1], gr);
-      Closure<C> cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
-                                    gr[3][1], ir, r.k2);
-      if constexpr (CORR) {
+      Closure<C> cl;
+      if constexpr (MODE == kClosureFull) {
+        cl = closure_terms_full(gr, m.mx, m.my, r.bx0 + m.dbx, r.by0 + m.dby, ir, r.k2);
+      } else {
+        if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9) local_gradients(cur, m, r, gr[1][0] - gr[0][1], gr);
+        cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0], gr[3][1], ir,
+                           r.k2);
+      }
+      if constexpr (MODE == kClosureCorr) {
         const int64_t n = (int64_t)nx * ny, ci = (int64_t)y * nx + x0 + tid;
         const C txx = C(corr[ci]), txy = C(corr[n + ci]), tyy = C(corr[2 * n + ci]), eps = C(corr[3 * n + ci]);
         cl.tau_xy += txy;
@@ -1008,35 +1019,38 @@ static bool streaming_stores(const Launch& L) {
   return 2.0 * double(kQ) * double(L.nx) * double(L.ny) * double(storage_bytes(L.dtype)) > 256.0e6;
 }
 
-template <typename S, typename C, int W, bool NT, bool CORR>
+template <typename S, typename C, int W, bool NT, int MODE>
 static void launch_les_k(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
   const int ry = fused_rows(L.nx, L.ny, W);
   const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
-  switch (L.stencil) {
-    case LBM_STENCIL_ISO9:
-      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT, CORR>), g, dim3(W + 64), 0, L.stream, src, dst,
-                         L.nx, L.ny, L.plane, ry, r, corr);
-      break;
-    case LBM_STENCIL_CENTRAL5:
-      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT, CORR>), g, dim3(W + 64), 0, L.stream, src,
+  if constexpr (MODE != kClosureFull) {  // the density-gradient closure takes stencil gradients only
+    if (L.stencil == LBM_STENCIL_LOCAL_ISO9) {
+      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_ISO9, NT, MODE>), g, dim3(W + 64), 0, L.stream, src,
                          dst, L.nx, L.ny, L.plane, ry, r, corr);
-      break;
-    case LBM_STENCIL_LOCAL_ISO9:
-      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_ISO9, NT, CORR>), g, dim3(W + 64), 0, L.stream, src,
-                         dst, L.nx, L.ny, L.plane, ry, r, corr);
-      break;
-    default:
-      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_CENTRAL5, NT, CORR>), g, dim3(W + 64), 0, L.stream,
+      return;
+    }
+    if (L.stencil == LBM_STENCIL_LOCAL_CENTRAL5) {
+      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_CENTRAL5, NT, MODE>), g, dim3(W + 64), 0, L.stream,
                          src, dst, L.nx, L.ny, L.plane, ry, r, corr);
+      return;
+    }
   }
+  if (L.stencil == LBM_STENCIL_CENTRAL5)
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT, MODE>), g, dim3(W + 64), 0, L.stream, src,
+                       dst, L.nx, L.ny, L.plane, ry, r, corr);
+  else
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT, MODE>), g, dim3(W + 64), 0, L.stream, src, dst,
+                       L.nx, L.ny, L.plane, ry, r, corr);
 }
 
 template <typename S, typename C, int W, bool NT>
 static void launch_les(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
   if (corr)
-    launch_les_k<S, C, W, NT, true>(L, src, dst, r, corr);
+    launch_les_k<S, C, W, NT, kClosureCorr>(L, src, dst, r, corr);
+  else if (L.full)
+    launch_les_k<S, C, W, NT, kClosureFull>(L, src, dst, r, nullptr);
   else
-    launch_les_k<S, C, W, NT, false>(L, src, dst, r, nullptr);
+    launch_les_k<S, C, W, NT, kClosurePlain>(L, src, dst, r, nullptr);
 }
 
 template <typename S, typename C, bool NT>

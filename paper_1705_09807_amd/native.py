@@ -37,6 +37,7 @@ LBM_SCHED_AA = 1
 LBM_SCHED_AA_LAGGED = 2
 LBM_CLOSURE_ANALYTIC = 0
 LBM_CLOSURE_LEARNED = 1
+LBM_CLOSURE_FULL = 2
 
 LBM_MLP_FEATURES = 64
 LBM_MLP_OUTPUTS = 4

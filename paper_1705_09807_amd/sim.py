@@ -14,7 +14,7 @@ _DTYPES = {"fp64": N.LBM_FP64, "fp32": N.LBM_FP32, "fp16": N.LBM_FP16, "bf16": N
 _STENCILS = {"iso9": N.LBM_STENCIL_ISO9, "central5": N.LBM_STENCIL_CENTRAL5,
              "local_iso9": N.LBM_STENCIL_LOCAL_ISO9, "local_central5": N.LBM_STENCIL_LOCAL_CENTRAL5}
 _SCHEDULES = {"fused": N.LBM_SCHED_FUSED, "aa": N.LBM_SCHED_AA, "aa_lagged": N.LBM_SCHED_AA_LAGGED}
-_CLOSURES = {"analytic": N.LBM_CLOSURE_ANALYTIC, "learned": N.LBM_CLOSURE_LEARNED}
+_CLOSURES = {"analytic": N.LBM_CLOSURE_ANALYTIC, "learned": N.LBM_CLOSURE_LEARNED, "full": N.LBM_CLOSURE_FULL}
 
 
 def make_params(nx, ny, nu, eta, delta=0.0, closure_scale=1.0, s5=0.0, s6=0.0, s7=0.0, s8=0.0,

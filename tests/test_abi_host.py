@@ -62,7 +62,7 @@ def test_buffer_sizes(lib):
 @pytest.mark.parametrize("field,value", [
     ("nx", 3), ("ny", 0), ("nx", 40000), ("nu", 0.0), ("nu", -1e-3), ("eta", float("nan")),
     ("s5", 2.0), ("s8", float("inf")), ("delta", -1.0), ("closure_scale", float("nan")),
-    ("grad_stencil", 4), ("grad_stencil", -1), ("dtype", 7), ("schedule", 3), ("schedule", -1), ("closure", 2),
+    ("grad_stencil", 4), ("grad_stencil", -1), ("dtype", 7), ("schedule", 3), ("schedule", -1), ("closure", 3),
     ("closure", -1),
     ("rho0", 0.0),
     ("bref_x", float("nan")), ("bref_y", float("inf")),
@@ -206,3 +206,25 @@ def test_sech2_params(lib):
             assert lib.lbm_init_sech2_jet(ctx, ctypes.byref(N.LbmSech2Params(**kw))) == N.LBM_EINVAL
     finally:
         lib.lbm_destroy(ctx)
+
+
+def test_density_gradient_closure_params(lib):
+    ok = _params(closure=N.LBM_CLOSURE_FULL)
+    assert lib.lbm_work_bytes(ctypes.byref(ok)) > 0
+    assert lib.lbm_work_bytes(ctypes.byref(_params(closure=N.LBM_CLOSURE_FULL,
+                                                   grad_stencil=N.LBM_STENCIL_CENTRAL5))) > 0
+    for bad in (dict(schedule=N.LBM_SCHED_AA), dict(schedule=N.LBM_SCHED_AA_LAGGED),
+                dict(grad_stencil=N.LBM_STENCIL_LOCAL_ISO9), dict(grad_stencil=N.LBM_STENCIL_LOCAL_CENTRAL5)):
+        assert lib.lbm_work_bytes(ctypes.byref(_params(closure=N.LBM_CLOSURE_FULL, **bad))) == 0, bad
+    assert lib.lbm_work_bytes(ctypes.byref(_params(closure=3))) == 0
+
+
+def test_header_constants_match_the_binding():
+    import re
+    seen = 0
+    for path in N.HEADERS:
+        for name, value in re.findall(r"#define\s+(LBM_[A-Z0-9_]+)\s+(-?\d+)\b", open(path).read()):
+            if hasattr(N, name):
+                assert getattr(N, name) == int(value), name
+                seen += 1
+    assert seen >= 20
