@@ -156,6 +156,129 @@ def precision_study(steps: int, dev, stream) -> int:
     return 0
 
 
+JET_RUNS = {
+    # label: (grid, Delta, nu = eta, length in units of the LES run's steps)
+    "dns1024": (1024, 0.0, 1e-3, 1),
+    "les1024_d1": (1024, 1.0, 1e-3, 1),
+    "les1024_d2": (1024, 2.0, 1e-3, 1),
+    "dns2048": (2048, 0.0, 2e-3, 2),
+}
+
+
+def _slope(ek, lo, hi):
+    """Least-squares exponent a of E(k) ~ k^a over the integer bins lo..hi."""
+    import numpy as np
+    k = np.arange(lo, hi + 1, dtype=np.float64)
+    e = np.asarray(ek[lo:hi + 1], dtype=np.float64)
+    ok = e > 0
+    return float(np.polyfit(np.log(k[ok]), np.log(e[ok]), 1)[0])
+
+
+def jet_compare(spectra: dict, a: str, b: str, kmax: int = 128) -> dict:
+    """Relative L2 distance of the total-energy spectra E_K + E_M of run a at
+    LES time t and run b at its matching time (2t for DNS 2048^2 against a
+    1024^2 run), over the bins 1..kmax, for every common snapshot."""
+    import numpy as np
+    ma, mb = JET_RUNS[a][3], JET_RUNS[b][3]
+    out = {}
+    for ta, sa in spectra.get(a, {}).items():
+        tb = str(int(ta) * mb // ma)
+        sb = spectra.get(b, {}).get(tb)
+        if sb is None:
+            continue
+        ea = np.asarray(sa["E_K"][1:kmax + 1]) + np.asarray(sa["E_M"][1:kmax + 1])
+        eb = np.asarray(sb["E_K"][1:kmax + 1]) + np.asarray(sb["E_M"][1:kmax + 1])
+        out[f"{ta}/{tb}"] = round(float(np.linalg.norm(ea - eb) / np.linalg.norm(eb)), 4)
+    return out
+
+
+def jet_study(args, dev, stream) -> int:
+    """The magnetized Kelvin-Helmholtz jet of Sec. 4 on the paper's grids.
+
+    sech^2 jet U0 = 4.88e-2, B_y = B0 = 0.005 U0 along the jet, the four 1 %
+    perturbations (lbm_init_sech2_jet); Re = U0 L / nu = 50k at every grid:
+    nu = eta = 1e-3 at 1024^2, 2e-3 at 2048^2.  Runs: DNS 1024^2, LES 1024^2
+    with Delta = 1 and Delta = 2 (simplified closure of Sec. 3, 3x3 isotropic
+    gradients) for T steps, DNS 2048^2 for 2T (t_DNS = 2 t_LES); the paper's
+    T is 780k.  Single-relaxation-time collisions (ghost rates = s3), FP64 by
+    default: the initial state is periodic in y with period L/4, and FP32
+    storage rounds the sub-ulp differences between the four periods away,
+    so the vortex-pairing modes are never seeded and the L/4 street never
+    merges; in FP64 they grow from round-off.  Reported per run at T/4, T/2 and T (DNS 2048^2: twice those
+    steps): kinetic and magnetic energy, enstrophy, max |div B|, and the
+    exponent of a power-law fit of the total-energy spectrum E_K + E_M over
+    two wavenumber ranges; the paper quotes -1.66 for the 1024^2 runs and
+    -1.71 for DNS 2048^2 at the final time (its fit range is not stated).
+    One JSON line on stdout; the spectra of every snapshot go to
+    gpurun_out/jet_spectra_<runs>.json when that directory exists.
+    """
+    import numpy as np
+    import torch
+
+    from paper_1705_09807_amd import Sim
+    from paper_1705_09807_amd import learned as G
+
+    T = int(args.jet_study)
+    labels = [r for r in args.jet_runs.split(",") if r]
+    for r in labels:
+        if r not in JET_RUNS:
+            log(f"unknown run {r}; choose from {sorted(JET_RUNS)}")
+            return 2
+    U0 = 4.88e-2
+    B0 = 0.005 * U0
+    dtype = args.jet_dtype
+    out = {"study": "sech2 jet (Sec. 4)", "T_les": T, "U0": U0, "B0": B0, "Re": 5e4, "dtype": dtype,
+           "collision": "SRT", "runs": {}}
+    spectra = {}
+    for label in labels:
+        n, delta, nu, mult = JET_RUNS[label]
+        steps = T * mult
+        sim = Sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype=dtype, b_ref=(0.0, B0), device=dev, stream=stream)
+        sim.init_sech2_jet(U0=U0, B0=B0, pert=0.01, k=4)
+        marks = sorted({steps // 4, steps // 2, steps})
+        rec = {"grid": n, "delta": delta, "nu": nu, "eta": nu, "steps": steps, "snapshots": {}}
+        chunk = max(1, min(20000 * mult, steps // 8))
+        t0 = time.perf_counter()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        gpu_ms = 0.0
+        while sim.t < steps:
+            nxt = min(steps, sim.t + chunk, min(m for m in marks if m > sim.t))
+            ev0.record(stream)
+            sim.step(nxt - sim.t)
+            ev1.record(stream)
+            torch.cuda.synchronize(dev)
+            gpu_ms += ev0.elapsed_time(ev1)
+            d = sim.diagnostics()
+            log(f"{label}: t = {sim.t} e_kin {d['e_kin']:.6e} e_mag {d['e_mag']:.6e} "
+                f"nonfinite {d['nonfinite']} ({time.perf_counter() - t0:.0f} s)")
+            if d["nonfinite"] or not np.isfinite(d["e_kin"]):
+                rec["overflow_at"] = sim.t
+                break
+            if sim.t in marks:
+                ek, em, _ = G.spectra(sim.moments())
+                tot = (ek + em).cpu().numpy()
+                snap = {k: d[k] for k in ("e_kin", "e_mag", "enstrophy", "j2", "divb_max", "divb_rms")}
+                snap["slope_k8_64"] = round(_slope(tot, 8, 64), 3)
+                snap["slope_k16_128"] = round(_slope(tot, 16, 128), 3)
+                snap["slope_k8_64_kinetic"] = round(_slope(ek.cpu().numpy(), 8, 64), 3)
+                rec["snapshots"][str(sim.t)] = snap
+                spectra.setdefault(label, {})[str(sim.t)] = {"E_K": ek.cpu().tolist(), "E_M": em.cpu().tolist()}
+        rec["gpu_seconds"] = round(gpu_ms / 1e3, 2)
+        rec["mlups"] = round(n * n * sim.t / max(gpu_ms, 1e-9) / 1e3, 1)
+        out["runs"][label] = rec
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    for a in ("les1024_d2", "les1024_d1", "dns1024"):
+        if a in spectra and "dns2048" in spectra:
+            out[f"spectrum_rel_l2_{a}_vs_dns2048"] = jet_compare(spectra, a, "dns2048")
+    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
+        with open(os.path.join(ROOT, "gpurun_out", f"jet_spectra_{'_'.join(labels)}.json"), "w") as fh:
+            json.dump(spectra, fh)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def learned_study(args, dev, stream) -> int:
     """A-posteriori test of the learned closure (filtered DNS -> 4x coarser LES).
 
@@ -347,6 +470,12 @@ def main() -> int:
                     help="instead of the benchmark: train the learned closure on filtered 4096^2 DNS and "
                          "compare learned and analytic 1024^2 LES with the filtered DNS of a held-out seed "
                          "over LES_STEPS steps (one JSON line)")
+    ap.add_argument("--jet-study", type=int, default=0, metavar="T",
+                    help="instead of the benchmark: the magnetized sech^2 jet of the paper, LES runs of T "
+                         "steps (the paper's T is 780000) and DNS 2048^2 of 2T (one JSON line)")
+    ap.add_argument("--jet-runs", default="dns1024,les1024_d1,les1024_d2,dns2048",
+                    help="comma-separated subset of the jet study's runs")
+    ap.add_argument("--jet-dtype", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--study-nu", type=float, default=1e-3, help="LES-grid viscosity of the study")
     ap.add_argument("--study-eta", type=float, default=1e-2, help="LES-grid resistivity of the study")
@@ -375,6 +504,8 @@ def main() -> int:
         return precision_study(args.precision_study, dev, stream)
     if args.learned_study > 0:
         return learned_study(args, dev, stream)
+    if args.jet_study > 0:
+        return jet_study(args, dev, stream)
 
     bref = (KH["B0"], 0.0)
     ghost = dict(s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
