@@ -578,27 +578,36 @@ def main() -> int:
 
     if args.les4096_steps > 0:
         del les
-        big = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype="fp32", schedule="fused",
-                  b_ref=bref, device=dev, stream=stream, **ghost)
-        big.init_kh_jet(seed=0, **KH)
-        big.step(20)
-        a, b = ev(), ev()
-        a.record(stream)
-        big.step(args.les4096_steps)
-        b.record(stream)
-        torch.cuda.synchronize(dev)
-        ms = a.elapsed_time(b) / args.les4096_steps
-        bw = BYTES_PER_LUP_FP32 * dns_lups / (ms * 1e-3) / 1e9
-        extra["les4096"] = {"mlups": round(dns_lups / (ms * 1e-3) / 1e6, 1), "avg_launch_us": round(ms * 1e3, 2),
-                            "achieved_GBps": round(bw, 1), "frac": round(bw / HBM_PEAK_GBS, 4),
-                            "kernel": "k_fused_les<float> (plain closure, Delta=4)"}
-        log(f"les 4096^2: {ms * 1e3:.1f} us/step, {bw:.0f} GB/s algorithmic")
-        del big
-        # closure variants of the same fused sweep (same 152 B per update):
-        # filtered-density gradient terms kept, and gradients from local
-        # non-equilibrium moments
-        for key, kw in (("les4096_full", dict(closure="full")), ("les4096_local_iso9", dict(grad_stencil="local_iso9"))):
-            sv = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype="fp32", schedule="fused",
+        # 4096^2 LES (Delta = 4) in every closure variant and schedule, each
+        # timed over the same steps from the same state; the end states are
+        # compared with the synchronous fused run (relative L2 of m and of
+        # B - mean B), beside the closure's own effect (sync LES vs Delta = 0).
+        # values per update: fused 19 + 19; in place synchronous 19 + 4 then
+        # 19 + 4 + 19; in place lagged 19 + 4 + 19 + 4.
+        variants = [
+            ("les4096", "fused", {}, 38, "k_fused_les<float> (plain closure, Delta=4)"),
+            ("les4096_full", "fused", dict(closure="full"), 38, "k_fused_les<float, ..., full> (density-gradient terms)"),
+            ("les4096_local_iso9", "fused", dict(grad_stencil="local_iso9"), 38,
+             "k_fused_les<float, LOCAL_ISO9> (gradients from non-equilibrium moments)"),
+            ("les4096_aa", "aa", {}, 65, "k_aa_moments + k_aa_les (in place, synchronous)"),
+            ("les4096_aa_lagged", "aa_lagged", {}, 46, "k_aa_les_lagged (in place, lagged gradients)"),
+        ]
+        nsteps = 20 + args.les4096_steps
+
+        def field_rel(a, b):
+            da, db = a[1:3] - b[1:3], b[1:3]
+            bm = b[3:5].mean(dim=(1, 2), keepdim=True)
+            return {"m": float(da.norm() / db.norm()), "B": float((a[3:5] - b[3:5]).norm() / (b[3:5] - bm).norm())}
+
+        sd = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=0.0, dtype="fp32", schedule="fused",
+                 b_ref=bref, device=dev, stream=stream, **ghost)
+        sd.init_kh_jet(seed=0, **KH)
+        sd.step(nsteps)
+        mom_off = sd.moments()
+        del sd
+        mom_sync = None
+        for key, sched, kw, vals, kname in variants:
+            sv = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype="fp32", schedule=sched,
                      b_ref=bref, device=dev, stream=stream, **ghost, **kw)
             sv.init_kh_jet(seed=0, **KH)
             sv.step(20)
@@ -608,30 +617,22 @@ def main() -> int:
             b.record(stream)
             torch.cuda.synchronize(dev)
             ms = a.elapsed_time(b) / args.les4096_steps
-            bw = BYTES_PER_LUP_FP32 * dns_lups / (ms * 1e-3) / 1e9
-            extra[key] = {"mlups": round(dns_lups / (ms * 1e-3) / 1e6, 1), "avg_launch_us": round(ms * 1e3, 2),
-                          "achieved_GBps": round(bw, 1), "frac": round(bw / HBM_PEAK_GBS, 4)}
+            bw = vals * 4 * dns_lups / (ms * 1e-3) / 1e9
+            rec = {"mlups": round(dns_lups / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 2),
+                   "bytes_per_lup": vals * 4, "achieved_GBps": round(bw, 1), "frac": round(bw / HBM_PEAK_GBS, 4),
+                   "kernel": kname}
+            mom = sv.moments()
+            if mom_sync is None:
+                mom_sync = mom
+                rec["closure_effect_vs_delta0"] = {k: float(f"{v:.3e}") for k, v in field_rel(mom, mom_off).items()}
+            else:
+                rec["rel_l2_vs_sync_fused"] = {k: float(f"{v:.3e}") for k, v in field_rel(mom, mom_sync).items()}
+                del mom
+            extra[key] = rec
             log(f"{key}: {ms * 1e3:.1f} us/step, {bw:.0f} GB/s algorithmic")
             del sv
-        # in-place schedules at 4096^2: synchronous (moment sweep + collide sweep,
-        # 65 values per update) and lagged (one sweep, 46 values per update)
-        for sched, vals in (("aa", 65), ("aa_lagged", 46)):
-            sa = Sim(nx=DNS_N, ny=DNS_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype="fp32", schedule=sched,
-                     b_ref=bref, device=dev, stream=stream, **ghost)
-            sa.init_kh_jet(seed=0, **KH)
-            sa.step(20)
-            a, b = ev(), ev()
-            a.record(stream)
-            sa.step(args.les4096_steps)
-            b.record(stream)
-            torch.cuda.synchronize(dev)
-            ms = a.elapsed_time(b) / args.les4096_steps
-            bw = vals * 4 * dns_lups / (ms * 1e-3) / 1e9
-            extra[f"les4096_{sched}"] = {"mlups": round(dns_lups / (ms * 1e-3) / 1e6, 1),
-                                         "avg_step_us": round(ms * 1e3, 2), "bytes_per_lup": vals * 4,
-                                         "achieved_GBps": round(bw, 1), "frac": round(bw / HBM_PEAK_GBS, 4)}
-            log(f"les 4096^2 {sched}: {ms * 1e3:.1f} us/step, {bw:.0f} GB/s algorithmic")
-            del sa
+        del mom_off, mom_sync
+        torch.cuda.empty_cache()
 
     if args.learned_steps > 0:
         # 1024^2 LES with the learned closure (moments -> network correction on
