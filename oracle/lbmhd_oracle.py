@@ -12,7 +12,9 @@ State and conventions
   dx = dt = 1).  Arrays are indexed ``[..., y, x]``.
 * ``f[9, ny, nx]``: D2Q9 scalar distribution (filtered density, momentum).
 * ``g[5, 2, ny, nx]``: vector distribution on the D2Q5 subset of the same
-  velocities, ``g[i, alpha]`` = component alpha of g_i (filtered B).
+  velocities, ``g[i, alpha]`` = component alpha of g_i (filtered B);
+  ``g[9, 2, ny, nx]`` with ``mag_lattice="d2q9"`` (all nine velocities,
+  collision in the moment space of ``MagTMatrix``).
 * The stored state at time t is post-streaming (what the next collision
   consumes).  Two arrays, no in-place tricks.
 
@@ -82,6 +84,23 @@ T = moment_matrix()
 T_INV = np.linalg.inv(T)
 
 
+def magnetic_moment_matrix() -> np.ndarray:
+    """The 9x9 transform T_m of the D2Q9 vector distribution built from its
+    symbolic rows, Sec. 2 ``MagTMatrix``: 1, c_x, c_y, c_x c_y, c_x^2, c_y^2,
+    c_x^2 c_y, c_x c_y^2, c_x^2 c_y^2."""
+    cx = CX.astype(np.float64)
+    cy = CY.astype(np.float64)
+    rows = [np.ones(9), cx, cy, cx * cy, cx ** 2, cy ** 2, cx ** 2 * cy, cx * cy ** 2, cx ** 2 * cy ** 2]
+    return np.array(rows)
+
+
+T_M = magnetic_moment_matrix()
+T_M_INV = np.linalg.inv(T_M)
+
+#: Magnetic lattices: number of velocities of g (the first n of the D2Q9 set).
+MAG_LATTICES = {"d2q5": 5, "d2q9": 9}
+
+
 def relaxation_rates(nu: float, s5=None, s6=None, s7=None, s8=None) -> np.ndarray:
     """Diagonal of the MRT rate matrix in moment space.
 
@@ -131,6 +150,52 @@ def g_equilibrium(rho, mx, my, Bx, By) -> np.ndarray:
         out[i, 0] = W5[i] * (Bx + 3.0 * (cu * Bx - cb * ux))
         out[i, 1] = W5[i] * (By + 3.0 * (cu * By - cb * uy))
     return out
+
+
+def magnetic_equilibrium_moments(Bx, By, lam) -> np.ndarray:
+    """N^(eq)_{alpha i}, i = 0..8, of the D2Q9 vector distribution, Sec. 2
+    ``MagMomentEq`` with u in place of rho u (the R2 reading): N0 = B_a,
+    N1 = Lam[x, a], N2 = Lam[y, a], N3 = 0, N4 = N5 = B_a / 3,
+    N6 = Lam[y, a] / 3, N7 = Lam[x, a] / 3, N8 = B_a / 9, where
+    Lam[b, a] = u_b B_a - B_b u_a (or its filtered value).  The table marks
+    N4, N5 with (0) instead of (eq); they are read as equilibria like the
+    rest.  Returns [9, 2, ...]."""
+    B = (Bx, By)
+    out = np.empty((9, 2) + np.shape(Bx))
+    for a in range(2):
+        out[0, a] = B[a]
+        out[1, a] = lam[0, a]
+        out[2, a] = lam[1, a]
+        out[3, a] = 0.0 * B[a]
+        out[4, a] = B[a] / 3.0
+        out[5, a] = B[a] / 3.0
+        out[6, a] = lam[1, a] / 3.0
+        out[7, a] = lam[0, a] / 3.0
+        out[8, a] = B[a] / 9.0
+    return out
+
+
+def unfiltered_induction(rho, mx, my, Bx, By) -> np.ndarray:
+    """Lam[b, a] = u_b B_a - B_b u_a with u = rho u / rho."""
+    u = (mx / rho, my / rho)
+    B = (Bx, By)
+    lam = np.empty((2, 2) + np.shape(rho))
+    for b in range(2):
+        for a in range(2):
+            lam[b, a] = u[b] * B[a] - B[b] * u[a]
+    return lam
+
+
+def g_equilibrium_d2q9(rho, mx, my, Bx, By) -> np.ndarray:
+    """Vector g^(eq) on D2Q9 (the lattice Sec. 2 uses for g): the moments of
+    ``MagMomentEq`` mapped back to populations, T_m^-1 N^(eq).  [9, 2, ...]."""
+    neq = magnetic_equilibrium_moments(Bx, By, unfiltered_induction(rho, mx, my, Bx, By))
+    return np.tensordot(T_M_INV, neq, axes=(1, 0))
+
+
+def g_equilibrium_for(lattice: str, rho, mx, my, Bx, By) -> np.ndarray:
+    """g^(eq) on the named magnetic lattice ('d2q5' or 'd2q9')."""
+    return g_equilibrium(rho, mx, my, Bx, By) if lattice == "d2q5" else g_equilibrium_d2q9(rho, mx, my, Bx, By)
 
 
 # ---------------------------------------------------------------------------
@@ -359,14 +424,15 @@ def uniform_pm1(seed: int, counter: np.ndarray) -> np.ndarray:
 
 
 def kh_jet_populations(x, y, nx, ny, U0=0.05, delta_over_L=0.05, B0=0.01, rho0=1.0,
-                       pert_amp_over_U0=1e-3, noise_amp=1e-5, seed=0):
+                       pert_amp_over_U0=1e-3, noise_amp=1e-5, seed=0, lattice="d2q5"):
     """Initial populations at integer nodes (x, y) (arrays of equal shape) of
     an nx x ny grid.  Double shear layer u_x = U0 [tanh((y - L/4)/d) -
     tanh((y - 3L/4)/d) - 1] with L = ny, d = delta_over_L * ny;
     u_y = pert * U0 sin(2 pi x / nx) + noise_amp * xi, xi uniform on [-1, 1)
     from SplitMix64 on the cell index y * nx + x; B = (B0, 0); rho = rho0.
     Populations are the unfiltered equilibria ``feq`` and ``geq`` (Sec. 2).
-    Returns (f[9, ...], g[5, 2, ...])."""
+    Returns (f[9, ...], g[q, 2, ...]) with q = 5 or 9 for the magnetic
+    lattice."""
     x = np.asarray(x, dtype=np.int64)
     y = np.asarray(y, dtype=np.int64)
     L = float(ny)
@@ -379,10 +445,11 @@ def kh_jet_populations(x, y, nx, ny, U0=0.05, delta_over_L=0.05, B0=0.01, rho0=1
     bx = np.full(x.shape, float(B0))
     by = np.zeros(x.shape)
     return (f_equilibrium(rho, rho * ux, rho * uy, bx, by),
-            g_equilibrium(rho, rho * ux, rho * uy, bx, by))
+            g_equilibrium_for(lattice, rho, rho * ux, rho * uy, bx, by))
 
 
-def sech2_jet_populations(x, y, nx, ny, U0=4.88e-2, B0=0.005 * 4.88e-2, pert=0.01, k=4, rho0=1.0):
+def sech2_jet_populations(x, y, nx, ny, U0=4.88e-2, B0=0.005 * 4.88e-2, pert=0.01, k=4, rho0=1.0,
+                          lattice="d2q5"):
     """The magnetized Kelvin-Helmholtz jet of Sec. 4 at integer nodes (x, y):
     u_y = U0 sech^2(2 pi k d / nx) + pert U0 sin(2 pi k x / nx),
     u_x = pert U0 sin(2 pi k y / ny),
@@ -400,7 +467,7 @@ def sech2_jet_populations(x, y, nx, ny, U0=4.88e-2, B0=0.005 * 4.88e-2, pert=0.0
     by = B0 + pert * B0 * np.sin(2.0 * math.pi * k * xf / nx)
     rho = np.full(xf.shape, float(rho0))
     return (f_equilibrium(rho, rho * ux, rho * uy, bx, by),
-            g_equilibrium(rho, rho * ux, rho * uy, bx, by))
+            g_equilibrium_for(lattice, rho, rho * ux, rho * uy, bx, by))
 
 
 # ---------------------------------------------------------------------------
@@ -419,7 +486,7 @@ class Oracle:
     def __init__(self, nx: int, ny: int, nu: float, eta: float, delta: float = 0.0,
                  closure_scale: float = 1.0, s5=None, s6=None, s7=None, s8=None,
                  grad_stencil: str = "iso9", closure_correction=None, closure_time: str = "sync",
-                 density_gradients: bool = False):
+                 density_gradients: bool = False, mag_lattice: str = "d2q5"):
         if nx < 4 or ny < 4:
             raise ValueError("grid must be at least 4 x 4")
         self.nx, self.ny = int(nx), int(ny)
@@ -456,9 +523,18 @@ class Oracle:
         self.density_gradients = bool(density_gradients)
         if self.density_gradients and (self.local or closure_time != "sync"):
             raise ValueError("the density-gradient closure takes synchronous stencil gradients")
+        # mag_lattice "d2q9": the vector distribution on all nine velocities with
+        # the collision in the moment space of ``MagTMatrix`` (Sec. 2's own
+        # lattice for g); "d2q5" is the five-velocity subset (R1)
+        if mag_lattice not in MAG_LATTICES:
+            raise ValueError("mag_lattice must be 'd2q5' or 'd2q9'")
+        if mag_lattice == "d2q9" and self.local:
+            raise ValueError("local gradients are defined for the D2Q5 vector distribution")
+        self.mag_lattice = mag_lattice
+        self.qg = MAG_LATTICES[mag_lattice]
         self._prev = None
         self.f = np.zeros((9, self.ny, self.nx))
-        self.g = np.zeros((5, 2, self.ny, self.nx))
+        self.g = np.zeros((self.qg, 2, self.ny, self.nx))
         self.t = 0
 
     # -- initial and injected states ------------------------------------
@@ -469,7 +545,7 @@ class Oracle:
         x = np.arange(self.nx, dtype=np.int64)[None, :] * np.ones((self.ny, 1), dtype=np.int64)
         y = np.arange(self.ny, dtype=np.int64)[:, None] * np.ones((1, self.nx), dtype=np.int64)
         self.f, self.g = kh_jet_populations(x, y, self.nx, self.ny, U0, delta_over_L, B0, rho0,
-                                            pert_amp_over_U0, noise_amp, seed)
+                                            pert_amp_over_U0, noise_amp, seed, self.mag_lattice)
         self.t = 0
         self._prev = None
 
@@ -478,13 +554,13 @@ class Oracle:
         ``sech2_jet_populations``)."""
         x = np.arange(self.nx, dtype=np.int64)[None, :] * np.ones((self.ny, 1), dtype=np.int64)
         y = np.arange(self.ny, dtype=np.int64)[:, None] * np.ones((1, self.nx), dtype=np.int64)
-        self.f, self.g = sech2_jet_populations(x, y, self.nx, self.ny, U0, B0, pert, k, rho0)
+        self.f, self.g = sech2_jet_populations(x, y, self.nx, self.ny, U0, B0, pert, k, rho0, self.mag_lattice)
         self.t = 0
         self._prev = None
 
     def set_state(self, f, g, t: int = 0):
         self.f = np.array(f, dtype=np.float64).reshape(9, self.ny, self.nx)
-        self.g = np.array(g, dtype=np.float64).reshape(5, 2, self.ny, self.nx)
+        self.g = np.array(g, dtype=np.float64).reshape(self.qg, 2, self.ny, self.nx)
         self.t = int(t)
         self._prev = None
 
@@ -541,8 +617,15 @@ class Oracle:
             lam[1, 0] = lam[1, 0] - c[3]
         M = np.tensordot(T, f, axes=(1, 0))
         fstar = f - np.tensordot(T_INV, self.rates[:, None, None] * (M - meq), axes=(1, 0))
-        geq = g_equilibrium_from_moments(Bx, By, lam)
-        gstar = g - self.s_m * (g - geq)
+        if self.qg == 9:
+            # D2Q9 g: relax N = T_m g towards the filtered ``MagMomentEq`` table,
+            # one rate s_m for every moment (SRT), and map back
+            N = np.tensordot(T_M, g, axes=(1, 0))
+            neq = magnetic_equilibrium_moments(Bx, By, lam)
+            gstar = np.tensordot(T_M_INV, N - self.s_m * (N - neq), axes=(1, 0))
+        else:
+            geq = g_equilibrium_from_moments(Bx, By, lam)
+            gstar = g - self.s_m * (g - geq)
         return fstar, gstar
 
     @staticmethod
@@ -552,7 +635,7 @@ class Oracle:
         g = np.empty_like(gstar)
         for i in range(9):
             f[i] = np.roll(fstar[i], (CY[i], CX[i]), axis=(0, 1))
-        for i in range(5):
+        for i in range(gstar.shape[0]):
             g[i] = np.roll(gstar[i], (CY[i], CX[i]), axis=(-2, -1))
         return f, g
 

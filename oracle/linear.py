@@ -2,14 +2,16 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-About a uniform equilibrium (rho0, u0, B0) a small perturbation of the 19
-populations (f_0..f_8, g_x0..g_x4, g_y0..g_y4) with wave vector k evolves as
+About a uniform equilibrium (rho0, u0, B0) a small perturbation of the
+9 + 2q populations (f_0..f_8, g_x0..g_x(q-1), g_y0..g_y(q-1); q = 5 for the
+D2Q5 vector distribution, 9 for D2Q9) with wave vector k evolves as
 x(t + 1) = G(k) x(t), G = Phi(k) (I - C):
 
 * C is the collision linearised by hand from the population-form equilibria
   of Sec. 2 (``feq``, ``geq``) -- not from the moment table the oracle uses --
   and the MRT relaxation T^-1 S T (``FluidTMatrix``) with T typed in from the
-  printed integer matrix, plus SRT for g (``LBMagEqn``).
+  printed integer matrix, plus SRT for g (``LBMagEqn``) in population space
+  (for D2Q9 g this bypasses the ``MagTMatrix`` route the oracle takes).
 * Phi(k) = diag(exp(-i k.c_q)) is streaming f_q(x + c_q) = f*_q(x).
 
 The subgrid closure is quadratic in gradients and drops out of the
@@ -44,25 +46,32 @@ _WM = np.array([1 / 3, 1 / 6, 1 / 6, 1 / 6, 1 / 6])
 NQ = 19
 
 
-def _macro_jacobian() -> np.ndarray:
-    """d(rho, m_x, m_y, B_x, B_y) / d(19 populations)."""
-    D = np.zeros((5, NQ))
+def _gweights(qg: int) -> np.ndarray:
+    """Weights of the vector distribution: D2Q5 (1/3, 1/6 x4) or the D2Q9 ones."""
+    return _WM if qg == 5 else _W
+
+
+def _macro_jacobian(qg: int = 5) -> np.ndarray:
+    """d(rho, m_x, m_y, B_x, B_y) / d(9 + 2 qg populations)."""
+    nq = 9 + 2 * qg
+    D = np.zeros((5, nq))
     D[0, :9] = 1.0
     D[1, :9] = _CX
     D[2, :9] = _CY
-    D[3, 9:14] = 1.0
-    D[4, 14:19] = 1.0
+    D[3, 9:9 + qg] = 1.0
+    D[4, 9 + qg:nq] = 1.0
     return D
 
 
-def equilibrium_jacobian(rho0: float, u0, B0) -> np.ndarray:
+def equilibrium_jacobian(rho0: float, u0, B0, qg: int = 5) -> np.ndarray:
     """d(f^eq, g^eq) / d(rho, m_x, m_y, B_x, B_y) at (rho0, rho0 u0, B0),
     differentiated by hand from ``feq`` and ``geq`` (u = m / rho)."""
     ux, uy = float(u0[0]), float(u0[1])
     bx, by = float(B0[0]), float(B0[1])
     u = (ux, uy)
     b = (bx, by)
-    J = np.zeros((NQ, 5))
+    wm = _gweights(qg)
+    J = np.zeros((9 + 2 * qg, 5))
     for i in range(9):
         c = (_CX[i], _CY[i])
         cu = c[0] * ux + c[1] * uy
@@ -75,42 +84,44 @@ def equilibrium_jacobian(rho0: float, u0, B0) -> np.ndarray:
             J[i, 1 + a] = _W[i] * (3.0 * c[a] + 9.0 * cu * c[a] - 3.0 * u[a])
             # 9/2 w [1/2 B^2 c^2 - (B.c)^2]
             J[i, 3 + a] = 4.5 * _W[i] * (b[a] * c2 - 2.0 * cb * c[a])
-    for i in range(5):
+    for i in range(qg):
         c = (_CX[i], _CY[i])
         cu = c[0] * ux + c[1] * uy
         cb = c[0] * bx + c[1] * by
         for a in range(2):
-            row = 9 + 5 * a + i
+            row = 9 + qg * a + i
             # w' [B_a + 3 ((c.m) B_a - (c.B) m_a) / rho]
-            J[row, 0] = -3.0 * _WM[i] * (cu * b[a] - cb * u[a]) / rho0
+            J[row, 0] = -3.0 * wm[i] * (cu * b[a] - cb * u[a]) / rho0
             for bb in range(2):
-                J[row, 1 + bb] = 3.0 * _WM[i] * (c[bb] * b[a] - cb * (1.0 if a == bb else 0.0)) / rho0
-                J[row, 3 + bb] = _WM[i] * ((1.0 if a == bb else 0.0)
-                                           + 3.0 * (cu * (1.0 if a == bb else 0.0) - c[bb] * u[a]))
+                J[row, 1 + bb] = 3.0 * wm[i] * (c[bb] * b[a] - cb * (1.0 if a == bb else 0.0)) / rho0
+                J[row, 3 + bb] = wm[i] * ((1.0 if a == bb else 0.0)
+                                          + 3.0 * (cu * (1.0 if a == bb else 0.0) - c[bb] * u[a]))
     return J
 
 
-def collision_matrix(rates, s_m: float, rho0: float = 1.0, u0=(0.0, 0.0), B0=(0.0, 0.0)) -> np.ndarray:
-    """Linear map x -> x* of one collision, 19 x 19 (real)."""
+def collision_matrix(rates, s_m: float, rho0: float = 1.0, u0=(0.0, 0.0), B0=(0.0, 0.0),
+                     qg: int = 5) -> np.ndarray:
+    """Linear map x -> x* of one collision, (9 + 2 qg) square (real)."""
     rates = np.asarray(rates, dtype=np.float64)
-    K = np.zeros((NQ, NQ))
+    nq = 9 + 2 * qg
+    K = np.zeros((nq, nq))
     K[:9, :9] = np.linalg.solve(_T_PRINTED, np.diag(rates) @ _T_PRINTED)
-    K[9:, 9:] = s_m * np.eye(10)
-    Jeq = equilibrium_jacobian(rho0, u0, B0) @ _macro_jacobian()
-    return np.eye(NQ) - K @ (np.eye(NQ) - Jeq)
+    K[9:, 9:] = s_m * np.eye(2 * qg)
+    Jeq = equilibrium_jacobian(rho0, u0, B0, qg) @ _macro_jacobian(qg)
+    return np.eye(nq) - K @ (np.eye(nq) - Jeq)
 
 
-def streaming_phase(k) -> np.ndarray:
-    """diag(exp(-i k.c_q)) for the 19 populations."""
+def streaming_phase(k, qg: int = 5) -> np.ndarray:
+    """diag(exp(-i k.c_q)) for the 9 + 2 qg populations."""
     kx, ky = float(k[0]), float(k[1])
-    cx = np.concatenate([_CX, _CX[:5], _CX[:5]])
-    cy = np.concatenate([_CY, _CY[:5], _CY[:5]])
+    cx = np.concatenate([_CX, _CX[:qg], _CX[:qg]])
+    cy = np.concatenate([_CY, _CY[:qg], _CY[:qg]])
     return np.diag(np.exp(-1j * (kx * cx + ky * cy)))
 
 
-def step_matrix(k, rates, s_m: float, rho0: float = 1.0, u0=(0.0, 0.0), B0=(0.0, 0.0)) -> np.ndarray:
+def step_matrix(k, rates, s_m: float, rho0: float = 1.0, u0=(0.0, 0.0), B0=(0.0, 0.0), qg: int = 5) -> np.ndarray:
     """G(k): Fourier amplitude at wave vector k after one collide-stream step."""
-    return streaming_phase(k) @ collision_matrix(rates, s_m, rho0, u0, B0)
+    return streaming_phase(k, qg) @ collision_matrix(rates, s_m, rho0, u0, B0, qg)
 
 
 def rates_from(nu: float, eta: float, s5=None, s6=None, s7=None, s8=None):
