@@ -26,8 +26,10 @@
  *    (row pitch nx, plane stride nx*ny).  Populations are ordered
  *    f_0..f_8, g_x0..g_x4, g_y0..g_y4 (19 planes), with the D2Q9
  *    velocities c_x = {0,1,0,-1,0,1,-1,-1,1}, c_y = {0,0,1,0,-1,1,1,-1,-1}
- *    of Sec. 2 (g uses the first five).  "State at time t" means the
- *    post-streaming populations the next collision consumes.
+ *    of Sec. 2 (g uses the first five); with mag_lattice = LBM_MAG_D2Q9
+ *    f_0..f_8, g_x0..g_x8, g_y0..g_y8 (27 planes, g on all nine).  "State
+ *    at time t" means the post-streaming populations the next collision
+ *    consumes.
  *  - Threading: a context is used by one host thread at a time.
  */
 #ifndef LBMHD_H
@@ -95,6 +97,14 @@ extern "C" {
                                    products; LBM_SCHED_FUSED with LBM_STENCIL_ISO9
                                    or LBM_STENCIL_CENTRAL5 only                   */
 
+/* Lattice of the vector distribution g. */
+#define LBM_MAG_D2Q5 0  /* the first five D2Q9 velocities, weights (1/3, 1/6 x4)   */
+#define LBM_MAG_D2Q9 1  /* all nine (Sec. 2's own choice, MagTMatrix / MagMomentEq;
+                           with one rate s_m the moment-space collision equals
+                           relaxation of g to the D2Q9 geq); LBM_SCHED_FUSED,
+                           LBM_CLOSURE_ANALYTIC or _FULL, a stencil gradient and
+                           FP64 or FP32 storage only                              */
+
 typedef struct lbm_ctx lbm_ctx;
 
 /* Run parameters, lattice units.  Rates follow Sec. 2: s3 = s4 = 2/(6 nu + 1)
@@ -111,6 +121,8 @@ typedef struct {
   int32_t dtype;           /* LBM_FP64, LBM_FP32, LBM_FP16 or LBM_BF16        */
   int32_t schedule;        /* LBM_SCHED_*                                     */
   int32_t closure;         /* LBM_CLOSURE_*                                   */
+  int32_t mag_lattice;     /* LBM_MAG_*                                       */
+  int32_t reserved;        /* must be 0                                       */
   double rho0;             /* reference density of the FP32 deviations, > 0   */
   double bref_x, bref_y;   /* reference field of the FP32 g deviations (finite;
                               the run's mean field, e.g. (B0, 0) for the jet) */
@@ -193,12 +205,13 @@ int lbm_get_time(const lbm_ctx* ctx, int64_t* t_out);
  * caller owned).  Sec. 2: rho = sum f_i, rho u = sum c_i f_i, B = sum g_i. */
 int lbm_moments(lbm_ctx* ctx, double* out_dev);
 
-/* Copy the populations of the state at time t to out_dev as 19 FP64 planes
- * in natural layout (19*nx*ny doubles, caller owned). */
+/* Copy the populations of the state at time t to out_dev as P FP64 planes
+ * in natural layout (P*nx*ny doubles, caller owned), P = 19 (D2Q5 g) or 27
+ * (D2Q9 g). */
 int lbm_get_state(lbm_ctx* ctx, double* out_dev);
 
-/* Replace the state by 19 FP64 planes in natural layout (rounded to the
- * storage precision) and set the time to t >= 0. */
+/* Replace the state by P (19 or 27) FP64 planes in natural layout (rounded
+ * to the storage precision) and set the time to t >= 0. */
 int lbm_set_state(lbm_ctx* ctx, const double* in_dev, int64_t t);
 
 /* Compute the diagnostics of the state at time t into *out_host (host

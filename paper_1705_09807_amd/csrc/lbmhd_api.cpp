@@ -69,6 +69,14 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     return fail(LBM_EINVAL, "the density-gradient closure runs with LBM_SCHED_FUSED and a stencil gradient only");
   if (p->closure == LBM_CLOSURE_LEARNED && p->schedule != LBM_SCHED_FUSED)
     return fail(LBM_EINVAL, "the learned closure runs with LBM_SCHED_FUSED only");
+  if (p->mag_lattice != LBM_MAG_D2Q5 && p->mag_lattice != LBM_MAG_D2Q9)
+    return fail(LBM_EINVAL, "mag_lattice must be LBM_MAG_D2Q5 or LBM_MAG_D2Q9");
+  if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+  if (p->mag_lattice == LBM_MAG_D2Q9 &&
+      (p->schedule != LBM_SCHED_FUSED || p->closure == LBM_CLOSURE_LEARNED ||
+       p->grad_stencil >= LBM_STENCIL_LOCAL_ISO9 || (p->dtype != LBM_FP64 && p->dtype != LBM_FP32)))
+    return fail(LBM_EINVAL, "the D2Q9 vector distribution runs with LBM_SCHED_FUSED, a stencil gradient, "
+                            "the analytic or density-gradient closure and FP64 or FP32 storage");
   if (!finite_pos(p->rho0)) return fail(LBM_EINVAL, "rho0 must be finite and > 0");
   if (!std::isfinite(p->bref_x) || !std::isfinite(p->bref_y)) return fail(LBM_EINVAL, "bref must be finite");
   if (L) {
@@ -80,6 +88,7 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     L->dtype = p->dtype;
     L->schedule = p->schedule;
     L->stencil = p->grad_stencil;
+    L->qg = p->mag_lattice == LBM_MAG_D2Q9 ? 9 : 5;
     L->learned = p->closure == LBM_CLOSURE_LEARNED;
     L->full = p->closure == LBM_CLOSURE_FULL;
     for (double& r : L->rate) r = 0.0;
@@ -113,7 +122,7 @@ extern "C" {
 
 size_t lbm_state_bytes(const lbm_params* p) {
   if (check_params(p, nullptr) != LBM_OK) return 0;
-  return lbm::state_bytes(p->nx, p->ny, p->dtype, p->schedule);
+  return lbm::state_bytes(p->nx, p->ny, p->dtype, p->schedule, p->mag_lattice == LBM_MAG_D2Q9 ? 9 : 5);
 }
 
 size_t lbm_work_bytes(const lbm_params* p) {

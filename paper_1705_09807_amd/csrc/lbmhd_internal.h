@@ -11,7 +11,8 @@
 
 namespace lbm {
 
-constexpr int kQ = 19;            // 9 (f) + 5 (g_x) + 5 (g_y) populations per cell
+constexpr int kQ = 19;            // 9 (f) + 5 (g_x) + 5 (g_y) populations per cell (D2Q5 g;
+                                  // 9 + 9 + 9 with the D2Q9 vector distribution)
 constexpr int kDiagVals = 12;     // accumulators of the diagnostics reduction
 constexpr int kDiagBlocksMax = 2048;
 
@@ -22,6 +23,7 @@ struct Launch {
   int dtype = LBM_FP64;
   int schedule = LBM_SCHED_FUSED;
   int stencil = LBM_STENCIL_ISO9;
+  int qg = 5;                     // velocities of the vector distribution: 5 (D2Q5) or 9 (D2Q9)
   double rate[9] = {0};           // MRT rates s0..s8 (s0..s2 = 0)
   double sm = 0;                  // magnetic SRT rate
   double k2 = 0;                  // closure_scale * Delta^2 / 12
@@ -47,7 +49,7 @@ struct Launch {
 // Layout helpers (host).
 size_t storage_bytes(int dtype);
 int64_t plane_elems(int nx, int ny);
-size_t state_bytes(int nx, int ny, int dtype, int schedule);
+size_t state_bytes(int nx, int ny, int dtype, int schedule, int qg);
 // Work layout for the given geometry; returns total bytes and fills offsets.
 size_t work_layout(Launch& L);
 

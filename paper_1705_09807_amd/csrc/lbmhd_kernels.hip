@@ -39,7 +39,9 @@ namespace lbm {
 
 // ---------------------------------------------------------------------------
 // Lattice (Sec. 2): D2Q9 velocities; the vector distribution uses the first
-// five (D2Q5).  Population q: f_q (q < 9), g_x,q-9 (9..13), g_y,q-14 (14..18).
+// QG of them: five (D2Q5, the default) or all nine (D2Q9, Sec. 2's own
+// lattice for g).  Population q: f_q (q < 9), g_x,q-9 (9 .. 8+QG),
+// g_y,q-9-QG (9+QG .. 8+2QG); NPOP = 9 + 2 QG populations per cell.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int cx9(int i) {
   return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
@@ -50,19 +52,29 @@ __host__ __device__ constexpr int cy9(int i) {
 __host__ __device__ constexpr int opp9(int i) {
   return i == 0 ? 0 : (i < 5 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
 }
-__host__ __device__ constexpr int qbase(int q) { return q < 9 ? q : (q < 14 ? q - 9 : q - 14); }
-__host__ __device__ constexpr int qcx(int q) { return cx9(qbase(q)); }
-__host__ __device__ constexpr int qcy(int q) { return cy9(qbase(q)); }
+template <int QG> constexpr int kPop = 9 + 2 * QG;
+template <int QG = 5>
+__host__ __device__ constexpr int qbase(int q) { return q < 9 ? q : (q < 9 + QG ? q - 9 : q - 9 - QG); }
+template <int QG = 5>
+__host__ __device__ constexpr int qcx(int q) { return cx9(qbase<QG>(q)); }
+template <int QG = 5>
+__host__ __device__ constexpr int qcy(int q) { return cy9(qbase<QG>(q)); }
+template <int QG = 5>
 __host__ __device__ constexpr int qopp(int q) {
-  return q < 9 ? opp9(q) : (q < 14 ? 9 + opp9(q - 9) : 14 + opp9(q - 14));
+  return q < 9 ? opp9(q) : (q < 9 + QG ? 9 + opp9(q - 9) : 9 + QG + opp9(q - 9 - QG));
 }
-// D2Q9 weights (rest deviation of f) and D2Q5 weights of the vector distribution.
+// D2Q9 weights (rest deviation of f, and g on D2Q9) and D2Q5 weights of the
+// vector distribution.
 __host__ __device__ constexpr double w9(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
 __host__ __device__ constexpr double w5(int i) { return i == 0 ? 1.0 / 3.0 : 1.0 / 6.0; }
+template <int QG>
+__host__ __device__ constexpr double wg(int i) { return QG == 5 ? w5(i) : w9(i); }
 
 static_assert(opp9(1) == 3 && opp9(2) == 4 && opp9(3) == 1 && opp9(4) == 2, "opposites");
 static_assert(opp9(5) == 7 && opp9(6) == 8 && opp9(7) == 5 && opp9(8) == 6, "opposites");
 static_assert(qcx(10) == 1 && qcy(16) == 1 && qopp(15) == 17, "vector planes");
+static_assert(qcx<9>(14) == 1 && qcy<9>(20) == 1 && qopp<9>(23) == 25 && qopp<9>(14) == 16, "D2Q9 vector planes");
+static_assert(kPop<5> == kQ, "D2Q5 population count");
 
 template <typename S> struct ComputeOf { using type = float; };
 template <> struct ComputeOf<double> { using type = double; };
@@ -134,15 +146,25 @@ struct Mom {
 // deviations f_i - w_i rho0 and g_i - w'_i B_ref (sum_i w_i = sum_i w'_i = 1,
 // sum_i w_i c_i = 0).  Fixed summation order: every kernel gets bit-identical
 // moments for a cell.
-template <typename C>
-__device__ __forceinline__ Mom<C> moments19(const C v[kQ]) {
+template <int QG, typename C>
+__device__ __forceinline__ Mom<C> moments_of(const C* v) {
   Mom<C> m;
   m.drho = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
   m.mx = ((v[1] - v[3]) + (v[5] - v[6])) + (v[8] - v[7]);
   m.my = ((v[2] - v[4]) + (v[5] - v[7])) + (v[6] - v[8]);
-  m.dbx = ((v[9] + v[10]) + (v[11] + v[12])) + v[13];
-  m.dby = ((v[14] + v[15]) + (v[16] + v[17])) + v[18];
+  if constexpr (QG == 5) {
+    m.dbx = ((v[9] + v[10]) + (v[11] + v[12])) + v[13];
+    m.dby = ((v[14] + v[15]) + (v[16] + v[17])) + v[18];
+  } else {
+    m.dbx = (((v[9] + v[10]) + (v[11] + v[12])) + ((v[13] + v[14]) + (v[15] + v[16]))) + v[17];
+    m.dby = (((v[18] + v[19]) + (v[20] + v[21])) + ((v[22] + v[23]) + (v[24] + v[25]))) + v[26];
+  }
   return m;
+}
+
+template <typename C>
+__device__ __forceinline__ Mom<C> moments19(const C v[kQ]) {
+  return moments_of<5>(v);
 }
 
 // One collision of the 19 populations of a cell (Sec. 2, Sec. 3).
@@ -152,12 +174,14 @@ __device__ __forceinline__ Mom<C> moments19(const C v[kQ]) {
 //     rate 0, so only rows 3..8 are formed, and T^-1 = T^T diag(1/|row|^2).
 //     In deviation storage M(w rho0) = (rho0, 0, ..., 0, 5 rho0 / 3) shifts
 //     only M8's equilibrium.
-//  g: g* = g - s_m (g - g_eq), g_eq_i = w'_i (B + 3 [(c.u) B - (c.B) u]) on D2Q5,
-//     which is g_eq_ix = w'_i (B_x - 3 c_iy E), g_eq_iy = w'_i (B_y + 3 c_ix E)
-//     with E = (m_x B_y - m_y B_x) / rho + eps.
-template <typename C>
-__device__ __forceinline__ void collide19(C v[kQ], const Mom<C>& m, const Closure<C>& cl,
-                                          const Rates<C>& r) {
+//  g: g* = g - s_m (g - g_eq), g_eq_i = w'_i (B + 3 [(c.u) B - (c.B) u]) on D2Q5
+//     or D2Q9, which is g_eq_ix = w'_i (B_x - 3 c_iy E), g_eq_iy = w'_i (B_y +
+//     3 c_ix E) with E = (m_x B_y - m_y B_x) / rho + eps.  On D2Q9 this is the
+//     moment-space SRT of MagTMatrix / MagMomentEq: with one rate for every
+//     moment, relaxing T_m g towards N^eq and mapping back is relaxing g
+//     towards T_m^-1 N^eq, the D2Q9 geq.
+template <int QG, typename C>
+__device__ __forceinline__ void collide_q(C* v, const Mom<C>& m, const Closure<C>& cl, const Rates<C>& r) {
   const C rho = r.rho0 + m.drho;
   const C ir = C(1) / rho;
   const C mx = m.mx, my = m.my, bx = r.bx0 + m.dbx, by = r.by0 + m.dby;
@@ -198,13 +222,18 @@ __device__ __forceinline__ void collide19(C v[kQ], const Mom<C>& m, const Closur
   const C E = (mx * by - my * bx) * ir + cl.eps;
   const C E3 = C(3) * E;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    const C wi = C(w5(i));
+  for (int i = 0; i < QG; ++i) {
+    const C wi = C(wg<QG>(i));
     const C gx = wi * (m.dbx - C(cy9(i)) * E3);
     const C gy = wi * (m.dby + C(cx9(i)) * E3);
     v[9 + i] -= r.sm * (v[9 + i] - gx);
-    v[14 + i] -= r.sm * (v[14 + i] - gy);
+    v[9 + QG + i] -= r.sm * (v[9 + QG + i] - gy);
   }
+}
+
+template <typename C>
+__device__ __forceinline__ void collide19(C v[kQ], const Mom<C>& m, const Closure<C>& cl, const Rates<C>& r) {
+  collide_q<5>(v, m, cl, r);
 }
 
 // Closure gradients from local non-equilibrium moments (LOCAL stencils),
@@ -300,35 +329,35 @@ __device__ __forceinline__ Cols cols_of(int x, int nx) {
 }
 
 // f_q(x, y) = src[q][x - c_q][y - c_q] for one cell.
-template <typename S, typename C>
+template <typename S, typename C, int QG = 5>
 __device__ __forceinline__ void pull_cell(const S* __restrict__ src, int64_t plane, const Rows& rw, const Cols& cl,
-                                          C v[kQ]) {
+                                          C* v) {
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const uint32_t xo = qcx(q) > 0 ? cl.w : (qcx(q) < 0 ? cl.e : cl.c);
-    const uint32_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
+  for (int q = 0; q < kPop<QG>; ++q) {
+    const uint32_t xo = qcx<QG>(q) > 0 ? cl.w : (qcx<QG>(q) < 0 ? cl.e : cl.c);
+    const uint32_t yo = qcy<QG>(q) > 0 ? rw.s : (qcy<QG>(q) < 0 ? rw.n : rw.c);
     v[q] = decode<C>(*at(src + q * plane, yo + xo));
   }
 }
 
 // Two horizontally adjacent cells x, x + 1 (x even, nx even): the c_x = 0
 // populations come in one aligned two-element load.
-template <typename S, typename C>
+template <typename S, typename C, int QG = 5>
 __device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t plane, int nx, const Rows& rw, int x,
-                                          C a[kQ], C b[kQ]) {
+                                          C* a, C* b) {
   using V2 = Vec2<S>;
   const uint32_t es = uint32_t(sizeof(S));
   const uint32_t xw = uint32_t(x == 0 ? nx - 1 : x - 1) * es, x0 = uint32_t(x) * es, x1 = x0 + es;
   const uint32_t x2 = uint32_t(x + 2 == nx ? 0 : x + 2) * es;
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const uint32_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
+  for (int q = 0; q < kPop<QG>; ++q) {
+    const uint32_t yo = qcy<QG>(q) > 0 ? rw.s : (qcy<QG>(q) < 0 ? rw.n : rw.c);
     const S* pq = src + q * plane;
-    if (qcx(q) == 0) {
+    if (qcx<QG>(q) == 0) {
       const V2 t = *reinterpret_cast<const V2*>(at(pq, yo + x0));
       a[q] = decode<C>(t.x);
       b[q] = decode<C>(t.y);
-    } else if (qcx(q) > 0) {
+    } else if (qcx<QG>(q) > 0) {
       a[q] = decode<C>(*at(pq, yo + xw));
       b[q] = decode<C>(*at(pq, yo + x0));
     } else {
@@ -340,7 +369,7 @@ __device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t pla
 
 // Closure off (Delta = 0).  One row segment of 2 * 128 cells per workgroup,
 // two cells per thread, aligned two-element stores.  Requires nx even.
-template <typename S, typename C, bool NT>
+template <typename S, typename C, bool NT, int QG>
 __global__ void __launch_bounds__(128)
 k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
   using nv2 = Vec2<S>;
@@ -348,20 +377,20 @@ k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
   const int y = blockIdx.y;
   if (x >= nx) return;
   const Rows rw = rows_of<S>(y, nx, ny);
-  C a[kQ], b[kQ];
-  pull_pair<S, C>(src, plane, nx, rw, x, a, b);
+  C a[kPop<QG>], b[kPop<QG>];
+  pull_pair<S, C, QG>(src, plane, nx, rw, x, a, b);
   const Closure<C> cl = {C(0), C(0), C(0), C(0)};
   {
-    const Mom<C> m = moments19(a);
-    collide19(a, m, cl, r);
+    const Mom<C> m = moments_of<QG>(a);
+    collide_q<QG>(a, m, cl, r);
   }
   {
-    const Mom<C> m = moments19(b);
-    collide19(b, m, cl, r);
+    const Mom<C> m = moments_of<QG>(b);
+    collide_q<QG>(b, m, cl, r);
   }
   const uint32_t off = rw.c + uint32_t(x) * uint32_t(sizeof(S));
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
+  for (int q = 0; q < kPop<QG>; ++q) {
     nv2 t;
     t.x = encode<S>(a[q]);
     t.y = encode<S>(b[q]);
@@ -370,7 +399,7 @@ k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
 }
 
 // Closure off, any nx: one cell per thread, row segments of 256 cells.
-template <typename S, typename C, bool NT>
+template <typename S, typename C, bool NT, int QG>
 __global__ void __launch_bounds__(256)
 k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
   const int x = blockIdx.x * 256 + threadIdx.x;
@@ -378,13 +407,13 @@ k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
   if (x >= nx) return;
   const Rows rw = rows_of<S>(y, nx, ny);
   const Cols cl = cols_of<S>(x, nx);
-  C v[kQ];
-  pull_cell<S, C>(src, plane, rw, cl, v);
-  const Mom<C> m = moments19(v);
+  C v[kPop<QG>];
+  pull_cell<S, C, QG>(src, plane, rw, cl, v);
+  const Mom<C> m = moments_of<QG>(v);
   const Closure<C> zero = {C(0), C(0), C(0), C(0)};
-  collide19(v, m, zero, r);
+  collide_q<QG>(v, m, zero, r);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, rw.c + cl.c), encode<S>(v[q]));
+  for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * plane, rw.c + cl.c), encode<S>(v[q]));
 }
 
 // Closure on.  A workgroup of W + 64 lanes owns the column strip
@@ -404,7 +433,7 @@ k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
 // closure keeps the filtered-density gradient terms.
 enum { kClosurePlain = 0, kClosureCorr = 1, kClosureFull = 2 };
 
-template <typename S, typename C, int W, int STENCIL, bool NT, int MODE>
+template <typename S, typename C, int W, int STENCIL, bool NT, int MODE, int QG>
 __global__ void __launch_bounds__(W + 64)
 k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry, Rates<C> r,
             const float* __restrict__ corr) {
@@ -428,7 +457,7 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
   const int y1 = min(y0 + ry, ny);
 
   auto put = [&](int slot, const C* v) {
-    const Mom<C> m = moments19(v);
+    const Mom<C> m = moments_of<QG>(v);
     ring[slot][0][widx] = m.mx;
     ring[slot][1][widx] = m.my;
     ring[slot][2][widx] = m.dbx;
@@ -437,20 +466,20 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
   };
   auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
 
-  C cur[kQ], nxt[kQ], nn[kQ];
+  C cur[kPop<QG>], nxt[kPop<QG>], nn[kPop<QG>];
   if (loader) {
-    pull_cell<S, C>(src, plane, rows_of<S>(wrapy(y0 - 1), nx, ny), cx, nn);
+    pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y0 - 1), nx, ny), cx, nn);
     if (writer) put(0, nn);
-    pull_cell<S, C>(src, plane, rows_of<S>(y0, nx, ny), cx, cur);
+    pull_cell<S, C, QG>(src, plane, rows_of<S>(y0, nx, ny), cx, cur);
     if (writer) put(1, cur);
-    pull_cell<S, C>(src, plane, rows_of<S>(wrapy(y0 + 1), nx, ny), cx, nxt);
+    pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y0 + 1), nx, ny), cx, nxt);
     if (writer) put(2, nxt);
   }
   __syncthreads();
   for (int y = y0; y < y1; ++y) {
     const int s = y - y0 + 1;                 // ring slot of row y is s & 3
     const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
-    if (more && loader) pull_cell<S, C>(src, plane, rows_of<S>(wrapy(y + 2), nx, ny), cx, nn);
+    if (more && loader) pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y + 2), nx, ny), cx, nn);
     if (valid) {
       const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
       C gr[NF][2];
@@ -460,13 +489,14 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
                             ring[sn][k][l + 1], ring[sn][k][l - 1], ring[ss][k][l + 1], ring[ss][k][l - 1], gr[k][0],
                             gr[k][1]);
       }
-      const Mom<C> m = moments19(cur);
+      const Mom<C> m = moments_of<QG>(cur);
       const C ir = C(1) / (r.rho0 + m.drho);
       Closure<C> cl;
       if constexpr (MODE == kClosureFull) {
         cl = closure_terms_full(gr, m.mx, m.my, r.bx0 + m.dbx, r.by0 + m.dby, ir, r.k2);
       } else {
-        if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9) local_gradients(cur, m, r, gr[1][0] - gr[0][1], gr);
+        if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9 && QG == 5)
+          local_gradients(cur, m, r, gr[1][0] - gr[0][1], gr);
         cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0], gr[3][1], ir,
                            r.k2);
       }
@@ -478,15 +508,15 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
         cl.tau_s += txx + tyy;
         cl.eps += eps;
       }
-      collide19(cur, m, cl, r);
+      collide_q<QG>(cur, m, cl, r);
       const uint32_t off = uint32_t(y) * uint32_t(nx) * uint32_t(sizeof(S)) + cx.c;
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) store<NT>(at(dst + q * plane, off), encode<S>(cur[q]));
+      for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * plane, off), encode<S>(cur[q]));
     }
     if (more && writer) put((s + 2) & 3, nn);
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
+    for (int q = 0; q < kPop<QG>; ++q) {
       cur[q] = nxt[q];
       nxt[q] = nn[q];
     }
@@ -668,10 +698,11 @@ constexpr int kLayoutNatural = 0;
 constexpr int kLayoutAAOdd = 1;
 constexpr int kLayoutPull = 2;
 
+template <int QG = 5>
 __device__ __forceinline__ int64_t natural_index(int q, int x, int y, int nx, int ny, int64_t plane, int layout) {
   if (layout == kLayoutNatural) return q * plane + (int64_t)y * nx + x;
-  const int xs = wrap1(x - qcx(q), nx), ys = wrap1(y - qcy(q), ny);
-  return (layout == kLayoutAAOdd ? qopp(q) : q) * plane + (int64_t)ys * nx + xs;
+  const int xs = wrap1(x - qcx<QG>(q), nx), ys = wrap1(y - qcy<QG>(q), ny);
+  return (layout == kLayoutAAOdd ? qopp<QG>(q) : q) * plane + (int64_t)ys * nx + xs;
 }
 
 // Rest values subtracted from the stored populations: w_q rho0 for f,
@@ -680,8 +711,9 @@ struct RestRef {
   double rho0, bx0, by0;
 };
 
+template <int QG = 5>
 __device__ __forceinline__ double rest_value(int q, const RestRef& ref) {
-  return q < 9 ? w9(q) * ref.rho0 : (q < 14 ? w5(q - 9) * ref.bx0 : w5(q - 14) * ref.by0);
+  return q < 9 ? w9(q) * ref.rho0 : (q < 9 + QG ? wg<QG>(q - 9) * ref.bx0 : wg<QG>(q - 9 - QG) * ref.by0);
 }
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output number counter + 1 of
@@ -695,7 +727,7 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t counte
 
 // Unfiltered equilibria feq / geq (Sec. 2) of one cell's fields, evaluated in
 // FP64 and rounded to the storage type.
-template <typename S>
+template <typename S, int QG = 5>
 __device__ __forceinline__ void write_equilibrium(S* __restrict__ base, int x, int y, int nx, int ny, int64_t plane,
                                                   int layout, const RestRef& ref, double rho, double ux, double uy,
                                                   double bx, double by) {
@@ -706,21 +738,22 @@ __device__ __forceinline__ void write_equilibrium(S* __restrict__ base, int x, i
     const double cb = cx9(i) * bx + cy9(i) * by;
     const double c2 = double(cx9(i) * cx9(i) + cy9(i) * cy9(i));
     const double feq = w9(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * w9(i) * (0.5 * bsq * c2 - cb * cb);
-    base[natural_index(i, x, y, nx, ny, plane, layout)] = encode<S>(feq - rest_value(i, ref));
+    base[natural_index<QG>(i, x, y, nx, ny, plane, layout)] = encode<S>(feq - rest_value<QG>(i, ref));
   }
 #pragma unroll
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < QG; ++i) {
     const double cu = cx9(i) * ux + cy9(i) * uy;
     const double cb = cx9(i) * bx + cy9(i) * by;
-    const double gx = w5(i) * (bx + 3.0 * (cu * bx - cb * ux));
-    const double gy = w5(i) * (by + 3.0 * (cu * by - cb * uy));
-    base[natural_index(9 + i, x, y, nx, ny, plane, layout)] = encode<S>(gx - rest_value(9 + i, ref));
-    base[natural_index(14 + i, x, y, nx, ny, plane, layout)] = encode<S>(gy - rest_value(14 + i, ref));
+    const double gx = wg<QG>(i) * (bx + 3.0 * (cu * bx - cb * ux));
+    const double gy = wg<QG>(i) * (by + 3.0 * (cu * by - cb * uy));
+    base[natural_index<QG>(9 + i, x, y, nx, ny, plane, layout)] = encode<S>(gx - rest_value<QG>(9 + i, ref));
+    base[natural_index<QG>(9 + QG + i, x, y, nx, ny, plane, layout)] =
+        encode<S>(gy - rest_value<QG>(9 + QG + i, ref));
   }
 }
 
 // Kelvin-Helmholtz double shear layer at the unfiltered equilibria.
-template <typename S>
+template <typename S, int QG>
 __global__ void __launch_bounds__(256)
 k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestRef ref, lbm_kh_params kh) {
   const int x = blockIdx.x * 64 + threadIdx.x;
@@ -732,11 +765,11 @@ k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestR
   const uint64_t z = splitmix64_at(kh.seed, (uint64_t)y * (uint64_t)nx + (uint64_t)x);
   const double xi = 2.0 * (double(z >> 11) * 0x1.0p-53) - 1.0;
   const double uy = kh.pert_amp_over_U0 * kh.U0 * sin(2.0 * M_PI * xx / double(nx)) + kh.noise_amp * xi;
-  write_equilibrium<S>(base, x, y, nx, ny, plane, layout, ref, kh.rho0, ux, uy, kh.B0, 0.0);
+  write_equilibrium<S, QG>(base, x, y, nx, ny, plane, layout, ref, kh.rho0, ux, uy, kh.B0, 0.0);
 }
 
 // The magnetized jet of Sec. 4 at the unfiltered equilibria.
-template <typename S>
+template <typename S, int QG>
 __global__ void __launch_bounds__(256)
 k_init_sech2(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestRef ref, lbm_sech2_params jet) {
   const int x = blockIdx.x * 64 + threadIdx.x;
@@ -749,11 +782,11 @@ k_init_sech2(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, Re
   const double ux = jet.pert * jet.U0 * sin(ky * yf);
   const double bx = jet.pert * jet.B0 * sin(ky * yf);
   const double by = jet.B0 + jet.pert * jet.B0 * sin(kx * xf);
-  write_equilibrium<S>(base, x, y, nx, ny, plane, layout, ref, jet.rho0, ux, uy, bx, by);
+  write_equilibrium<S, QG>(base, x, y, nx, ny, plane, layout, ref, jet.rho0, ux, uy, bx, by);
 }
 
 // Equilibria of given fields: 5 FP64 planes rho, m_x, m_y, B_x, B_y.
-template <typename S>
+template <typename S, int QG>
 __global__ void __launch_bounds__(256)
 k_init_moments(S* __restrict__ base, const double* __restrict__ mom, int nx, int ny, int64_t plane, int layout,
                RestRef ref) {
@@ -762,11 +795,11 @@ k_init_moments(S* __restrict__ base, const double* __restrict__ mom, int nx, int
   if (x >= nx || y >= ny) return;
   const int64_t n = (int64_t)nx * ny, c = (int64_t)y * nx + x;
   const double rho = mom[c];
-  write_equilibrium<S>(base, x, y, nx, ny, plane, layout, ref, rho, mom[n + c] / rho, mom[2 * n + c] / rho,
+  write_equilibrium<S, QG>(base, x, y, nx, ny, plane, layout, ref, rho, mom[n + c] / rho, mom[2 * n + c] / rho,
                        mom[3 * n + c], mom[4 * n + c]);
 }
 
-template <typename S>
+template <typename S, int QG>
 __global__ void __launch_bounds__(256)
 k_get_state(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, int layout,
             RestRef ref) {
@@ -775,13 +808,13 @@ k_get_state(const S* __restrict__ base, double* __restrict__ out, int nx, int ny
   if (x >= nx || y >= ny) return;
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const double v = decode<double>(base[natural_index(q, x, y, nx, ny, plane, layout)]);
-    out[q * n + c0] = v + rest_value(q, ref);
+  for (int q = 0; q < kPop<QG>; ++q) {
+    const double v = decode<double>(base[natural_index<QG>(q, x, y, nx, ny, plane, layout)]);
+    out[q * n + c0] = v + rest_value<QG>(q, ref);
   }
 }
 
-template <typename S>
+template <typename S, int QG>
 __global__ void __launch_bounds__(256)
 k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny, int64_t plane, int layout,
             RestRef ref) {
@@ -790,29 +823,29 @@ k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny,
   if (x >= nx || y >= ny) return;
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
+  for (int q = 0; q < kPop<QG>; ++q) {
     const double v = in[q * n + c0];
-    base[natural_index(q, x, y, nx, ny, plane, layout)] = encode<S>(v - rest_value(q, ref));
+    base[natural_index<QG>(q, x, y, nx, ny, plane, layout)] = encode<S>(v - rest_value<QG>(q, ref));
   }
 }
 
 // rho, m_x, m_y, B_x, B_y in FP64 (5 dense planes).  With mark_nonfinite,
 // rho is set to NaN where any population is NaN or infinite.
-template <typename S>
+template <typename S, int QG>
 __global__ void __launch_bounds__(256)
 k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, int layout,
               RestRef ref, bool mark_nonfinite) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= nx || y >= ny) return;
-  double v[kQ];
+  double v[kPop<QG>];
   bool finite = true;
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    v[q] = decode<double>(base[natural_index(q, x, y, nx, ny, plane, layout)]);
+  for (int q = 0; q < kPop<QG>; ++q) {
+    v[q] = decode<double>(base[natural_index<QG>(q, x, y, nx, ny, plane, layout)]);
     finite = finite && isfinite(v[q]);
   }
-  const Mom<double> m = moments19(v);
+  const Mom<double> m = moments_of<QG>(v);
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
   out[c0] = (mark_nonfinite && !finite) ? __builtin_nan("") : ref.rho0 + m.drho;
   out[n + c0] = m.mx;
@@ -943,8 +976,8 @@ int64_t plane_elems(int nx, int ny) {
   return ((n + 1023) / 1024) * 1024 + 256;
 }
 
-size_t state_bytes(int nx, int ny, int dtype, int schedule) {
-  const size_t one = (size_t)kQ * (size_t)plane_elems(nx, ny) * storage_bytes(dtype);
+size_t state_bytes(int nx, int ny, int dtype, int schedule, int qg) {
+  const size_t one = (size_t)(9 + 2 * qg) * (size_t)plane_elems(nx, ny) * storage_bytes(dtype);
   return schedule == LBM_SCHED_FUSED ? 2 * one : one;
 }
 
@@ -977,12 +1010,23 @@ size_t work_layout(Launch& L) {
 }
 
 static dim3 tile_grid(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
+
+// Magnetic-lattice dispatch: f(std::integral_constant<int, QG>).  The D2Q9
+// vector distribution is built for FP64 and FP32 storage (the ABI rejects
+// the 16-bit types with it), so 16-bit storage instantiates D2Q5 only.
+template <typename S, typename F>
+static hipError_t by_lattice(const Launch& L, F&& f) {
+  if constexpr (sizeof(S) >= 4) {
+    if (L.qg == 9) return f(std::integral_constant<int, 9>{});
+  }
+  return f(std::integral_constant<int, 5>{});
+}
 static const dim3 kTile(64, 4);
 
 template <typename S>
 static S* buffer_at(const Launch& L, int64_t t) {
   S* base = static_cast<S*>(L.state);
-  if (L.schedule == LBM_SCHED_FUSED && (t & 1)) base += (size_t)kQ * (size_t)L.plane;
+  if (L.schedule == LBM_SCHED_FUSED && (t & 1)) base += (size_t)(9 + 2 * L.qg) * (size_t)L.plane;
   return base;
 }
 
@@ -1016,66 +1060,72 @@ static int fused_rows(int nx, int ny, int strip) {
 // Non-temporal stores pay off once the two population buffers no longer fit
 // in the 256 MB Infinity Cache; below that the next step re-reads them from it.
 static bool streaming_stores(const Launch& L) {
-  return 2.0 * double(kQ) * double(L.nx) * double(L.ny) * double(storage_bytes(L.dtype)) > 256.0e6;
+  return 2.0 * double(9 + 2 * L.qg) * double(L.nx) * double(L.ny) * double(storage_bytes(L.dtype)) > 256.0e6;
 }
 
-template <typename S, typename C, int W, bool NT, int MODE>
+template <typename S, typename C, int W, bool NT, int MODE, int QG>
 static void launch_les_k(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
   const int ry = fused_rows(L.nx, L.ny, W);
   const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
-  if constexpr (MODE != kClosureFull) {  // the density-gradient closure takes stencil gradients only
+  // the density-gradient closure and the D2Q9 vector distribution take
+  // stencil gradients only
+  if constexpr (MODE != kClosureFull && QG == 5) {
     if (L.stencil == LBM_STENCIL_LOCAL_ISO9) {
-      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_ISO9, NT, MODE>), g, dim3(W + 64), 0, L.stream, src,
-                         dst, L.nx, L.ny, L.plane, ry, r, corr);
+      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_ISO9, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream,
+                         src, dst, L.nx, L.ny, L.plane, ry, r, corr);
       return;
     }
     if (L.stencil == LBM_STENCIL_LOCAL_CENTRAL5) {
-      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_CENTRAL5, NT, MODE>), g, dim3(W + 64), 0, L.stream,
-                         src, dst, L.nx, L.ny, L.plane, ry, r, corr);
+      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_CENTRAL5, NT, MODE, QG>), g, dim3(W + 64), 0,
+                         L.stream, src, dst, L.nx, L.ny, L.plane, ry, r, corr);
       return;
     }
   }
   if (L.stencil == LBM_STENCIL_CENTRAL5)
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT, MODE>), g, dim3(W + 64), 0, L.stream, src,
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream, src,
                        dst, L.nx, L.ny, L.plane, ry, r, corr);
   else
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT, MODE>), g, dim3(W + 64), 0, L.stream, src, dst,
-                       L.nx, L.ny, L.plane, ry, r, corr);
+    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream, src,
+                       dst, L.nx, L.ny, L.plane, ry, r, corr);
 }
 
-template <typename S, typename C, int W, bool NT>
+template <typename S, typename C, int W, bool NT, int QG>
 static void launch_les(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
-  if (corr)
-    launch_les_k<S, C, W, NT, kClosureCorr>(L, src, dst, r, corr);
-  else if (L.full)
-    launch_les_k<S, C, W, NT, kClosureFull>(L, src, dst, r, nullptr);
+  if constexpr (QG == 5) {  // the learned correction is built for D2Q5
+    if (corr) {
+      launch_les_k<S, C, W, NT, kClosureCorr, QG>(L, src, dst, r, corr);
+      return;
+    }
+  }
+  if (L.full)
+    launch_les_k<S, C, W, NT, kClosureFull, QG>(L, src, dst, r, nullptr);
   else
-    launch_les_k<S, C, W, NT, kClosurePlain>(L, src, dst, r, nullptr);
+    launch_les_k<S, C, W, NT, kClosurePlain, QG>(L, src, dst, r, nullptr);
 }
 
-template <typename S, typename C, bool NT>
+template <typename S, typename C, bool NT, int QG>
 static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
   if (L.k2 == 0.0 && !corr) {
     if ((L.nx & 1) == 0)
-      hipLaunchKernelGGL((k_fused_dns_pair<S, C, NT>), dim3((L.nx + 255) / 256, L.ny), dim3(128), 0, L.stream, src,
-                         dst, L.nx, L.ny, L.plane, r);
+      hipLaunchKernelGGL((k_fused_dns_pair<S, C, NT, QG>), dim3((L.nx + 255) / 256, L.ny), dim3(128), 0, L.stream,
+                         src, dst, L.nx, L.ny, L.plane, r);
     else
-      hipLaunchKernelGGL((k_fused_dns<S, C, NT>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream, src, dst,
-                         L.nx, L.ny, L.plane, r);
+      hipLaunchKernelGGL((k_fused_dns<S, C, NT, QG>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream, src,
+                         dst, L.nx, L.ny, L.plane, r);
     return;
   }
   // Strip width: 512 lanes for wide FP32 grids (the LDS ring of a 512-lane
   // FP64 strip would exceed 64 KB), 256 otherwise, 64 for narrow grids.
   if constexpr (sizeof(C) == 4) {
     if (L.nx >= 1024) {
-      launch_les<S, C, 512, NT>(L, src, dst, r, corr);
+      launch_les<S, C, 512, NT, QG>(L, src, dst, r, corr);
       return;
     }
   }
   if (L.nx >= 256)
-    launch_les<S, C, 256, NT>(L, src, dst, r, corr);
+    launch_les<S, C, 256, NT, QG>(L, src, dst, r, corr);
   else
-    launch_les<S, C, 64, NT>(L, src, dst, r, corr);
+    launch_les<S, C, 64, NT, QG>(L, src, dst, r, corr);
 }
 
 template <typename S>
@@ -1124,11 +1174,14 @@ static hipError_t step_typed(const Launch& L, int64_t t) {
       if (e != hipSuccess) return e;
       corr = c;
     }
-    if (streaming_stores(L))
-      launch_fused<S, C, true>(L, src, dst, r, corr);
-    else
-      launch_fused<S, C, false>(L, src, dst, r, corr);
-    return hipGetLastError();
+    return by_lattice<S>(L, [&](auto qg) {
+      constexpr int QG = decltype(qg)::value;
+      if (streaming_stores(L))
+        launch_fused<S, C, true, QG>(L, src, dst, r, corr);
+      else
+        launch_fused<S, C, false, QG>(L, src, dst, r, corr);
+      return hipGetLastError();
+    });
   }
   S* A = static_cast<S*>(L.state);
   const bool odd = t & 1;
@@ -1209,9 +1262,11 @@ hipError_t launch_step(const Launch& L, int64_t t) {
 
 template <typename S>
 static hipError_t init_typed(const Launch& L, const lbm_kh_params& kh) {
-  hipLaunchKernelGGL((k_init_kh<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, 0), L.nx, L.ny,
-                     L.plane, layout_at(L, 0), rest_ref(L), kh);
-  return hipGetLastError();
+  return by_lattice<S>(L, [&](auto qg) {
+    hipLaunchKernelGGL((k_init_kh<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
+                       buffer_at<S>(L, 0), L.nx, L.ny, L.plane, layout_at(L, 0), rest_ref(L), kh);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh) {
@@ -1225,9 +1280,11 @@ hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh) {
 
 template <typename S>
 static hipError_t init_sech2_typed(const Launch& L, const lbm_sech2_params& jet) {
-  hipLaunchKernelGGL((k_init_sech2<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, 0), L.nx, L.ny,
-                     L.plane, layout_at(L, 0), rest_ref(L), jet);
-  return hipGetLastError();
+  return by_lattice<S>(L, [&](auto qg) {
+    hipLaunchKernelGGL((k_init_sech2<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
+                       buffer_at<S>(L, 0), L.nx, L.ny, L.plane, layout_at(L, 0), rest_ref(L), jet);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_init_sech2(const Launch& L, const lbm_sech2_params& jet) {
@@ -1241,9 +1298,11 @@ hipError_t launch_init_sech2(const Launch& L, const lbm_sech2_params& jet) {
 
 template <typename S>
 static hipError_t init_moments_typed(const Launch& L, int64_t t, const double* mom) {
-  hipLaunchKernelGGL((k_init_moments<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), mom, L.nx,
-                     L.ny, L.plane, layout_at(L, t), rest_ref(L));
-  return hipGetLastError();
+  return by_lattice<S>(L, [&](auto qg) {
+    hipLaunchKernelGGL((k_init_moments<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
+                       buffer_at<S>(L, t), mom, L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L));
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_init_moments(const Launch& L, int64_t t, const double* mom) {
@@ -1257,9 +1316,11 @@ hipError_t launch_init_moments(const Launch& L, int64_t t, const double* mom) {
 
 template <typename S>
 static hipError_t get_typed(const Launch& L, int64_t t, double* out) {
-  hipLaunchKernelGGL((k_get_state<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), out, L.nx,
-                     L.ny, L.plane, layout_at(L, t), rest_ref(L));
-  return hipGetLastError();
+  return by_lattice<S>(L, [&](auto qg) {
+    hipLaunchKernelGGL((k_get_state<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
+                       buffer_at<S>(L, t), out, L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L));
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_get_state(const Launch& L, int64_t t, double* out) {
@@ -1273,9 +1334,11 @@ hipError_t launch_get_state(const Launch& L, int64_t t, double* out) {
 
 template <typename S>
 static hipError_t set_typed(const Launch& L, int64_t t, const double* in) {
-  hipLaunchKernelGGL((k_set_state<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), in, L.nx,
-                     L.ny, L.plane, layout_at(L, t), rest_ref(L));
-  return hipGetLastError();
+  return by_lattice<S>(L, [&](auto qg) {
+    hipLaunchKernelGGL((k_set_state<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
+                       buffer_at<S>(L, t), in, L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L));
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_set_state(const Launch& L, int64_t t, const double* in) {
@@ -1289,9 +1352,11 @@ hipError_t launch_set_state(const Launch& L, int64_t t, const double* in) {
 
 template <typename S>
 static hipError_t moments_typed(const Launch& L, int64_t t, double* out, bool mark) {
-  hipLaunchKernelGGL((k_moments_out<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), out,
-                     L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L), mark);
-  return hipGetLastError();
+  return by_lattice<S>(L, [&](auto qg) {
+    hipLaunchKernelGGL((k_moments_out<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
+                       buffer_at<S>(L, t), out, L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L), mark);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_moments(const Launch& L, int64_t t, double* out, bool mark_nonfinite) {

@@ -38,6 +38,8 @@ LBM_SCHED_AA_LAGGED = 2
 LBM_CLOSURE_ANALYTIC = 0
 LBM_CLOSURE_LEARNED = 1
 LBM_CLOSURE_FULL = 2
+LBM_MAG_D2Q5 = 0
+LBM_MAG_D2Q9 = 1
 
 LBM_MLP_FEATURES = 64
 LBM_MLP_OUTPUTS = 4
@@ -60,6 +62,7 @@ class LbmParams(ctypes.Structure):
         ("delta", ctypes.c_double), ("closure_scale", ctypes.c_double),
         ("grad_stencil", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("schedule", ctypes.c_int32), ("closure", ctypes.c_int32),
+        ("mag_lattice", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("rho0", ctypes.c_double),
         ("bref_x", ctypes.c_double), ("bref_y", ctypes.c_double),
     ]

@@ -15,17 +15,19 @@ _STENCILS = {"iso9": N.LBM_STENCIL_ISO9, "central5": N.LBM_STENCIL_CENTRAL5,
              "local_iso9": N.LBM_STENCIL_LOCAL_ISO9, "local_central5": N.LBM_STENCIL_LOCAL_CENTRAL5}
 _SCHEDULES = {"fused": N.LBM_SCHED_FUSED, "aa": N.LBM_SCHED_AA, "aa_lagged": N.LBM_SCHED_AA_LAGGED}
 _CLOSURES = {"analytic": N.LBM_CLOSURE_ANALYTIC, "learned": N.LBM_CLOSURE_LEARNED, "full": N.LBM_CLOSURE_FULL}
+_MAG = {"d2q5": N.LBM_MAG_D2Q5, "d2q9": N.LBM_MAG_D2Q9}
 
 
 def make_params(nx, ny, nu, eta, delta=0.0, closure_scale=1.0, s5=0.0, s6=0.0, s7=0.0, s8=0.0,
                 grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0, b_ref=(0.0, 0.0),
-                closure="analytic") -> N.LbmParams:
+                closure="analytic", mag_lattice="d2q5") -> N.LbmParams:
     return N.LbmParams(
         nx=int(nx), ny=int(ny), nu=float(nu), eta=float(eta),
         s5=float(s5 or 0.0), s6=float(s6 or 0.0), s7=float(s7 or 0.0), s8=float(s8 or 0.0),
         delta=float(delta), closure_scale=float(closure_scale),
         grad_stencil=_STENCILS[grad_stencil], dtype=_DTYPES[dtype],
-        schedule=_SCHEDULES[schedule], closure=_CLOSURES[closure], rho0=float(rho0),
+        schedule=_SCHEDULES[schedule], closure=_CLOSURES[closure], mag_lattice=_MAG[mag_lattice], reserved=0,
+        rho0=float(rho0),
         bref_x=float(b_ref[0]), bref_y=float(b_ref[1]))
 
 
@@ -42,14 +44,16 @@ class Sim:
 
     def __init__(self, nx, ny, nu, eta, delta=0.0, closure_scale=1.0, s5=0.0, s6=0.0, s7=0.0, s8=0.0,
                  grad_stencil="iso9", dtype="fp64", schedule="fused", rho0=1.0, b_ref=(0.0, 0.0),
-                 closure="analytic", device="cuda:0", stream=None):
+                 closure="analytic", mag_lattice="d2q5", device="cuda:0", stream=None):
         import torch
 
         lib = N.load()
         self._torch = torch
         self.params = make_params(nx, ny, nu, eta, delta, closure_scale, s5, s6, s7, s8,
-                                  grad_stencil, dtype, schedule, rho0, b_ref, closure)
+                                  grad_stencil, dtype, schedule, rho0, b_ref, closure, mag_lattice)
         self.nx, self.ny = int(nx), int(ny)
+        # populations per cell: 9 f plus two components of g on 5 or 9 velocities
+        self.npop = 9 + 2 * (9 if mag_lattice == "d2q9" else 5)
         self.device = torch.device(device)
         sb = lib.lbm_state_bytes(ctypes.byref(self.params))
         wb = lib.lbm_work_bytes(ctypes.byref(self.params))
@@ -106,17 +110,18 @@ class Sim:
         return out
 
     def get_state(self, out=None):
-        """[19, ny, nx] float64 device tensor of the populations at time t."""
+        """[npop, ny, nx] float64 device tensor of the populations at time t
+        (npop = 19 with D2Q5 g, 27 with D2Q9 g)."""
         if out is None:
-            out = self._torch.empty((19, self.ny, self.nx), dtype=self._torch.float64, device=self.device)
-        self._check_field(out, 19)
+            out = self._torch.empty((self.npop, self.ny, self.nx), dtype=self._torch.float64, device=self.device)
+        self._check_field(out, self.npop)
         N.check(self._lib.lbm_get_state(self._ctx, ctypes.c_void_p(out.data_ptr())), "lbm_get_state")
         return out
 
     def set_state(self, state, t: int = 0):
-        """state: [19, ny, nx] float64 (any device; copied to this GPU)."""
+        """state: [npop, ny, nx] float64 (any device; copied to this GPU)."""
         s = self._torch.as_tensor(state, dtype=self._torch.float64).to(self.device).contiguous()
-        self._check_field(s, 19)
+        self._check_field(s, self.npop)
         N.check(self._lib.lbm_set_state(self._ctx, ctypes.c_void_p(s.data_ptr()), int(t)), "lbm_set_state")
         self._keep = s  # the copy must outlive the asynchronous kernel
 

@@ -21,7 +21,8 @@ def lib():
 
 def _params(**kw):
     base = dict(nx=64, ny=48, nu=1e-3, eta=2e-3, s5=0.0, s6=0.0, s7=0.0, s8=0.0, delta=2.0,
-                closure_scale=1.0, grad_stencil=0, dtype=0, schedule=0, closure=0, rho0=1.0,
+                closure_scale=1.0, grad_stencil=0, dtype=0, schedule=0, closure=0, mag_lattice=0, reserved=0,
+                rho0=1.0,
                 bref_x=0.01, bref_y=0.0)
     base.update(kw)
     return N.LbmParams(**base)
@@ -37,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_struct_layouts_match_header():
     # int32 pairs then doubles: no hidden padding differences between C and ctypes
-    assert ctypes.sizeof(N.LbmParams) == 4 * 2 + 8 * 8 + 4 * 4 + 3 * 8
+    assert ctypes.sizeof(N.LbmParams) == 4 * 2 + 8 * 8 + 6 * 4 + 3 * 8
     assert ctypes.sizeof(N.LbmKhParams) == 7 * 8
     assert ctypes.sizeof(N.LbmDiag) == 8 + 11 * 8 + 8
 
@@ -228,3 +229,18 @@ def test_header_constants_match_the_binding():
                 assert getattr(N, name) == int(value), name
                 seen += 1
     assert seen >= 20
+
+
+def test_d2q9_magnetic_lattice_params(lib):
+    p = _params(mag_lattice=N.LBM_MAG_D2Q9)
+    n_plane = ((64 * 48 + 1023) // 1024) * 1024 + 256
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 2 * 27 * n_plane * 8
+    p.dtype = N.LBM_FP32
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 2 * 27 * n_plane * 4
+    assert lib.lbm_work_bytes(ctypes.byref(_params(mag_lattice=N.LBM_MAG_D2Q9, closure=N.LBM_CLOSURE_FULL))) > 0
+    for bad in (dict(schedule=N.LBM_SCHED_AA), dict(schedule=N.LBM_SCHED_AA_LAGGED),
+                dict(closure=N.LBM_CLOSURE_LEARNED), dict(grad_stencil=N.LBM_STENCIL_LOCAL_ISO9),
+                dict(dtype=N.LBM_FP16), dict(dtype=N.LBM_BF16)):
+        assert lib.lbm_state_bytes(ctypes.byref(_params(mag_lattice=N.LBM_MAG_D2Q9, **bad))) == 0, bad
+    assert lib.lbm_state_bytes(ctypes.byref(_params(mag_lattice=2))) == 0
+    assert lib.lbm_state_bytes(ctypes.byref(_params(reserved=1))) == 0

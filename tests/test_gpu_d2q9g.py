@@ -1,0 +1,213 @@
+"""GPU parity of the D2Q9 vector distribution (LBM_MAG_D2Q9: g on all nine
+velocities, Sec. 2's MagTMatrix / MagMomentEq collision) against the
+oracle's mag_lattice='d2q9'.  Tolerances as for D2Q5: FP64 <= 1e-12
+relative at every step, FP32 <= 1e-5 after 100 steps, two steps from random
+states within 1e-14 absolute, sampled full-size cells against windowed
+oracle runs."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lbmhd_oracle as O
+from seeded_inputs import offset_noise, perturbed
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+KH0 = dict(U0=0.05, delta_over_L=0.05, B0=0.01, rho0=1.0, pert_amp_over_U0=1e-3, noise_amp=1e-5)
+
+
+def _sim(**kw):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_09807_amd import Sim
+    return Sim(mag_lattice="d2q9", **kw)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def pack(f, g):
+    return np.concatenate([f, g[:, 0], g[:, 1]], 0)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def field_errors(mg, mo):
+    mo = np.stack(mo)
+    return {"rho": rel(mg[0], mo[0]), "m": rel(mg[1:3], mo[1:3]), "B": rel(mg[3:5], mo[3:5])}
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_initial_state_and_roundtrip(dtype):
+    n = 48
+    _say("d2q9 init", dtype)
+    s = _sim(nx=n, ny=n, nu=1e-3, eta=1e-3, delta=2.0, dtype=dtype, b_ref=(0.01, 0.0))
+    o = O.Oracle(n, n, 1e-3, 1e-3, delta=2.0, mag_lattice="d2q9")
+    s.init_kh_jet(seed=3, **KH0)
+    o.init_kh_jet(seed=3, **KH0)
+    st = s.get_state().cpu().numpy()
+    assert st.shape == (27, n, n)
+    e = np.abs(st - pack(*o.state()[:2])).max()
+    # the kernel writes geq in population form, the oracle through T_m^-1 N^eq
+    assert e <= (4e-16 if dtype == "fp64" else 1e-9), e
+    # set_state / get_state round trip (FP64 exact)
+    f, g, _ = o.state()
+    s.set_state(pack(f, g), 5)
+    back = s.get_state().cpu().numpy()
+    if dtype == "fp64":
+        assert np.array_equal(back, pack(f, g))
+    else:
+        assert np.abs(back - pack(f, g)).max() <= 1e-9
+    assert s.t == 5
+
+
+@pytest.mark.parametrize("stencil", ["iso9", "central5"])
+@pytest.mark.parametrize("delta", [0.0, 2.0])
+def test_kh_fp64_every_step(stencil, delta):
+    n, steps = 64, 200
+    _say("d2q9 fp64", stencil, delta)
+    s = _sim(nx=n, ny=n, nu=1e-3, eta=1e-3, delta=delta, dtype="fp64", grad_stencil=stencil)
+    o = O.Oracle(n, n, 1e-3, 1e-3, delta=delta, grad_stencil=stencil, mag_lattice="d2q9")
+    s.init_kh_jet(seed=0, **KH0)
+    o.init_kh_jet(seed=0, **KH0)
+    worst = 0.0
+    for k in range(steps):
+        s.step(1)
+        o.step(1)
+        if k % 10 == 9 or k < 5:
+            e = rel(s.get_state().cpu().numpy(), pack(*o.state()[:2]))
+            worst = max(worst, e)
+            assert e <= 1e-12, (k, e)
+    _say("  worst", worst)
+
+
+@pytest.mark.parametrize("nx", [1040, 200])
+def test_kh_fp32_100_steps(nx):
+    """512-lane strips with a ragged last strip (1040) and 64-lane strips (200)."""
+    ny = 48
+    _say("d2q9 fp32", nx)
+    kh = dict(KH0, pert_amp_over_U0=1e-2)
+    s = _sim(nx=nx, ny=ny, nu=2e-3, eta=2e-3, delta=3.0, dtype="fp32", b_ref=(0.01, 0.0), s5=1.6, s6=1.6,
+             s7=1.6, s8=1.6)
+    o = O.Oracle(nx, ny, 2e-3, 2e-3, delta=3.0, s5=1.6, s6=1.6, s7=1.6, s8=1.6, mag_lattice="d2q9")
+    s.init_kh_jet(seed=2, **kh)
+    o.init_kh_jet(seed=2, **kh)
+    s.step(100)
+    o.step(100)
+    e = field_errors(s.moments().cpu().numpy(), o.moments())
+    e["state"] = rel(s.get_state().cpu().numpy(), pack(*o.state()[:2]))
+    _say("  fp32 relative L2 after 100 steps:", e)
+    for key, v in e.items():
+        assert v <= 1e-5, (key, v)
+
+
+@pytest.mark.parametrize("shape", [(33, 17), (130, 66), (257, 10), (300, 7)])
+@pytest.mark.parametrize("delta", [0.0, 3.0])
+def test_random_states_two_steps(shape, delta):
+    nx, ny = shape
+    _say("d2q9 random", shape, delta)
+    f = perturbed(O.W9, (9, ny, nx), 21, 0.15)
+    g = offset_noise(np.zeros(18), (18, ny, nx), 22, 0.01).reshape(9, 2, ny, nx)
+    s = _sim(nx=nx, ny=ny, nu=0.02, eta=0.03, delta=delta, dtype="fp64", s5=1.3, s6=0.9, s7=1.7, s8=1.1)
+    o = O.Oracle(nx, ny, 0.02, 0.03, delta=delta, s5=1.3, s6=0.9, s7=1.7, s8=1.1, mag_lattice="d2q9")
+    for t0 in (0, 1):
+        s.set_state(pack(f, g), t0)
+        o.set_state(f, g, t0)
+        s.step(2)
+        o.step(2)
+        e = np.abs(s.get_state().cpu().numpy() - pack(*o.state()[:2])).max()
+        assert e <= 1e-14, (t0, e)
+
+
+def test_density_gradient_closure_on_d2q9():
+    nx, ny = 80, 36
+    _say("d2q9 full closure")
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    k = 2 * math.pi / nx
+    q = 2 * math.pi / ny
+    m = np.stack([1.0 + 0.08 * np.sin(3 * k * X + q * Y), 0.05 * np.sin(4 * k * X + q * Y),
+                  0.04 * np.cos(k * X - 3 * q * Y), 0.01 + 0.02 * np.sin(2 * k * X + 4 * q * Y),
+                  0.015 * np.cos(3 * k * X - 2 * q * Y)])
+    s = _sim(nx=nx, ny=ny, nu=2e-3, eta=4e-3, delta=3.0, dtype="fp64", closure="full")
+    o = O.Oracle(nx, ny, 2e-3, 4e-3, delta=3.0, density_gradients=True, mag_lattice="d2q9")
+    s.init_from_moments(torch.from_numpy(m))
+    o.set_state(O.f_equilibrium(*m), O.g_equilibrium_d2q9(*m))
+    for k_ in range(10):
+        s.step(1)
+        o.step(1)
+        e = rel(s.get_state().cpu().numpy(), pack(*o.state()[:2]))
+        assert e <= 1e-12, (k_, e)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_sech2_jet_on_d2q9(dtype):
+    n = 64
+    _say("d2q9 sech2", dtype)
+    B0 = 0.005 * 4.88e-2
+    s = _sim(nx=n, ny=n, nu=1e-3 * 64 / 1024, eta=1e-3 * 64 / 1024, delta=2.0, dtype=dtype, b_ref=(0.0, B0))
+    o = O.Oracle(n, n, 1e-3 * 64 / 1024, 1e-3 * 64 / 1024, delta=2.0, mag_lattice="d2q9")
+    s.init_sech2_jet()
+    o.init_sech2_jet()
+    s.step(200)
+    o.step(200)
+    e = field_errors(s.moments().cpu().numpy(), o.moments())
+    _say("  ", e)
+    for key, v in e.items():
+        assert v <= (1e-12 if dtype == "fp64" else 1e-5), (key, v)
+
+
+def test_diagnostics_match_oracle():
+    n = 48
+    s = _sim(nx=n, ny=n, nu=2e-3, eta=2e-3, delta=2.0, dtype="fp64")
+    o = O.Oracle(n, n, 2e-3, 2e-3, delta=2.0, mag_lattice="d2q9")
+    s.init_kh_jet(seed=4, **KH0)
+    o.init_kh_jet(seed=4, **KH0)
+    s.step(50)
+    o.step(50)
+    dg, do = s.diagnostics(), o.diagnostics()
+    # difference-based quantities carry the rounding of neighbour differences
+    # (c = 10 eps 0.05 per difference, as for D2Q5)
+    c = 10 * np.finfo(np.float64).eps * 0.05
+    for key in ("mass", "e_kin", "e_mag"):
+        assert abs(dg[key] - do[key]) <= 1e-12 * abs(do[key]), (key, dg[key], do[key])
+    for key in ("enstrophy", "j2"):
+        assert abs(dg[key] - do[key]) <= 1e-12 * abs(do[key]) + 2 * math.sqrt(abs(do[key])) * c + c * c, key
+    assert abs(dg["divb_max"] - do["divb_max"]) <= 1e-12 * abs(do["divb_max"]) + c
+
+
+@pytest.mark.parametrize("delta", [0.0, 4.0])
+def test_full_size_sampled(delta):
+    """4096^2 FP32 in the benchmark's launch configuration: 3 steps, 24
+    sampled cells against the oracle on the 15 x 15 window around each."""
+    n, nu, B0, steps = 4096, 2e-4, 0.01, 3
+    _say("d2q9 full size", delta)
+    kh = dict(U0=0.05, delta_over_L=1 / 40, B0=B0, rho0=1.0, pert_amp_over_U0=1e-3, noise_amp=1e-5)
+    g4 = dict(s5=1.6, s6=1.6, s7=1.6, s8=1.6)
+    s = _sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype="fp32", b_ref=(B0, 0.0), **g4)
+    s.init_kh_jet(seed=11, **kh)
+    s.step(steps)
+    rng = np.random.default_rng(13)
+    pts = [(0, 0), (n - 1, n - 1), (511, 512)] + [tuple(v) for v in rng.integers(0, n, size=(21, 2))]
+    xs = torch.tensor([p[0] for p in pts], device=s.device)
+    ys = torch.tensor([p[1] for p in pts], device=s.device)
+    got = s.get_state()[:, ys, xs].cpu().numpy()
+    win = 2 * (2 * steps + 1) + 1
+    half = win // 2
+    for k, (x, y) in enumerate(pts):
+        gx = (x - half + np.arange(win)) % n
+        gy = (y - half + np.arange(win)) % n
+        X, Y = np.meshgrid(gx, gy)
+        f, g = O.kh_jet_populations(X, Y, n, n, seed=11, lattice="d2q9", **kh)
+        o = O.Oracle(win, win, nu, nu, delta=delta, mag_lattice="d2q9", **g4)
+        o.set_state(f, g)
+        o.step(steps)
+        ref = pack(*o.state()[:2])[:, half, half]
+        err = np.abs(got[:, k] - ref).max()
+        assert err <= 2e-6, (x, y, err)
+    assert s.diagnostics()["nonfinite"] == 0
