@@ -21,6 +21,7 @@ struct lbm_ctx {
   int64_t t = 0;
   bool initialized = false;
   bool mlp_set = false;  // learned closure: a network has been installed
+  bool cus_known = false;  // compute-unit count queried
   bool lag_ready = false;  // lagged schedule: moment set t & 1 holds step t - 1
 };
 
@@ -204,6 +205,14 @@ int lbm_step(lbm_ctx* ctx, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   if (ctx->L.learned && !ctx->mlp_set)
     return fail(LBM_ESTATE, "learned closure: install a network with lbm_set_closure_mlp first");
+  if (n > 0 && !ctx->cus_known) {
+    // launch shapes depend on the compute-unit count of the current device
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      ctx->L.cus = cus;
+    ctx->cus_known = true;
+  }
   if (n > 0 && ctx->L.schedule == LBM_SCHED_AA_LAGGED && ctx->L.k2 != 0.0 && !ctx->lag_ready) {
     hipError_t e = lbm::launch_lag_prime(ctx->L, ctx->t);
     if (e != hipSuccess) return hip_fail(e, "lbm_step");

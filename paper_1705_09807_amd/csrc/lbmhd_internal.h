@@ -24,6 +24,7 @@ struct Launch {
   int schedule = LBM_SCHED_FUSED;
   int stencil = LBM_STENCIL_ISO9;
   int qg = 5;                     // velocities of the vector distribution: 5 (D2Q5) or 9 (D2Q9)
+  int cus = 256;                  // compute units of the device (queried at the first step)
   double rate[9] = {0};           // MRT rates s0..s8 (s0..s2 = 0)
   double sm = 0;                  // magnetic SRT rate
   double k2 = 0;                  // closure_scale * Delta^2 / 12

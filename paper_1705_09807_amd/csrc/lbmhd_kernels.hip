@@ -1048,16 +1048,19 @@ static C* moment_set(const Launch& L, int k) {
   return reinterpret_cast<C*>(static_cast<char*>(L.work) + L.off_mb + (size_t)k * stride);
 }
 
-// Rows per workgroup of the fused closure kernel: long strips (the two halo
-// rows are re-read once per strip) as long as the launch keeps at least 512
-// workgroups (measured at 1024^2 .. 8192^2 on MI355X: fewer leave the chip
-// latency bound, longer strips gain little).
-static int fused_rows(int nx, int ny, int strip) {
+// Rows per workgroup of the fused closure kernel.  Measured on MI355X over
+// 1024^2 .. 8192^2 (FP32 and FP64 strips): one workgroup per compute unit is
+// fastest (every strip segment runs concurrently from start to end, and the
+// two halo rows re-read per segment are amortised over many rows) as long as
+// a segment then holds at most 128 rows (FP32) or 64 rows (FP64); larger
+// grids run more, 64-row segments (8192^2 FP32: 1952 us at 64 rows, 2041 us
+// at 128, 2180 us at 512 = one per compute unit).
+static int fused_rows(int nx, int ny, int strip, int cus, int cap) {
   const int64_t strips = (nx + strip - 1) / strip;
-  int64_t ry = 64;
-  while (ry > 2 && strips * ((ny + ry - 1) / ry) < 512) ry /= 2;
-  if (ry > ny) ry = ny;
-  return (int)ry;
+  const int64_t blocks = cus / strips > 1 ? cus / strips : 1;  // segments per strip column
+  int64_t ry = (ny + blocks - 1) / blocks;
+  if (ry > cap) ry = 64;
+  return (int)(ry < 1 ? 1 : ry);
 }
 
 // Non-temporal stores pay off once the two population buffers no longer fit
@@ -1068,7 +1071,7 @@ static bool streaming_stores(const Launch& L) {
 
 template <typename S, typename C, int W, bool NT, int MODE, int QG>
 static void launch_les_k(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
-  const int ry = fused_rows(L.nx, L.ny, W);
+  const int ry = fused_rows(L.nx, L.ny, W, L.cus, sizeof(C) == 4 ? 128 : 64);
   const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
   // the density-gradient closure and the D2Q9 vector distribution take
   // stencil gradients only
