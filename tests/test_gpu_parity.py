@@ -387,3 +387,62 @@ def test_sech2_jet_matches_oracle(dtype):
     _say("sech2 jet", dtype, "after 200 steps:", e)
     for key, v in e.items():
         assert v <= (1e-12 if dtype == "fp64" else 1e-5), (key, v)
+
+
+# ---------------------------------------------------------------------------
+# Extreme sizes: the longest rows and columns the ABI accepts, and the
+# largest grid of the benchmark family (16384^2 FP32, 40.8 GB of state).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(32768, 4), (4, 32768), (32767, 5)])
+@pytest.mark.parametrize("schedule", ["fused", "aa", "aa_lagged"])
+def test_extreme_aspect_grids(shape, schedule):
+    """Two steps from a random state on grids at the maximum extent in one
+    direction (many strips / row segments in a row, or thousands of rows per
+    strip), every population within 1e-14 of the oracle (the lagged oracle
+    for the lagged schedule)."""
+    nx, ny = shape
+    _say("extreme", shape, schedule)
+    f, g = _random_state(nx, ny, 7)
+    s = _sim(nx=nx, ny=ny, nu=0.02, eta=0.03, delta=2.0, dtype="fp64", schedule=schedule)
+    o = O.Oracle(nx, ny, 0.02, 0.03, delta=2.0, closure_time="lagged" if schedule == "aa_lagged" else "sync")
+    s.set_state(torch.from_numpy(pack(f, g)), t=1)
+    o.set_state(f, g, t=1)
+    for _ in range(2):
+        s.step(1)
+        o.step(1)
+        err = np.abs(s.get_state().cpu().numpy() - pack(*o.state()[:2])).max()
+        assert err <= 1e-14, err
+
+
+def test_16384_fp32_sampled():
+    """16384^2 FP32 LES (Delta = 4) in the fused schedule: 3 steps, 16 sampled
+    cells' moments against the oracle on the 15 x 15 window around each."""
+    n, nu, B0, steps, delta = 16384, 2e-4, 0.01, 3, 4.0
+    _say("16384^2 sampled")
+    kh = dict(U0=0.05, delta_over_L=1 / 40, B0=B0, rho0=1.0, pert_amp_over_U0=1e-3, noise_amp=1e-5)
+    g4 = dict(s5=1.6, s6=1.6, s7=1.6, s8=1.6)
+    s = _sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype="fp32", b_ref=(B0, 0.0), **g4)
+    s.init_kh_jet(seed=5, **kh)
+    s.step(steps)
+    rng = np.random.default_rng(17)
+    pts = [(0, 0), (n - 1, n - 1), (8191, 4096)] + [tuple(v) for v in rng.integers(0, n, size=(13, 2))]
+    mom = s.moments()
+    xs = torch.tensor([p[0] for p in pts], device=s.device)
+    ys = torch.tensor([p[1] for p in pts], device=s.device)
+    got = mom[:, ys, xs].cpu().numpy()
+    del mom
+    win = 2 * (2 * steps + 1) + 1
+    half = win // 2
+    for k, (x, y) in enumerate(pts):
+        gx = (x - half + np.arange(win)) % n
+        gy = (y - half + np.arange(win)) % n
+        X, Y = np.meshgrid(gx, gy)
+        f, g = O.kh_jet_populations(X, Y, n, n, seed=5, **kh)
+        o = O.Oracle(win, win, nu, nu, delta=delta, **g4)
+        o.set_state(f, g)
+        o.step(steps)
+        ref = np.array([a[half, half] for a in o.moments()])
+        assert np.abs(got[:, k] - ref).max() <= 2e-6, (x, y, np.abs(got[:, k] - ref).max())
+    assert s.diagnostics()["nonfinite"] == 0
+    s.close()
