@@ -303,6 +303,7 @@ k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float*
   constexpr int LX = kCorrLX, PL = kCorrPL;
   __shared__ float fld[7 * PL];
   __shared__ unsigned char bad[PL];
+  __shared__ unsigned char patch_bad[kCorrTX * kCorrTY];
   __shared__ __attribute__((aligned(16))) float bias[132];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, h = lane >> 5;
   if (tid < 132) bias[tid] = reinterpret_cast<const float*>(pk + kPkB1)[tid];
@@ -367,10 +368,20 @@ k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float*
     }
   }
   __syncthreads();
+  // 3b. one flag per tile cell: any out-of-range value in its 3 x 3 patch
+  for (int e = tid; e < kCorrTX * kCorrTY; e += 256) {
+    const int ty = e / kCorrTX, base = ty * LX + (e - ty * kCorrTX);
+    int o = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) o |= bad[base + (q / 3) * LX + q % 3 + LX + 1];
+    patch_bad[e] = (unsigned char)o;
+  }
+  __syncthreads();
   // 4. the network, 32 cells per wave at a time (operands and biases held in
-  // registers for the whole loop)
+  // registers for the whole loop; output scales in scalar registers)
   MlpA w;
   load_mlp(pk, lane, w);
+  const float os0 = nm->out_scale[0], os1 = nm->out_scale[1], os2 = nm->out_scale[2], os3 = nm->out_scale[3];
   for (int g = wid; g < kCorrTX * kCorrTY / 32; g += 4) {
     const int ty = g >> 1, tx = (g & 1) * 32 + (lane & 31), base = ty * LX + tx;
     bf16x8 zb[4];
@@ -387,16 +398,16 @@ k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float*
       }
       zb[kb] = to_bf16x8(zf);
     }
-    int o = 0;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) o |= bad[base + (q / 3) * LX + q % 3 + LX + 1];
+    const bool pb = patch_bad[ty * kCorrTX + tx] != 0;
     const f32x4 v = mlp_wave(w, zb, bias, lane, nullptr, nullptr);
-    o = o || !(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]));
+    const bool o = pb || !(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]));
     const int gx = x0 + tx, gy = y0 + ty;
     if (h == 0 && gx < nx && gy < ny) {
-      const int64_t c = (int64_t)gy * nx + gx;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) corr[q * n + c] = o ? 0.0f : v[q] * nm->out_scale[q];
+      float* cp = corr + ((int64_t)gy * nx + gx);
+      cp[0] = o ? 0.0f : v[0] * os0;
+      cp[n] = o ? 0.0f : v[1] * os1;
+      cp[2 * n] = o ? 0.0f : v[2] * os2;
+      cp[3 * n] = o ? 0.0f : v[3] * os3;
     }
   }
 }
