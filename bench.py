@@ -227,13 +227,19 @@ def jet_study(args, dev, stream) -> int:
     U0 = 4.88e-2
     B0 = 0.005 * U0
     dtype = args.jet_dtype
-    out = {"study": "sech2 jet (Sec. 4)", "T_les": T, "U0": U0, "B0": B0, "Re": 5e4, "dtype": dtype,
+    # "paper" variant: g on D2Q9 and the closure with the filtered-density
+    # terms (Sec. 2's lattice and Sec. 2.1's closure before Sec. 3's
+    # simplification); "default": D2Q5 g, simplified closure
+    variant = dict(mag_lattice="d2q9", closure="full") if args.jet_variant == "paper" else {}
+    out = {"study": "sech2 jet (Sec. 4)", "variant": args.jet_variant, "T_les": T, "U0": U0, "B0": B0, "Re": 5e4,
+           "dtype": dtype,
            "collision": "SRT", "runs": {}}
     spectra = {}
     for label in labels:
         n, delta, nu, mult = JET_RUNS[label]
         steps = T * mult
-        sim = Sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype=dtype, b_ref=(0.0, B0), device=dev, stream=stream)
+        sim = Sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype=dtype, b_ref=(0.0, B0), device=dev, stream=stream,
+                  **variant)
         sim.init_sech2_jet(U0=U0, B0=B0, pert=0.01, k=4)
         marks = sorted({steps // 4, steps // 2, steps})
         rec = {"grid": n, "delta": delta, "nu": nu, "eta": nu, "steps": steps, "snapshots": {}}
@@ -273,7 +279,7 @@ def jet_study(args, dev, stream) -> int:
         if a in spectra and "dns2048" in spectra:
             out[f"spectrum_rel_l2_{a}_vs_dns2048"] = jet_compare(spectra, a, "dns2048")
     if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
-        with open(os.path.join(ROOT, "gpurun_out", f"jet_spectra_{'_'.join(labels)}.json"), "w") as fh:
+        with open(os.path.join(ROOT, "gpurun_out", f"jet_spectra_{args.jet_variant}_{'_'.join(labels)}.json"), "w") as fh:
             json.dump(spectra, fh)
     print(json.dumps(out), flush=True)
     return 0
@@ -476,6 +482,8 @@ def main() -> int:
     ap.add_argument("--jet-runs", default="dns1024,les1024_d1,les1024_d2,dns2048",
                     help="comma-separated subset of the jet study's runs")
     ap.add_argument("--jet-dtype", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--jet-variant", default="default", choices=["default", "paper"],
+                    help="paper: D2Q9 magnetic distribution and the density-gradient closure")
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--study-nu", type=float, default=1e-3, help="LES-grid viscosity of the study")
     ap.add_argument("--study-eta", type=float, default=1e-2, help="LES-grid resistivity of the study")
