@@ -112,6 +112,60 @@ def cpu_baseline(les_steps: int, dns_steps: int) -> dict:
     }
 
 
+def variant_oracle_rates(n: int = 512, steps: int = 2) -> dict:
+    """The FP64 oracle, one thread, on an n^2 sample (`steps` steps of the
+    same jet) in the mode that matches each closure / lattice variant the
+    benchmark times on the GPU, in MLUPS.  The in-place synchronous schedule
+    computes the same step as the fused one and the storage types are not
+    emulated, so those legs share the plain oracle's rate."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import numpy as np
+    from oracle.lbmhd_oracle import Oracle
+    from oracle import learned as OL
+
+    def learned_hook():
+        from paper_1705_09807_amd import learned as G
+        flat = G.glorot_params(0).double().numpy()
+        nm = {"w1": flat[:4096].reshape(64, 64), "b1": flat[4096:4160], "w2": flat[4160:8256].reshape(64, 64),
+              "b2": flat[8256:8320], "w3": flat[8320:8576].reshape(64, 4), "b3": flat[8576:8580]}
+        # per-feature normalisation: each field's value on its nine patch columns, pad 0 / 1
+        shift = np.append(np.repeat([1.0, 0.0, 0.0, KH["B0"], 0.0, 0.0, 0.0], 9), 0.0)
+        scale = np.append(np.repeat([1e3, 20.0, 20.0, 100.0, 100.0, 1e3, 1e3], 9), 1.0)
+        return OL.learned_correction(nm, shift, scale, np.full(4, 1e-6))
+
+    modes = {
+        "les4096": dict(delta=LES_DELTA),
+        "les4096_full": dict(delta=LES_DELTA, density_gradients=True),
+        "les4096_local_iso9": dict(delta=LES_DELTA, grad_stencil="local_iso9"),
+        "les4096_aa_lagged": dict(delta=LES_DELTA, closure_time="lagged"),
+        "les4096_d2q9": dict(delta=LES_DELTA, mag_lattice="d2q9"),
+        "dns4096_d2q9": dict(delta=0.0, mag_lattice="d2q9"),
+        "les1024_learned": dict(delta=LES_DELTA, closure_correction="learned"),
+    }
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    out = {}
+    try:
+        for key, kw in modes.items():
+            kw = dict(kw)
+            if kw.get("closure_correction") == "learned":
+                kw["closure_correction"] = learned_hook()
+            o = Oracle(n, n, NU, ETA, s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST, **kw)
+            o.init_kh_jet(seed=0, **KH)
+            t0 = time.perf_counter()
+            o.step(steps)
+            dt = time.perf_counter() - t0
+            out[key] = {"oracle_mlups": round(n * n * steps / dt / 1e6, 3),
+                        "oracle_sample": f"FP64 NumPy oracle, 1 thread, {n}^2 x {steps} steps, {dt:.2f} s"}
+            log(f"oracle {key}: {dt:.2f} s")
+    finally:
+        if ctx is not None:
+            ctx.unregister() if hasattr(ctx, "unregister") else None
+    return out
+
+
 def precision_study(steps: int, dev, stream) -> int:
     """Per-field relative L2 error (rho; m as a vector field; B as a vector
     field) of FP32, FP16 and BF16 storage against an FP64 run of the same
@@ -755,6 +809,11 @@ def main() -> int:
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_les_steps, args.cpu_dns_steps)
+        # the oracle beside each variant leg (its own mode, a 512^2 sample)
+        for key, rec in variant_oracle_rates().items():
+            for k, v in out["extra"].items():
+                if k == key or (key == "les1024_learned" and k.startswith(key)):
+                    v.update(rec)
     print(json.dumps(out), flush=True)
     return 0
 
