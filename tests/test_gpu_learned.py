@@ -457,3 +457,55 @@ def test_non_finite_network_output_keeps_the_analytic_closure():
     a = _sim_state(nx, ny, f, g, delta=2.0, s5=1.3, s6=1.5, s7=1.7, s8=1.1, b_ref=(0.01, 0.0))
     a.step(2)
     assert torch.equal(s.get_state(), a.get_state())
+
+
+def test_full_size_learned_step_sampled():
+    """The benchmark's learned leg: 1024^2 LES (Delta = 4, FP32 storage, MRT
+    ghost rates 1.6) with the learned closure in its launch configuration,
+    one step from the jet; 24 sampled cells against the oracle on the 7 x 7
+    window around each, whose closure_correction hook returns the GPU's
+    correction planes on that window (the network itself is checked against
+    the oracle's above)."""
+    G = _gpu()
+    from paper_1705_09807_amd import Sim
+    n, nu, B0 = 1024, 2e-4, 0.01
+    kh = dict(U0=0.05, delta_over_L=1 / 40, B0=B0, rho0=1.0, pert_amp_over_U0=1e-2, noise_amp=1e-3)
+    g4 = dict(s5=1.6, s6=1.6, s7=1.6, s8=1.6)
+    p = _params(81)
+    s = Sim(nx=n, ny=n, nu=nu, eta=nu, delta=4.0, dtype="fp32", b_ref=(B0, 0.0), closure="learned", **g4)
+    s.init_kh_jet(seed=9, **kh)
+    X = s.moments().cpu().numpy()
+    feats = L.closure_features(*X[:, ::8, ::8])
+    shift, scale, _ = L.feature_stats(feats, np.ones((feats.shape[0], 4)))
+    m = _mlp(G, p, shift[::9][:7].astype(np.float32), scale[::9][:7].astype(np.float32),
+             np.array([1e-3, 7e-4, 1e-3, 3e-4], dtype=np.float32))
+    s.set_closure_mlp(m.pack())
+    st0 = s.get_state().cpu().numpy()
+    corr = s.closure_correction().cpu().numpy().astype(np.float64)
+    assert np.abs(corr).max() > 0
+    s.step(1)
+    rng = np.random.default_rng(23)
+    pts = [(0, 0), (n - 1, n - 1), (511, 512)] + [tuple(v) for v in rng.integers(0, n, size=(21, 2))]
+    xs = torch.tensor([q[0] for q in pts], device=s.device)
+    ys = torch.tensor([q[1] for q in pts], device=s.device)
+    got = s.get_state()[:, ys, xs].cpu().numpy()
+    win, half = 7, 3
+    for k, (x, y) in enumerate(pts):
+        gx = (x - half + np.arange(win)) % n
+        gy = (y - half + np.arange(win)) % n
+        w = st0[:, gy[:, None], gx[None, :]]
+        cw = corr[:, gy[:, None], gx[None, :]]
+        o = O.Oracle(win, win, nu, nu, delta=4.0, closure_correction=lambda *a, c=cw: c, **g4)
+        o.set_state(w[:9], np.stack([w[9:14], w[14:19]], axis=1))
+        o.step(1)
+        fo, go_ = o.state()[:2]
+        ref = np.concatenate([fo, go_[:, 0], go_[:, 1]], 0)[:, half, half]
+        err = np.abs(got[:, k] - ref).max()
+        assert err <= 2e-6, (x, y, err)
+        if k < 4:   # the correction itself is far above the tolerance
+            o0 = O.Oracle(win, win, nu, nu, delta=4.0, **g4)
+            o0.set_state(w[:9], np.stack([w[9:14], w[14:19]], axis=1))
+            o0.step(1)
+            f0, g0 = o0.state()[:2]
+            plain = np.concatenate([f0, g0[:, 0], g0[:, 1]], 0)[:, half, half]
+            assert np.abs(plain - ref).max() > 50 * 2e-6, (x, y, np.abs(plain - ref).max())
