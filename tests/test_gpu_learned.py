@@ -509,3 +509,50 @@ def test_full_size_learned_step_sampled():
             f0, g0 = o0.state()[:2]
             plain = np.concatenate([f0, g0[:, 0], g0[:, 1]], 0)[:, half, half]
             assert np.abs(plain - ref).max() > 50 * 2e-6, (x, y, np.abs(plain - ref).max())
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp16"])
+def test_learned_step_16bit_beyond_the_caches_sampled(dtype):
+    """16-bit storage with the state beyond the 256 MB Infinity Cache (2048^2:
+    319 MB) runs the correction sweep in 256-lane strips; one learned step from
+    the rounded state the GPU holds, 16 sampled cells against windowed oracle
+    runs with the GPU's correction; bound: one rounding of each stored
+    deviation (u |deviation|)."""
+    G = _gpu()
+    from paper_1705_09807_amd import Sim
+    n, nu, B0 = 2048, 2e-4, 0.01
+    unit = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[dtype]
+    kh = dict(U0=0.05, delta_over_L=1 / 40, B0=B0, rho0=1.0, pert_amp_over_U0=1e-2, noise_amp=1e-3)
+    g4 = dict(s5=1.6, s6=1.6, s7=1.6, s8=1.6)
+    p = _params(91)
+    s = Sim(nx=n, ny=n, nu=nu, eta=nu, delta=4.0, dtype=dtype, b_ref=(B0, 0.0), closure="learned", **g4)
+    s.init_kh_jet(seed=4, **kh)
+    X = s.moments().cpu().numpy()
+    feats = L.closure_features(*X[:, ::16, ::16])
+    shift, scale, _ = L.feature_stats(feats, np.ones((feats.shape[0], 4)))
+    m = _mlp(G, p, shift[::9][:7].astype(np.float32), scale[::9][:7].astype(np.float32),
+             np.array([1e-3, 7e-4, 1e-3, 3e-4], dtype=np.float32))
+    s.set_closure_mlp(m.pack())
+    st0 = s.get_state().cpu().numpy()
+    corr = s.closure_correction().cpu().numpy().astype(np.float64)
+    s.step(1)
+    rng = np.random.default_rng(29)
+    pts = [(0, 0), (n - 1, n - 1), (255, 256), (256, 255)] + [tuple(v) for v in rng.integers(0, n, size=(12, 2))]
+    xs = torch.tensor([q[0] for q in pts], device=s.device)
+    ys = torch.tensor([q[1] for q in pts], device=s.device)
+    got = s.get_state()[:, ys, xs].cpu().numpy()
+    rest = np.concatenate([O.W9, O.W5 * B0, O.W5 * 0.0])
+    win, half = 7, 3
+    for k, (x, y) in enumerate(pts):
+        gx = (x - half + np.arange(win)) % n
+        gy = (y - half + np.arange(win)) % n
+        w = st0[:, gy[:, None], gx[None, :]]
+        cw = corr[:, gy[:, None], gx[None, :]]
+        o = O.Oracle(win, win, nu, nu, delta=4.0, closure_correction=lambda *a, c=cw: c, **g4)
+        o.set_state(w[:9], np.stack([w[9:14], w[14:19]], axis=1))
+        o.step(1)
+        fo, go_ = o.state()[:2]
+        ref = np.concatenate([fo, go_[:, 0], go_[:, 1]], 0)[:, half, half]
+        err = np.abs(got[:, k] - ref).max()
+        bound = unit * np.abs(ref - rest).max() + 1e-6
+        assert err <= bound, (x, y, err, bound)
