@@ -102,3 +102,43 @@ def test_lag_changes_the_result_and_restarts_synchronously():
     lag.step(1)
     syn.step(1)
     assert torch.equal(lag.get_state(), syn.get_state())
+
+
+VARIANTS = [
+    # label, schedule, grad_stencil, oracle closure_time
+    ("local_fused", "fused", "local_iso9", "sync"),
+    ("local_aa", "aa", "local_iso9", "sync"),
+    ("lagged", "aa_lagged", "iso9", "lagged"),
+]
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=[v[0] for v in VARIANTS])
+def test_full_size_variants_sampled(variant):
+    """4096^2 FP32 LES (Delta = 4) of the lagged and local-gradient variants in
+    the benchmark's launch configuration: 3 steps from the jet, 24 sampled
+    cells against the oracle in the same mode on the 15 x 15 window around
+    each."""
+    label, schedule, stencil, ctime = variant
+    n, nu, B0, steps, delta = 4096, 2e-4, 0.01, 3, 4.0
+    kh = dict(U0=0.05, delta_over_L=1 / 40, B0=B0, rho0=1.0, pert_amp_over_U0=1e-3, noise_amp=1e-5)
+    g4 = dict(s5=1.6, s6=1.6, s7=1.6, s8=1.6)
+    s = _sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype="fp32", schedule=schedule, grad_stencil=stencil,
+             b_ref=(B0, 0.0), **g4)
+    s.init_kh_jet(seed=19, **kh)
+    s.step(steps)
+    rng = np.random.default_rng(31)
+    pts = [(0, 0), (n - 1, n - 1), (255, 256), (256, 255)] + [tuple(v) for v in rng.integers(0, n, size=(20, 2))]
+    xs = torch.tensor([q[0] for q in pts], device=s.device)
+    ys = torch.tensor([q[1] for q in pts], device=s.device)
+    got = s.get_state()[:, ys, xs].cpu().numpy()
+    win = 2 * (2 * steps + 1) + 1
+    half = win // 2
+    for k, (x, y) in enumerate(pts):
+        X, Y = np.meshgrid((x - half + np.arange(win)) % n, (y - half + np.arange(win)) % n)
+        f, g = O.kh_jet_populations(X, Y, n, n, seed=19, **kh)
+        o = O.Oracle(win, win, nu, nu, delta=delta, grad_stencil=stencil, closure_time=ctime, **g4)
+        o.set_state(f, g)
+        o.step(steps)
+        ref = pack(*o.state()[:2])[:, half, half]
+        err = np.abs(got[:, k] - ref).max()
+        assert err <= 2e-6, (label, x, y, err)
