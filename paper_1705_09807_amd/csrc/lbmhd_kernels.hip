@@ -398,6 +398,64 @@ k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
   }
 }
 
+// Closure off, 16-bit storage, nx a multiple of 4: four cells per thread, so
+// every plane moves in one aligned 8-byte load and store per thread (plus one
+// 2-byte load of the neighbour column for the planes that stream along x).
+// Measured 7-9 % faster than the pair kernel at 8192^2 with FP16 and BF16
+// storage (slower with FP32, whose pair loads are already 8 bytes).
+template <typename S, typename C, bool NT>
+__global__ void __launch_bounds__(64)
+k_fused_dns_quad(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
+  using V4 = S __attribute__((ext_vector_type(4)));
+  const int x = (blockIdx.x * 64 + threadIdx.x) * 4;
+  const int y = blockIdx.y;
+  if (x >= nx) return;
+  const Rows rw = rows_of<S>(y, nx, ny);
+  const uint32_t es = uint32_t(sizeof(S));
+  const uint32_t x0 = uint32_t(x) * es;
+  const uint32_t xw = uint32_t(x == 0 ? nx - 1 : x - 1) * es;
+  const uint32_t x4 = uint32_t(x + 4 == nx ? 0 : x + 4) * es;
+  C v[4][kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const uint32_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
+    const S* pq = src + q * plane;
+    const V4 t = *reinterpret_cast<const V4*>(at(pq, yo + x0));
+    if (qcx(q) == 0) {
+      v[0][q] = decode<C>(t.x);
+      v[1][q] = decode<C>(t.y);
+      v[2][q] = decode<C>(t.z);
+      v[3][q] = decode<C>(t.w);
+    } else if (qcx(q) > 0) {  // the cells pull from x - 1
+      v[0][q] = decode<C>(*at(pq, yo + xw));
+      v[1][q] = decode<C>(t.x);
+      v[2][q] = decode<C>(t.y);
+      v[3][q] = decode<C>(t.z);
+    } else {  // from x + 1
+      v[0][q] = decode<C>(t.y);
+      v[1][q] = decode<C>(t.z);
+      v[2][q] = decode<C>(t.w);
+      v[3][q] = decode<C>(*at(pq, yo + x4));
+    }
+  }
+  const Closure<C> cl = {C(0), C(0), C(0), C(0)};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const Mom<C> m = moments19(v[k]);
+    collide19(v[k], m, cl, r);
+  }
+  const uint32_t off = rw.c + x0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    V4 t;
+    t.x = encode<S>(v[0][q]);
+    t.y = encode<S>(v[1][q]);
+    t.z = encode<S>(v[2][q]);
+    t.w = encode<S>(v[3][q]);
+    store<NT>(reinterpret_cast<V4*>(at(dst + q * plane, off)), t);
+  }
+}
+
 // Closure off, any nx: one cell per thread, row segments of 256 cells.
 template <typename S, typename C, bool NT, int QG>
 __global__ void __launch_bounds__(256)
@@ -1112,6 +1170,13 @@ static void launch_les(const Launch& L, const S* src, S* dst, const Rates<C>& r,
 template <typename S, typename C, bool NT, int QG>
 static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
   if (L.k2 == 0.0 && !corr) {
+    if constexpr (sizeof(S) == 2 && QG == 5) {
+      if ((L.nx & 3) == 0) {
+        hipLaunchKernelGGL((k_fused_dns_quad<S, C, NT>), dim3((L.nx + 255) / 256, L.ny), dim3(64), 0, L.stream, src,
+                           dst, L.nx, L.ny, L.plane, r);
+        return;
+      }
+    }
     if ((L.nx & 1) == 0)
       hipLaunchKernelGGL((k_fused_dns_pair<S, C, NT, QG>), dim3((L.nx + 255) / 256, L.ny), dim3(128), 0, L.stream,
                          src, dst, L.nx, L.ny, L.plane, r);
