@@ -263,8 +263,8 @@ def jet_study(args, dev, stream) -> int:
     exponent of a power-law fit of the total-energy spectrum E_K + E_M over
     two wavenumber ranges; the paper quotes -1.66 for the 1024^2 runs and
     -1.71 for DNS 2048^2 at the final time (its fit range is not stated).
-    One JSON line on stdout; the spectra of every snapshot go to
-    gpurun_out/jet_spectra_<runs>.json when that directory exists.
+    One JSON line on stdout; with --out-dir the spectra of every snapshot go
+    to <out-dir>/jet_spectra_<variant>_<runs>.json.
     """
     import numpy as np
     import torch
@@ -332,8 +332,9 @@ def jet_study(args, dev, stream) -> int:
     for a in ("les1024_d2", "les1024_d1", "dns1024"):
         if a in spectra and "dns2048" in spectra:
             out[f"spectrum_rel_l2_{a}_vs_dns2048"] = jet_compare(spectra, a, "dns2048")
-    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
-        with open(os.path.join(ROOT, "gpurun_out", f"jet_spectra_{args.jet_variant}_{'_'.join(labels)}.json"), "w") as fh:
+    if args.out_dir:
+        os.makedirs(args.out_dir, exist_ok=True)
+        with open(os.path.join(args.out_dir, f"jet_spectra_{args.jet_variant}_{'_'.join(labels)}.json"), "w") as fh:
             json.dump(spectra, fh)
     print(json.dumps(out), flush=True)
     return 0
@@ -519,6 +520,8 @@ def main() -> int:
                     help="steps of the supplementary 8192^2 FP32/FP16/BF16 timings (0 = skip)")
     ap.add_argument("--learned-steps", type=int, default=300,
                     help="steps of the supplementary 1024^2 learned-closure LES timing (0 = skip)")
+    ap.add_argument("--production-steps", type=int, default=5,
+                    help="steps of the supplementary 16384^2 learned-closure BF16 timing (0 = skip)")
     ap.add_argument("--cpu-les-steps", type=int, default=15)
     ap.add_argument("--cpu-dns-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -541,6 +544,7 @@ def main() -> int:
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--study-nu", type=float, default=1e-3, help="LES-grid viscosity of the study")
     ap.add_argument("--study-eta", type=float, default=1e-2, help="LES-grid resistivity of the study")
+    ap.add_argument("--out-dir", default="", help="folder for the jet study's per-snapshot spectra")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, run a plain device-to-device copy of this many bytes "
                          "(reference kernel for the HBM byte counters)")
@@ -548,8 +552,8 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharded design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU (the library has no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
         return 2
 
     import torch
@@ -765,6 +769,51 @@ def main() -> int:
                 log(f"{key}: {ms * 1e3:.1f} us/step, {lups8 / (ms * 1e-3) / 1e6:.0f} MLUPS, {bw:.0f} GB/s")
                 del sim8
                 torch.cuda.empty_cache()
+
+    if args.production_steps > 0:
+        # 16384^2 jet (268M cells) with the learned closure and BF16 population
+        # storage, nu = eta = 5e-5, B0 = 0.02: the step, and the radially binned
+        # spectra taken every 1000 steps (moments + FP64 FFTs), timed once.
+        from paper_1705_09807_amd import learned as G
+        n16, b16 = 16384, 0.02
+        kh16 = dict(KH, B0=b16)
+        mlp = G.Mlp(G.glorot_params(0), device=dev, stream=stream)
+        mlp.set_norm(shift=[1.0, 0.0, 0.0, b16, 0.0, 0.0, 0.0],
+                     scale=[1e3, 20.0, 20.0, 100.0, 100.0, 1e3, 1e3], out_scale=[1e-6] * 4)
+        packed = mlp.pack()
+        sp = Sim(nx=n16, ny=n16, nu=5e-5, eta=5e-5, delta=LES_DELTA, dtype="bf16", schedule="fused",
+                 b_ref=(b16, 0.0), closure="learned", device=dev, stream=stream, **ghost)
+        sp.init_kh_jet(seed=0, **kh16)
+        sp.set_closure_mlp(packed)
+        sp.step(2)
+        a, b = ev(), ev()
+        a.record(stream)
+        sp.step(args.production_steps)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ms = a.elapsed_time(b) / args.production_steps
+        mom16 = torch.empty((5, n16, n16), dtype=torch.float64, device=dev)
+        sp.moments(mom16)
+        G.spectra(mom16, stream=stream)  # first call: the allocator takes the work buffer
+        a.record(stream)
+        sp.moments(mom16)
+        ek, em, _ = G.spectra(mom16, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ms_spec = a.elapsed_time(b)
+        d16 = sp.diagnostics()
+        lups16 = n16 * n16
+        extra["les16384_learned_bf16"] = {
+            "mlups": round(lups16 / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 1),
+            "spectra_ms": round(ms_spec, 2), "spectra_share_every_1000_steps": round(ms_spec / (1000 * ms), 5),
+            "nonfinite": int(d16["nonfinite"]), "e_kin": d16["e_kin"], "e_mag": d16["e_mag"],
+            # Parseval: the magnetic spectrum sums to the domain mean <|B|^2 / 2>
+            "parseval_em_rel": float(abs(em.sum().item() - d16["e_mag"]) / d16["e_mag"]),
+            "kernels": "k_moments5f + k_mlp_correct (bf16 MFMA) + k_fused_les<bf16, ..., CORR>; "
+                       "spectra: k_moments_out + k_fft_rows_big + k_fft_cols_big + k_bin_cols"}
+        log(f"production 16384^2 learned bf16: {ms * 1e3:.0f} us/step, spectra {ms_spec:.1f} ms")
+        del sp, mom16, mlp, packed, ek, em
+        torch.cuda.empty_cache()
 
     last_dns, last_les = diag_log[-1] if diag_log else ({}, {})
     out = {

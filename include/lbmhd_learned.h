@@ -163,7 +163,7 @@ int lbm_set_closure_mlp(lbm_ctx* ctx, const void* packed_dev);
 int lbm_closure_correction(lbm_ctx* ctx, float* out_dev);
 
 /* Radially binned energy spectra of an n x n periodic field, n a power of
- * two in [8, 4096]: with a_hat(k) = N^-2 sum_x a(x) exp(-2 pi i k.x / N) and
+ * two in [8, 16384]: with a_hat(k) = N^-2 sum_x a(x) exp(-2 pi i k.x / N) and
  * integer k_a in [-n/2, n/2),
  *   ek[b] = 1/2 sum_{round(|k|) = b} |u_x_hat|^2 + |u_y_hat|^2  (u = m / rho),
  *   em[b] = the same for B,  b = 0 .. lbm_spectra_bins(n) - 1,
@@ -171,7 +171,10 @@ int lbm_closure_correction(lbm_ctx* ctx, float* out_dev);
  *   m = 0 .. n/2,
  * round(r) = floor(r + 1/2).  FP64 FFTs and fixed-order sums.  mom_dev: the
  * 5 FP64 planes of lbm_moments (or the first 5 of lbm_filter_subsample).
- * work_dev: >= lbm_spectra_work_bytes(n) bytes (0 = invalid n). */
+ * work_dev: >= lbm_spectra_work_bytes(n) bytes (0 = invalid n): the row
+ * transforms (32 n^2 bytes), the per-column bins (16 n lbm_spectra_bins(n))
+ * and, beyond n = 4096, the column powers (16 n^2); 0.86 GB at 4096,
+ * 18.1 GB at 16384. */
 int32_t lbm_spectra_bins(int32_t n);
 size_t lbm_spectra_work_bytes(int32_t n);
 int lbm_spectra(const double* mom_dev, int32_t n, double* ek_dev, double* em_dev, double* ekx_dev, void* work_dev,

@@ -434,7 +434,7 @@ int lbm_closure_samples(const double* coarse_dev, int32_t nx, int32_t ny, double
 }
 
 namespace {
-bool spectra_n_ok(int32_t n) { return n >= 8 && n <= 4096 && (n & (n - 1)) == 0; }
+bool spectra_n_ok(int32_t n) { return n >= 8 && n <= 16384 && (n & (n - 1)) == 0; }
 }  // namespace
 
 int32_t lbm_spectra_bins(int32_t n) { return spectra_n_ok(n) ? lbm::spectra_bins(n) : 0; }
@@ -443,7 +443,7 @@ size_t lbm_spectra_work_bytes(int32_t n) { return spectra_n_ok(n) ? lbm::spectra
 
 int lbm_spectra(const double* mom_dev, int32_t n, double* ek_dev, double* em_dev, double* ekx_dev, void* work_dev,
                 size_t work_bytes, void* hip_stream) {
-  if (!spectra_n_ok(n)) return fail(LBM_EINVAL, "n must be a power of two in [8, 4096]");
+  if (!spectra_n_ok(n)) return fail(LBM_EINVAL, "n must be a power of two in [8, 16384]");
   if (!mom_dev || !ek_dev || !em_dev || !work_dev || !aligned(mom_dev) || !aligned(ek_dev) || !aligned(em_dev) ||
       !aligned(work_dev) || (ekx_dev && !aligned(ekx_dev)))
     return fail(LBM_EINVAL, "mom, ek, em, work (and ekx if given) must be non-NULL 256-byte aligned device pointers");

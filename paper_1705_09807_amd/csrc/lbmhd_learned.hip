@@ -885,6 +885,106 @@ k_fft_cols(const double2* __restrict__ work, int n, int bits, int nbins, double*
   }
 }
 
+// Rows and columns longer than one LDS transform (n > kFftLds): n = n1 n2
+// with n2 = kFftLds.  With x = j1 n2 + j2 and k = k1 + n1 k2 (w_m =
+// exp(-2 pi i / m)),
+//   X[k1 + n1 k2] = sum_j2 w_n2^(j2 k2) [w_n^(j2 k1) sum_j1 a[j1 n2 + j2] w_n1^(j1 k1)],
+// so each workgroup takes one residue class k1: an n1-point DFT and a twiddle
+// per element, then one n2-point FFT in LDS.  The column pass stores the
+// scaled |Z|^2 per column; k_bin_cols then bins every column in the same
+// order as k_fft_cols.
+constexpr int kFftLds = 4096, kFftLdsBits = 12;
+
+__device__ __forceinline__ double2 cmul_w(double2 v, double num, double den) {
+  double s, c;
+  sincospi(-2.0 * num / den, &s, &c);
+  return make_double2(c * v.x - s * v.y, c * v.y + s * v.x);
+}
+
+__global__ void __launch_bounds__(256)
+k_fft_rows_big(const double* __restrict__ mom, int n, int n1, double2* __restrict__ work) {
+  extern __shared__ double2 a[];
+  const int y = blockIdx.x, k1 = blockIdx.y, pair = blockIdx.z;
+  const int64_t nn = (int64_t)n * n;
+  for (int j2 = threadIdx.x; j2 < kFftLds; j2 += blockDim.x) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int j1 = 0; j1 < n1; ++j1) {
+      const int64_t c = (int64_t)y * n + (int64_t)j1 * kFftLds + j2;
+      double re, im;
+      if (pair == 0) {
+        const double r = mom[c];
+        re = mom[nn + c] / r;
+        im = mom[2 * nn + c] / r;
+      } else {
+        re = mom[3 * nn + c];
+        im = mom[4 * nn + c];
+      }
+      const double2 t = cmul_w(make_double2(re, im), double(j1 * k1), double(n1));
+      s.x += t.x;
+      s.y += t.y;
+    }
+    a[bitrev(j2, kFftLdsBits)] = cmul_w(s, double(j2) * double(k1), double(n));
+  }
+  fft_lds(a, kFftLds, kFftLdsBits);
+  for (int k2 = threadIdx.x; k2 < kFftLds; k2 += blockDim.x)
+    work[pair * nn + (int64_t)y * n + k1 + (int64_t)n1 * k2] = a[k2];
+}
+
+__global__ void __launch_bounds__(256)
+k_fft_cols_big(const double2* __restrict__ work, int n, int n1, double* __restrict__ pw) {
+  extern __shared__ double2 a[];
+  const int kxi = blockIdx.x, k1 = blockIdx.y, pair = blockIdx.z;
+  const int64_t nn = (int64_t)n * n;
+  const double inv = 1.0 / (double(n) * double(n));
+  for (int j2 = threadIdx.x; j2 < kFftLds; j2 += blockDim.x) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int j1 = 0; j1 < n1; ++j1) {
+      const double2 t =
+          cmul_w(work[pair * nn + ((int64_t)j1 * kFftLds + j2) * n + kxi], double(j1 * k1), double(n1));
+      s.x += t.x;
+      s.y += t.y;
+    }
+    a[bitrev(j2, kFftLdsBits)] = cmul_w(s, double(j2) * double(k1), double(n));
+  }
+  fft_lds(a, kFftLds, kFftLdsBits);
+  double* col = pw + pair * nn + (int64_t)kxi * n;
+  for (int k2 = threadIdx.x; k2 < kFftLds; k2 += blockDim.x) {
+    const double2 z = a[k2];
+    col[k1 + (int64_t)n1 * k2] = (z.x * inv) * (z.x * inv) + (z.y * inv) * (z.y * inv);
+  }
+}
+
+// Bins of one column of scaled |Z|^2 (k_fft_cols' walk and order).
+__global__ void __launch_bounds__(256)
+k_bin_cols(const double* __restrict__ pw, int n, int nbins, double* __restrict__ part, double* __restrict__ partx) {
+  const int kxi = blockIdx.x, pair = blockIdx.y;
+  const double* col = pw + (int64_t)pair * n * n + (int64_t)kxi * n;
+  const int kx = kxi < n / 2 ? kxi : kxi - n;
+  const int64_t kx2 = (int64_t)kx * kx;
+  double* out = part + ((int64_t)pair * n + kxi) * nbins;
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    const int64_t lo = b == 0 ? 0 : (int64_t)b * b - b + 1 - kx2;
+    const int64_t hi = (int64_t)b * b + b - kx2;
+    double s = 0.0;
+    if (hi >= 0) {
+      const int a0 = lo <= 0 ? 0 : isqrt_ceil(lo);
+      int a1 = isqrt_floor(hi);
+      if (a1 > n / 2) a1 = n / 2;
+      for (int ay = a0; ay <= a1; ++ay) {
+        const int idx[2] = {ay == n / 2 ? n / 2 : ay, n - ay};
+        const int cnt = (ay == 0 || ay == n / 2) ? 1 : 2;
+        for (int u = 0; u < cnt; ++u) s += col[idx[u]];
+      }
+    }
+    out[b] = s;
+  }
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int yi = 0; yi < n; ++yi) s += col[yi];
+    partx[(int64_t)pair * n + kxi] = s;
+  }
+}
+
 __global__ void __launch_bounds__(256)
 k_spectra_final(const double* __restrict__ part, const double* __restrict__ partx, int n, int nbins,
                 double* __restrict__ ek, double* __restrict__ em, double* __restrict__ ekx) {
@@ -1034,7 +1134,9 @@ int spectra_bins(int n) { return (int)floor(sqrt(2.0) * double(n / 2) + 0.5) + 1
 
 size_t spectra_work_bytes(int n) {
   const size_t nn = (size_t)n * n;
-  return 2 * nn * sizeof(double2) + (size_t)2 * n * spectra_bins(n) * sizeof(double) + (size_t)2 * n * sizeof(double);
+  const size_t big = n > kFftLds ? 2 * nn * sizeof(double) : 0;  // scaled |Z|^2 of the long columns
+  return 2 * nn * sizeof(double2) + big + (size_t)2 * n * spectra_bins(n) * sizeof(double) +
+         (size_t)2 * n * sizeof(double);
 }
 
 hipError_t launch_spectra(const double* mom, int n, double* ek, double* em, double* ekx, void* work, hipStream_t st) {
@@ -1043,13 +1145,27 @@ hipError_t launch_spectra(const double* mom, int n, double* ek, double* em, doub
   const int nb = spectra_bins(n);
   double2* cw = static_cast<double2*>(work);
   double* part = reinterpret_cast<double*>(cw + (size_t)2 * n * n);
+  hipError_t e;
+  if (n <= kFftLds) {
+    double* partx = part + (size_t)2 * n * nb;
+    const size_t lds = (size_t)n * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_rows, dim3(n, 2), dim3(256), lds, st, mom, n, bits, cw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fft_cols, dim3(n, 2), dim3(256), lds, st, cw, n, bits, nb, part, partx);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    double* pw = part;
+    part = pw + (size_t)2 * n * n;
+    const int n1 = n / kFftLds;
+    const size_t lds = (size_t)kFftLds * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_rows_big, dim3(n, n1, 2), dim3(256), lds, st, mom, n, n1, cw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fft_cols_big, dim3(n, n1, 2), dim3(256), lds, st, cw, n, n1, pw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_cols, dim3(n, 2), dim3(256), 0, st, pw, n, nb, part, part + (size_t)2 * n * nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   double* partx = part + (size_t)2 * n * nb;
-  const size_t lds = (size_t)n * sizeof(double2);
-  hipLaunchKernelGGL(k_fft_rows, dim3(n, 2), dim3(256), lds, st, mom, n, bits, cw);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fft_cols, dim3(n, 2), dim3(256), lds, st, cw, n, bits, nb, part, partx);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int fin = (nb > n / 2 + 1 ? nb : n / 2 + 1);
   hipLaunchKernelGGL(k_spectra_final, dim3((fin + 255) / 256), dim3(256), 0, st, part, partx, n, nb, ek, em, ekx);
   return hipGetLastError();

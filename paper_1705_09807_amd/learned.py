@@ -217,7 +217,7 @@ def spectra(mom, stream=None):
     nb = lib.lbm_spectra_bins(n)
     wb = lib.lbm_spectra_work_bytes(n)
     if nb == 0 or wb == 0:
-        raise ValueError("n must be a power of two in [8, 4096]")
+        raise ValueError("n must be a power of two in [8, 16384]")
     work = torch.empty(wb, dtype=torch.uint8, device=mom.device)
     ek = torch.empty(nb, dtype=torch.float64, device=mom.device)
     em = torch.empty(nb, dtype=torch.float64, device=mom.device)

@@ -155,10 +155,12 @@ def test_learned_closure_params_and_call_order(lib):
 
 def test_learned_sizes_and_argument_checks(lib):
     from oracle import spectra as S
-    for n in (8, 64, 1024, 4096):
+    for n in (8, 64, 1024, 4096, 8192, 16384):
         assert lib.lbm_spectra_bins(n) == S.nbins(n)
-        assert lib.lbm_spectra_work_bytes(n) > 2 * n * n * 16
-    for bad in (4, 1000, 8192):
+        # row transforms, per-column bins and, beyond 4096, the column powers
+        big = 2 * n * n * 8 if n > 4096 else 0
+        assert lib.lbm_spectra_work_bytes(n) == 2 * n * n * 16 + big + 2 * n * S.nbins(n) * 8 + 2 * n * 8
+    for bad in (4, 1000, 12288, 32768):
         assert lib.lbm_spectra_bins(bad) == 0 and lib.lbm_spectra_work_bytes(bad) == 0
     assert lib.lbm_mlp_train_work_bytes(0) == 0 and lib.lbm_mlp_train_work_bytes((1 << 20) + 1) == 0
     assert lib.lbm_mlp_train_work_bytes(4096) >= N.LBM_MLP_PACKED_BYTES + N.LBM_MLP_PARAMS * 4

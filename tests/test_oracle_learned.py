@@ -17,6 +17,7 @@ import pytest
 from oracle import learned as L
 from oracle import lbmhd_oracle as O
 from oracle import spectra as S
+import fourier_modes as FM
 from seeded_inputs import smooth_field, perturbed, offset_noise
 
 
@@ -414,6 +415,19 @@ def test_spectrum_parseval_and_brute_force():
                 s += abs(c / n ** 2) ** 2
             want[int(math.floor(math.hypot(kx, ky) + 0.5))] += 0.5 * s
     assert np.max(np.abs(E - want)) < 1e-15
+
+
+def test_many_mode_closed_form_matches_the_oracle():
+    """The closed form the GPU's large-grid spectra are checked against
+    (A^2 / 4 per mode in its bin) equals the oracle's FFT spectra on a
+    64 x 64 grid for fields of 12 random modes each."""
+    n = 64
+    rng = np.random.default_rng(64)
+    sets = [FM.random_modes(rng, n, 12) for _ in range(2)]
+    a, b = (FM.mode_field_numpy(n, m) for m in sets)
+    e, ex = FM.mode_spectra(n, sets)
+    assert np.max(np.abs(S.spectrum(a, b) - e)) < 1e-15
+    assert np.max(np.abs(S.x_spectrum(a, b) - ex)) < 1e-15
 
 
 def test_energy_spectra_sum_to_diagnostic_energies():
