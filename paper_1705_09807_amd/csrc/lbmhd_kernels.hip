@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lbmhd_device.h"
 #include "lbmhd_internal.h"
 #include "lbmhd_learned.h"
@@ -398,24 +400,19 @@ k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
   }
 }
 
-// Closure off, 16-bit storage, nx a multiple of 4: four cells per thread, so
-// every plane moves in one aligned 8-byte load and store per thread (plus one
-// 2-byte load of the neighbour column for the planes that stream along x).
-// Measured 7-9 % faster than the pair kernel at 8192^2 with FP16 and BF16
-// storage (slower with FP32, whose pair loads are already 8 bytes).
-template <typename S, typename C, bool NT>
-__global__ void __launch_bounds__(64)
-k_fused_dns_quad(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
-  using V4 = S __attribute__((ext_vector_type(4)));
-  const int x = (blockIdx.x * 64 + threadIdx.x) * 4;
-  const int y = blockIdx.y;
-  if (x >= nx) return;
-  const Rows rw = rows_of<S>(y, nx, ny);
+template <typename S> using Vec4 = S __attribute__((ext_vector_type(4)));
+
+// Four horizontally adjacent cells x .. x + 3 (x a multiple of 4, nx too):
+// every plane in one aligned four-element load, plus one load of the
+// neighbour column for the planes that stream along x.
+template <typename S, typename C>
+__device__ __forceinline__ void pull_quad(const S* __restrict__ src, int64_t plane, int nx, const Rows& rw, int x,
+                                          C (&v)[4][kQ]) {
+  using V4 = Vec4<S>;
   const uint32_t es = uint32_t(sizeof(S));
   const uint32_t x0 = uint32_t(x) * es;
   const uint32_t xw = uint32_t(x == 0 ? nx - 1 : x - 1) * es;
   const uint32_t x4 = uint32_t(x + 4 == nx ? 0 : x + 4) * es;
-  C v[4][kQ];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     const uint32_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
@@ -438,6 +435,24 @@ k_fused_dns_quad(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
       v[3][q] = decode<C>(*at(pq, yo + x4));
     }
   }
+}
+
+// Closure off, 16-bit storage, nx a multiple of 4: four cells per thread, so
+// every plane moves in one aligned 8-byte load and store per thread (plus one
+// 2-byte load of the neighbour column for the planes that stream along x).
+// Measured 7-9 % faster than the pair kernel at 8192^2 with FP16 and BF16
+// storage (slower with FP32, whose pair loads are already 8 bytes).
+template <typename S, typename C, bool NT>
+__global__ void __launch_bounds__(64)
+k_fused_dns_quad(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
+  using V4 = Vec4<S>;
+  const int x = (blockIdx.x * 64 + threadIdx.x) * 4;
+  const int y = blockIdx.y;
+  if (x >= nx) return;
+  const Rows rw = rows_of<S>(y, nx, ny);
+  const uint32_t x0 = uint32_t(x) * uint32_t(sizeof(S));
+  C v[4][kQ];
+  pull_quad<S, C>(src, plane, nx, rw, x, v);
   const Closure<C> cl = {C(0), C(0), C(0), C(0)};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -534,49 +549,106 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
     if (writer) put(2, nxt);
   }
   __syncthreads();
-  for (int y = y0; y < y1; ++y) {
-    const int s = y - y0 + 1;                 // ring slot of row y is s & 3
-    const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
-    if (more && loader) pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y + 2), nx, ny), cx, nn);
-    if (valid) {
-      const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
-      C gr[NF][2];
+  if constexpr (std::is_same<S, _Float16>::value) {
+    // FP16 storage: the row loop unrolled three times so that the three rows
+    // rotate through fixed registers (8192^2 and 16384^2: 3-7 % faster than
+    // rotating them by copies; with BF16 storage it measured 5-6 % slower,
+    // with FP32 up to 2 % slower).  row(): loads of row y + 2 into fr, the
+    // collision of cu (row y), the ring write of row y + 2 and the barrier.
+    auto row = [&](C (&cu)[kPop<QG>], C (&fr)[kPop<QG>], int y) __attribute__((always_inline)) {
+      const int s = y - y0 + 1;                 // ring slot of row y is s & 3
+      const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
+      if (more && loader) pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y + 2), nx, ny), cx, fr);
+      if (valid) {
+        const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
+        C gr[NF][2];
 #pragma unroll
-      for (int k = 0; k < NF; ++k) {
-        grad3x3<C, STENCIL>(ring[sc][k][l + 1], ring[sc][k][l - 1], ring[sn][k][l], ring[ss][k][l],
-                            ring[sn][k][l + 1], ring[sn][k][l - 1], ring[ss][k][l + 1], ring[ss][k][l - 1], gr[k][0],
-                            gr[k][1]);
-      }
-      const Mom<C> m = moments_of<QG>(cur);
-      const C ir = C(1) / (r.rho0 + m.drho);
-      Closure<C> cl;
-      if constexpr (MODE == kClosureFull) {
-        cl = closure_terms_full(gr, m.mx, m.my, r.bx0 + m.dbx, r.by0 + m.dby, ir, r.k2);
-      } else {
-        if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9 && QG == 5)
-          local_gradients(cur, m, r, gr[1][0] - gr[0][1], gr);
-        cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0], gr[3][1], ir,
-                           r.k2);
-      }
-      if constexpr (MODE == kClosureCorr) {
-        const int64_t n = (int64_t)nx * ny, ci = (int64_t)y * nx + x0 + tid;
-        const C txx = C(corr[ci]), txy = C(corr[n + ci]), tyy = C(corr[2 * n + ci]), eps = C(corr[3 * n + ci]);
-        cl.tau_xy += txy;
-        cl.tau_d += txx - tyy;
-        cl.tau_s += txx + tyy;
-        cl.eps += eps;
-      }
-      collide_q<QG>(cur, m, cl, r);
-      const uint32_t off = uint32_t(y) * uint32_t(nx) * uint32_t(sizeof(S)) + cx.c;
+        for (int k = 0; k < NF; ++k) {
+          grad3x3<C, STENCIL>(ring[sc][k][l + 1], ring[sc][k][l - 1], ring[sn][k][l], ring[ss][k][l],
+                              ring[sn][k][l + 1], ring[sn][k][l - 1], ring[ss][k][l + 1], ring[ss][k][l - 1], gr[k][0],
+                              gr[k][1]);
+        }
+        const Mom<C> m = moments_of<QG>(cu);
+        const C ir = C(1) / (r.rho0 + m.drho);
+        Closure<C> cl;
+        if constexpr (MODE == kClosureFull) {
+          cl = closure_terms_full(gr, m.mx, m.my, r.bx0 + m.dbx, r.by0 + m.dby, ir, r.k2);
+        } else {
+          if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9 && QG == 5)
+            local_gradients(cu, m, r, gr[1][0] - gr[0][1], gr);
+          cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0], gr[3][1], ir,
+                             r.k2);
+        }
+        if constexpr (MODE == kClosureCorr) {
+          const int64_t n = (int64_t)nx * ny, ci = (int64_t)y * nx + x0 + tid;
+          const C txx = C(corr[ci]), txy = C(corr[n + ci]), tyy = C(corr[2 * n + ci]), eps = C(corr[3 * n + ci]);
+          cl.tau_xy += txy;
+          cl.tau_d += txx - tyy;
+          cl.tau_s += txx + tyy;
+          cl.eps += eps;
+        }
+        collide_q<QG>(cu, m, cl, r);
+        const uint32_t off = uint32_t(y) * uint32_t(nx) * uint32_t(sizeof(S)) + cx.c;
 #pragma unroll
-      for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * plane, off), encode<S>(cur[q]));
+        for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * plane, off), encode<S>(cu[q]));
+      }
+      if (more && writer) put((s + 2) & 3, fr);
+      __syncthreads();
+    };
+    for (int y = y0;;) {
+      if (y >= y1) break;
+      row(cur, nn, y++);
+      if (y >= y1) break;
+      row(nxt, cur, y++);
+      if (y >= y1) break;
+      row(nn, nxt, y++);
     }
-    if (more && writer) put((s + 2) & 3, nn);
-    __syncthreads();
+  } else {
+    // the same row body written inline, rows rotated by copies
+    for (int y = y0; y < y1; ++y) {
+      const int s = y - y0 + 1;                 // ring slot of row y is s & 3
+      const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
+      if (more && loader) pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y + 2), nx, ny), cx, nn);
+      if (valid) {
+        const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
+        C gr[NF][2];
 #pragma unroll
-    for (int q = 0; q < kPop<QG>; ++q) {
-      cur[q] = nxt[q];
-      nxt[q] = nn[q];
+        for (int k = 0; k < NF; ++k) {
+          grad3x3<C, STENCIL>(ring[sc][k][l + 1], ring[sc][k][l - 1], ring[sn][k][l], ring[ss][k][l],
+                              ring[sn][k][l + 1], ring[sn][k][l - 1], ring[ss][k][l + 1], ring[ss][k][l - 1], gr[k][0],
+                              gr[k][1]);
+        }
+        const Mom<C> m = moments_of<QG>(cur);
+        const C ir = C(1) / (r.rho0 + m.drho);
+        Closure<C> cl;
+        if constexpr (MODE == kClosureFull) {
+          cl = closure_terms_full(gr, m.mx, m.my, r.bx0 + m.dbx, r.by0 + m.dby, ir, r.k2);
+        } else {
+          if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9 && QG == 5)
+            local_gradients(cur, m, r, gr[1][0] - gr[0][1], gr);
+          cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0], gr[3][1], ir,
+                             r.k2);
+        }
+        if constexpr (MODE == kClosureCorr) {
+          const int64_t n = (int64_t)nx * ny, ci = (int64_t)y * nx + x0 + tid;
+          const C txx = C(corr[ci]), txy = C(corr[n + ci]), tyy = C(corr[2 * n + ci]), eps = C(corr[3 * n + ci]);
+          cl.tau_xy += txy;
+          cl.tau_d += txx - tyy;
+          cl.tau_s += txx + tyy;
+          cl.eps += eps;
+        }
+        collide_q<QG>(cur, m, cl, r);
+        const uint32_t off = uint32_t(y) * uint32_t(nx) * uint32_t(sizeof(S)) + cx.c;
+#pragma unroll
+        for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * plane, off), encode<S>(cur[q]));
+      }
+      if (more && writer) put((s + 2) & 3, nn);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kPop<QG>; ++q) {
+        cur[q] = nxt[q];
+        nxt[q] = nn[q];
+      }
     }
   }
 }
@@ -913,6 +985,29 @@ k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int 
 }
 
 // rho, m_x, m_y, B_x, B_y in FP32 (5 dense planes): the network's input.
+// The five FP32 moment planes of a fused-schedule state (layout kLayoutPull):
+// the gather of the fused sweep over 256-cell row segments, one cell per
+// thread.  Same values as k_moments5f; measured 16-29 % faster than its
+// 64 x 4 tiles at 8192^2 and 16384^2 with 16-bit storage (four cells per
+// thread with 8-byte loads was 6-8 % slower than one).
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_moments5f_row(const S* __restrict__ src, float* __restrict__ out, int nx, int ny, int64_t plane, RestRef ref) {
+  using C = typename ComputeOf<S>::type;
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= nx) return;
+  C v[kQ];
+  pull_cell<S, C, 5>(src, plane, rows_of<S>(y, nx, ny), cols_of<S>(x, nx), v);
+  const Mom<C> m = moments19(v);
+  const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
+  out[c0] = float(C(ref.rho0) + m.drho);
+  out[n + c0] = float(m.mx);
+  out[2 * n + c0] = float(m.my);
+  out[3 * n + c0] = float(C(ref.bx0) + m.dbx);
+  out[4 * n + c0] = float(C(ref.by0) + m.dby);
+}
+
 template <typename S>
 __global__ void __launch_bounds__(256)
 k_moments5f(const S* __restrict__ base, float* __restrict__ out, int nx, int ny, int64_t plane, int layout,
@@ -1204,8 +1299,14 @@ static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& 
 
 template <typename S>
 static hipError_t mom5f_typed(const Launch& L, int64_t t, float* out) {
+  const int layout = layout_at(L, t);
+  if (layout == kLayoutPull) {
+    hipLaunchKernelGGL((k_moments5f_row<S>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream,
+                       buffer_at<S>(L, t), out, L.nx, L.ny, L.plane, rest_ref(L));
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_moments5f<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), out, L.nx,
-                     L.ny, L.plane, layout_at(L, t), rest_ref(L));
+                     L.ny, L.plane, layout, rest_ref(L));
   return hipGetLastError();
 }
 

@@ -361,9 +361,13 @@ def test_step_requires_a_network():
         s.step(1)
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("ood", [False, True])
 @pytest.mark.parametrize("nx,ny", [(96, 64), (70, 37)])
-def test_correction_of_state_matches_oracle(nx, ny, ood):
+def test_correction_of_state_matches_oracle(nx, ny, ood, dtype):
+    """The correction of a state (moments of the stored state, features,
+    network, out-of-range fallback) against the oracle's on the state the GPU
+    holds, for FP64, FP32 and BF16 storage."""
     G = _gpu()
     f, g = _smooth_state(nx, ny, 61)
     p = _params(62)
@@ -374,7 +378,7 @@ def test_correction_of_state_matches_oracle(nx, ny, ood):
         rho = f.sum(axis=0)
         scale[0] = np.float32(6.0 / (0.6 * np.abs(rho - shift[0]).max()))
         c64[:9] = scale[0]
-    s = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale)
+    s = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale, dtype=dtype)
     corr = s.closure_correction().cpu().numpy().astype(np.float64)
     st = s.get_state().cpu().numpy()
     fo, go = st[:9], np.stack([st[9:14], st[14:19]], axis=1)
