@@ -739,7 +739,7 @@ def main() -> int:
                 "fine_equivalent_mlups": round(64 * n_l / (ms * 1e-3) / 1e6, 1),
                 "note": "fine-equivalent: a 4x coarser grid (16x fewer cells) and 4x longer steps "
                         "than the 4096^2 DNS it stands for",
-                "kernels": "k_moments5f + k_mlp_correct (bf16 MFMA) + k_fused_les<..., CORR>"}
+                "kernels": "k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<..., CORR>"}
             log(f"learned les 1024^2 {dt}: {ms * 1e3:.1f} us/step")
             del sl
         del mlp, packed
@@ -809,7 +809,7 @@ def main() -> int:
             "nonfinite": int(d16["nonfinite"]), "e_kin": d16["e_kin"], "e_mag": d16["e_mag"],
             # Parseval: the magnetic spectrum sums to the domain mean <|B|^2 / 2>
             "parseval_em_rel": float(abs(em.sum().item() - d16["e_mag"]) / d16["e_mag"]),
-            "kernels": "k_moments5f + k_mlp_correct (bf16 MFMA) + k_fused_les<bf16, ..., CORR>; "
+            "kernels": "k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<bf16, ..., CORR>; "
                        "spectra: k_moments_out + k_fft_rows_big + k_fft_cols_big + k_bin_cols"}
         log(f"production 16384^2 learned bf16: {ms * 1e3:.0f} us/step, spectra {ms_spec:.1f} ms")
         del sp, mom16, mlp, packed, ek, em

@@ -987,9 +987,9 @@ k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int 
 // rho, m_x, m_y, B_x, B_y in FP32 (5 dense planes): the network's input.
 // The five FP32 moment planes of a fused-schedule state (layout kLayoutPull):
 // the gather of the fused sweep over 256-cell row segments, one cell per
-// thread.  Same values as k_moments5f; measured 16-29 % faster than its
-// 64 x 4 tiles at 8192^2 and 16384^2 with 16-bit storage (four cells per
-// thread with 8-byte loads was 6-8 % slower than one).
+// thread.  Measured 16-29 % faster at 8192^2 and 16384^2 with 16-bit storage
+// than a 64 x 4 tile gather with 64-bit indices (four cells per thread with
+// 8-byte loads was 6-8 % slower than one).
 template <typename S>
 __global__ void __launch_bounds__(256)
 k_moments5f_row(const S* __restrict__ src, float* __restrict__ out, int nx, int ny, int64_t plane, RestRef ref) {
@@ -999,26 +999,6 @@ k_moments5f_row(const S* __restrict__ src, float* __restrict__ out, int nx, int 
   if (x >= nx) return;
   C v[kQ];
   pull_cell<S, C, 5>(src, plane, rows_of<S>(y, nx, ny), cols_of<S>(x, nx), v);
-  const Mom<C> m = moments19(v);
-  const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
-  out[c0] = float(C(ref.rho0) + m.drho);
-  out[n + c0] = float(m.mx);
-  out[2 * n + c0] = float(m.my);
-  out[3 * n + c0] = float(C(ref.bx0) + m.dbx);
-  out[4 * n + c0] = float(C(ref.by0) + m.dby);
-}
-
-template <typename S>
-__global__ void __launch_bounds__(256)
-k_moments5f(const S* __restrict__ base, float* __restrict__ out, int nx, int ny, int64_t plane, int layout,
-            RestRef ref) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  if (x >= nx || y >= ny) return;
-  using C = typename ComputeOf<S>::type;
-  C v[kQ];
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) v[q] = decode<C>(base[natural_index(q, x, y, nx, ny, plane, layout)]);
   const Mom<C> m = moments19(v);
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
   out[c0] = float(C(ref.rho0) + m.drho);
@@ -1298,15 +1278,12 @@ static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& 
 }
 
 template <typename S>
+// The learned closure runs in the fused schedule only (checked at creation),
+// so the state is always in the pull layout here.
 static hipError_t mom5f_typed(const Launch& L, int64_t t, float* out) {
-  const int layout = layout_at(L, t);
-  if (layout == kLayoutPull) {
-    hipLaunchKernelGGL((k_moments5f_row<S>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream,
-                       buffer_at<S>(L, t), out, L.nx, L.ny, L.plane, rest_ref(L));
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL((k_moments5f<S>), tile_grid(L.nx, L.ny), kTile, 0, L.stream, buffer_at<S>(L, t), out, L.nx,
-                     L.ny, L.plane, layout, rest_ref(L));
+  if (layout_at(L, t) != kLayoutPull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_moments5f_row<S>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream,
+                     buffer_at<S>(L, t), out, L.nx, L.ny, L.plane, rest_ref(L));
   return hipGetLastError();
 }
 
