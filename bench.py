@@ -341,11 +341,12 @@ def jet_study(args, dev, stream) -> int:
 
 
 def learned_study(args, dev, stream) -> int:
-    """A-posteriori test of the learned closure (filtered DNS -> 4x coarser LES).
+    """A-posteriori test of the learned closure (filtered DNS -> F x coarser
+    LES, F = --study-factor, 4 by default).
 
-    DNS 4096^2 (FP32) of the jet at nu_DNS = 4 nu_LES (constant Reynolds
-    number), Gaussian filter of width 16 fine cells, 4x subsampled to 1024^2
-    (Delta = 4 LES cells).  The network is trained on two seeds with the
+    DNS 4096^2 (FP32) of the jet at nu_DNS = F nu_LES (constant Reynolds
+    number), Gaussian filter of width 4 F fine cells, subsampled every F-th
+    cell to (4096 / F)^2 (Delta = 4 LES cells).  The network is trained on two seeds with the
     library's kernels; on a held-out seed the LES (analytic closure, and
     analytic plus learned correction; FP32 and BF16 storage for the learned
     one) starts from the filtered DNS initial state and runs alongside the
@@ -367,7 +368,8 @@ def learned_study(args, dev, stream) -> int:
     # single-relaxation-time magnetic distribution, runs at eta <= 3e-3
     # (s_m >= 1.96) overflow at roll-up on both grids (div B grows first);
     # eta = 1e-2 keeps them finite.
-    setup = TR.JetSetup(n_fine=4096, factor=4, delta_fine=16.0, nu_les=args.study_nu, eta_les=args.study_eta,
+    setup = TR.JetSetup(n_fine=4096, factor=args.study_factor, delta_fine=4.0 * args.study_factor,
+                        nu_les=args.study_nu, eta_les=args.study_eta,
                         ghost=GHOST,
                         U0=KH["U0"],
                         delta_over_L=KH["delta_over_L"], B0=KH["B0"], noise_amp=1e-4,
@@ -531,7 +533,8 @@ def main() -> int:
                          "relative L2 errors against the FP64 run as one JSON line")
     ap.add_argument("--learned-study", type=int, default=0, metavar="LES_STEPS",
                     help="instead of the benchmark: train the learned closure on filtered 4096^2 DNS and "
-                         "compare learned and analytic 1024^2 LES with the filtered DNS of a held-out seed "
+                         "compare learned and analytic LES (1024^2, or 4096/--study-factor) with the filtered "
+                         "DNS of a held-out seed "
                          "over LES_STEPS steps (one JSON line)")
     ap.add_argument("--jet-study", type=int, default=0, metavar="T",
                     help="instead of the benchmark: the magnetized sech^2 jet of the paper, LES runs of T "
@@ -544,6 +547,8 @@ def main() -> int:
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--study-nu", type=float, default=1e-3, help="LES-grid viscosity of the study")
     ap.add_argument("--study-eta", type=float, default=1e-2, help="LES-grid resistivity of the study")
+    ap.add_argument("--study-factor", type=int, default=4, choices=[2, 4, 8],
+                    help="coarsening of the learned-closure study (LES grid 4096 / factor)")
     ap.add_argument("--out-dir", default="", help="folder for the jet study's per-snapshot spectra")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, run a plain device-to-device copy of this many bytes "
