@@ -1,0 +1,40 @@
+"""Host-side checks of bench.py's contract (no GPU needed)."""
+
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    """--gpus N > 1 exits with status 2 and says why, before touching a GPU."""
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120, cwd=ROOT)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr
+    assert res.stdout == ""
+
+
+def test_traffic_summaries_parse(tmp_path, monkeypatch):
+    """A counter summary is used only for the kernel source and workload it was
+    taken on: matching hash and size give its bytes, anything else None."""
+    algorithmic = 152 * 4096 * 4096
+    got = bench.measured_traffic("fused_dns_fp32", 4096 * 4096)
+    assert got is None or algorithmic < got < 1.5 * algorithmic
+    assert bench.measured_traffic("fused_dns_fp32", 1024 * 1024) is None
+    assert bench.measured_traffic("no_such_kernel", 4096 * 4096) is None
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    text = ("kernel_source_sha256: {h}\nlups_per_launch: 100\nhbm_bytes_per_launch: 16000\n")
+    (prof / "traffic_k.txt").write_text(text.format(h=bench.kernel_source_hash()))
+    (prof / "traffic_old.txt").write_text(text.format(h="0" * 16))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("k", 100) == 16000.0
+    assert bench.measured_traffic("k", 101) is None
+    assert bench.measured_traffic("old", 100) is None
