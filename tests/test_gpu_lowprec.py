@@ -92,6 +92,31 @@ def test_one_step_from_random_state(dtype, schedule, delta, shape):
 
 
 @pytest.mark.parametrize("dtype", ["fp16", "bf16"])
+@pytest.mark.parametrize("ny", [512, 768, 1280])
+def test_closure_sweep_segment_heights(dtype, ny):
+    """64-column grids of 512, 768 and 1280 rows give the closure sweep
+    segments of 2, 3 and 5 rows on a 256-CU device, so the FP16 sweep's
+    three-way unrolled row loop ends in each of its phases; three steps, each
+    from the rounded state the GPU holds, against the oracle."""
+    nx = 64
+    f = perturbed(O.W9, (9, ny, nx), 15, 0.15)
+    g = offset_noise(np.zeros(10), (10, ny, nx), 16, 0.01).reshape(5, 2, ny, nx)
+    s = _sim(nx=nx, ny=ny, nu=0.02, eta=0.03, delta=2.0, dtype=dtype)
+    s.set_state(torch.from_numpy(pack(f, g)), 0)
+    for step in range(3):
+        st0 = s.get_state().cpu().numpy()
+        s.step(1)
+        o = O.Oracle(nx, ny, 0.02, 0.03, delta=2.0)
+        o.set_state(*unpack(st0))
+        o.step(1)
+        ref = pack(*o.state()[:2])
+        err = np.abs(s.get_state().cpu().numpy() - ref).max()
+        bound = UNIT[dtype] * np.abs(deviation(ref)).max() + 1e-6
+        print(f"{dtype} 64x{ny} step {step}: max error {err:.2e}, bound {bound:.2e}", flush=True)
+        assert err <= bound
+
+
+@pytest.mark.parametrize("dtype", ["fp16", "bf16"])
 @pytest.mark.parametrize("steps", [100, 1000])
 def test_kh_64_fields(dtype, steps):
     """Per-field relative L2 of rho, m, B after n steps of the 64^2 LES jet
