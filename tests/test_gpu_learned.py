@@ -363,7 +363,7 @@ def test_step_requires_a_network():
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("ood", [False, True])
-@pytest.mark.parametrize("nx,ny", [(96, 64), (70, 37)])
+@pytest.mark.parametrize("nx,ny", [(96, 64), (70, 37), (67, 33)])
 def test_correction_of_state_matches_oracle(nx, ny, ood, dtype):
     """The correction of a state (moments of the stored state, features,
     network, out-of-range fallback) against the oracle's on the state the GPU
@@ -390,7 +390,8 @@ def test_correction_of_state_matches_oracle(nx, ny, ood, dtype):
     got_ood = (corr == 0).all(axis=0).ravel()
     assert np.array_equal(got_ood[decided], oo[decided])
     if ood:
-        assert 0.05 < oo.mean() < 0.95
+        # both branches exercised (the flagged share depends on the shape's field)
+        assert 0.02 < oo.mean() < 0.98
     else:
         assert not oo.any()
     rows = lambda a: (a / out_scale[:, None, None]).reshape(4, -1).T[decided]
