@@ -819,6 +819,12 @@ __device__ void fft_lds(double2* a, int n, int bits) {
   __syncthreads();
 }
 
+// Column of a column-pass workgroup.  Workgroups are dealt to the 8 XCDs in
+// turn; this gives each XCD a contiguous range of columns, so the workgroups
+// that read neighbouring columns (the same cache lines of every row) share an
+// L2.  n is a power of two >= 8.
+__device__ __forceinline__ int column_of_block(int bx, int n) { return (bx & 7) * (n >> 3) + (bx >> 3); }
+
 __global__ void __launch_bounds__(256)
 k_fft_rows(const double* __restrict__ mom, int n, int bits, double2* __restrict__ work) {
   extern __shared__ double2 a[];
@@ -845,7 +851,7 @@ __global__ void __launch_bounds__(256)
 k_fft_cols(const double2* __restrict__ work, int n, int bits, int nbins, double* __restrict__ part,
            double* __restrict__ partx) {
   extern __shared__ double2 a[];
-  const int kxi = blockIdx.x, pair = blockIdx.y;
+  const int kxi = column_of_block(blockIdx.x, n), pair = blockIdx.y;
   const int64_t nn = (int64_t)n * n;
   for (int y = threadIdx.x; y < n; y += blockDim.x) a[bitrev(y, bits)] = work[pair * nn + (int64_t)y * n + kxi];
   fft_lds(a, n, bits);
@@ -933,7 +939,7 @@ k_fft_rows_big(const double* __restrict__ mom, int n, int n1, double2* __restric
 __global__ void __launch_bounds__(256)
 k_fft_cols_big(const double2* __restrict__ work, int n, int n1, double* __restrict__ pw) {
   extern __shared__ double2 a[];
-  const int kxi = blockIdx.x, k1 = blockIdx.y, pair = blockIdx.z;
+  const int kxi = column_of_block(blockIdx.x, n), k1 = blockIdx.y, pair = blockIdx.z;
   const int64_t nn = (int64_t)n * n;
   const double inv = 1.0 / (double(n) * double(n));
   for (int j2 = threadIdx.x; j2 < kFftLds; j2 += blockDim.x) {
@@ -985,23 +991,38 @@ k_bin_cols(const double* __restrict__ pw, int n, int nbins, double* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(256)
+// Sums of the per-column bins in a fixed order: thread (bin, s) of a 64 x 16
+// block adds the columns s, s + 16, s + 32, ... of its bin (consecutive bins
+// are consecutive addresses), then the 16 partial sums are added in order of s.
+__global__ void __launch_bounds__(1024)
 k_spectra_final(const double* __restrict__ part, const double* __restrict__ partx, int n, int nbins,
                 double* __restrict__ ek, double* __restrict__ em, double* __restrict__ ekx) {
-  const int b = blockIdx.x * 256 + threadIdx.x;
+  __shared__ double red[2][16][64];
+  const int bl = threadIdx.x, sl = threadIdx.y;
+  const int b = blockIdx.x * 64 + bl;
+  double su = 0.0, sb = 0.0;
   if (b < nbins) {
-    double su = 0.0, sb = 0.0;
-    for (int k = 0; k < n; ++k) {
+    for (int k = sl; k < n; k += 16) {
       su += part[(int64_t)k * nbins + b];
       sb += part[((int64_t)n + k) * nbins + b];
     }
-    ek[b] = 0.5 * su;
-    em[b] = 0.5 * sb;
   }
-  if (ekx && b <= n / 2) {
-    double s = partx[b];
-    if (b != 0 && b != n / 2) s += partx[n - b];
-    ekx[b] = 0.5 * s;
+  red[0][sl][bl] = su;
+  red[1][sl][bl] = sb;
+  __syncthreads();
+  if (sl == 0 && b < nbins) {
+    double tu = 0.0, tb = 0.0;
+    for (int i = 0; i < 16; ++i) {
+      tu += red[0][i][bl];
+      tb += red[1][i][bl];
+    }
+    ek[b] = 0.5 * tu;
+    em[b] = 0.5 * tb;
+  }
+  if (ekx && sl == 1 && b <= n / 2) {
+    double x = partx[b];
+    if (b != 0 && b != n / 2) x += partx[n - b];
+    ekx[b] = 0.5 * x;
   }
 }
 
@@ -1167,7 +1188,7 @@ hipError_t launch_spectra(const double* mom, int n, double* ek, double* em, doub
   }
   double* partx = part + (size_t)2 * n * nb;
   const int fin = (nb > n / 2 + 1 ? nb : n / 2 + 1);
-  hipLaunchKernelGGL(k_spectra_final, dim3((fin + 255) / 256), dim3(256), 0, st, part, partx, n, nb, ek, em, ekx);
+  hipLaunchKernelGGL(k_spectra_final, dim3((fin + 63) / 64), dim3(64, 16), 0, st, part, partx, n, nb, ek, em, ekx);
   return hipGetLastError();
 }
 
