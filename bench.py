@@ -523,7 +523,7 @@ def main() -> int:
     ap.add_argument("--learned-steps", type=int, default=300,
                     help="steps of the supplementary 1024^2 learned-closure LES timing (0 = skip)")
     ap.add_argument("--production-steps", type=int, default=5,
-                    help="steps of the supplementary 16384^2 learned-closure BF16 timing (0 = skip)")
+                    help="steps of the supplementary 16384^2 learned-closure timings, BF16 and FP16 (0 = skip)")
     ap.add_argument("--cpu-les-steps", type=int, default=15)
     ap.add_argument("--cpu-dns-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -776,48 +776,61 @@ def main() -> int:
                 torch.cuda.empty_cache()
 
     if args.production_steps > 0:
-        # 16384^2 jet (268M cells) with the learned closure and BF16 population
-        # storage, nu = eta = 5e-5, B0 = 0.02: the step, and the radially binned
-        # spectra taken every 1000 steps (moments + FP64 FFTs), timed once.
+        # 16384^2 jet (268M cells) with the learned closure, nu = eta = 5e-5,
+        # B0 = 0.02, BF16 population storage (the production configuration)
+        # and FP16 (the 16-bit storage that keeps the growth rate): the step,
+        # and with BF16 the radially binned spectra taken every 1000 steps
+        # (moments + FP64 FFTs), timed once.
         from paper_1705_09807_amd import learned as G
         n16, b16 = 16384, 0.02
         kh16 = dict(KH, B0=b16)
+        lups16 = n16 * n16
         mlp = G.Mlp(G.glorot_params(0), device=dev, stream=stream)
         mlp.set_norm(shift=[1.0, 0.0, 0.0, b16, 0.0, 0.0, 0.0],
                      scale=[1e3, 20.0, 20.0, 100.0, 100.0, 1e3, 1e3], out_scale=[1e-6] * 4)
         packed = mlp.pack()
-        sp = Sim(nx=n16, ny=n16, nu=5e-5, eta=5e-5, delta=LES_DELTA, dtype="bf16", schedule="fused",
-                 b_ref=(b16, 0.0), closure="learned", device=dev, stream=stream, **ghost)
-        sp.init_kh_jet(seed=0, **kh16)
-        sp.set_closure_mlp(packed)
-        sp.step(2)
-        a, b = ev(), ev()
-        a.record(stream)
-        sp.step(args.production_steps)
-        b.record(stream)
-        torch.cuda.synchronize(dev)
-        ms = a.elapsed_time(b) / args.production_steps
-        mom16 = torch.empty((5, n16, n16), dtype=torch.float64, device=dev)
-        sp.moments(mom16)
-        G.spectra(mom16, stream=stream)  # first call: the allocator takes the work buffer
-        a.record(stream)
-        sp.moments(mom16)
-        ek, em, _ = G.spectra(mom16, stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize(dev)
-        ms_spec = a.elapsed_time(b)
-        d16 = sp.diagnostics()
-        lups16 = n16 * n16
-        extra["les16384_learned_bf16"] = {
-            "mlups": round(lups16 / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 1),
-            "spectra_ms": round(ms_spec, 2), "spectra_share_every_1000_steps": round(ms_spec / (1000 * ms), 5),
-            "nonfinite": int(d16["nonfinite"]), "e_kin": d16["e_kin"], "e_mag": d16["e_mag"],
-            # Parseval: the magnetic spectrum sums to the domain mean <|B|^2 / 2>
-            "parseval_em_rel": float(abs(em.sum().item() - d16["e_mag"]) / d16["e_mag"]),
-            "kernels": "k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<bf16, ..., CORR>; "
-                       "spectra: k_moments_out + k_fft_rows_big + k_fft_cols_big + k_bin_cols"}
-        log(f"production 16384^2 learned bf16: {ms * 1e3:.0f} us/step, spectra {ms_spec:.1f} ms")
-        del sp, mom16, mlp, packed, ek, em
+        for dt in ("bf16", "fp16"):
+            sp = Sim(nx=n16, ny=n16, nu=5e-5, eta=5e-5, delta=LES_DELTA, dtype=dt, schedule="fused",
+                     b_ref=(b16, 0.0), closure="learned", device=dev, stream=stream, **ghost)
+            sp.init_kh_jet(seed=0, **kh16)
+            sp.set_closure_mlp(packed)
+            sp.step(2)
+            a, b = ev(), ev()
+            a.record(stream)
+            sp.step(args.production_steps)
+            b.record(stream)
+            torch.cuda.synchronize(dev)
+            ms = a.elapsed_time(b) / args.production_steps
+            rec = {"mlups": round(lups16 / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 1),
+                   "kernels": f"k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<{dt}, ..., CORR>"}
+            if dt == "bf16":
+                mom16 = torch.empty((5, n16, n16), dtype=torch.float64, device=dev)
+                sp.moments(mom16)
+                G.spectra(mom16, stream=stream)  # first call: the allocator takes the work buffer
+                a.record(stream)
+                sp.moments(mom16)
+                ek, em, _ = G.spectra(mom16, stream=stream)
+                b.record(stream)
+                torch.cuda.synchronize(dev)
+                ms_spec = a.elapsed_time(b)
+                d16 = sp.diagnostics()
+                rec.update({
+                    "spectra_ms": round(ms_spec, 2),
+                    "spectra_share_every_1000_steps": round(ms_spec / (1000 * ms), 5),
+                    "nonfinite": int(d16["nonfinite"]), "e_kin": d16["e_kin"], "e_mag": d16["e_mag"],
+                    # Parseval: the magnetic spectrum sums to the domain mean <|B|^2 / 2>
+                    "parseval_em_rel": float(abs(em.sum().item() - d16["e_mag"]) / d16["e_mag"]),
+                    "spectra_kernels": "k_moments_out + k_fft_rows_big + k_fft_cols_big + k_bin_cols + "
+                                       "k_spectra_final"})
+                log(f"production 16384^2 spectra {ms_spec:.1f} ms")
+                del mom16, ek, em
+            else:
+                rec["nonfinite"] = int(sp.diagnostics()["nonfinite"])
+            extra[f"les16384_learned_{dt}"] = rec
+            log(f"production 16384^2 learned {dt}: {ms * 1e3:.0f} us/step")
+            del sp
+            torch.cuda.empty_cache()
+        del mlp, packed
         torch.cuda.empty_cache()
 
     last_dns, last_les = diag_log[-1] if diag_log else ({}, {})

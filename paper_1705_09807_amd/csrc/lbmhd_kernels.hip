@@ -549,12 +549,14 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
     if (writer) put(2, nxt);
   }
   __syncthreads();
-  if constexpr (std::is_same<S, _Float16>::value) {
-    // FP16 storage: the row loop unrolled three times so that the three rows
-    // rotate through fixed registers (8192^2 and 16384^2: 3-7 % faster than
-    // rotating them by copies; with BF16 storage it measured 5-6 % slower,
-    // with FP32 up to 2 % slower).  row(): loads of row y + 2 into fr, the
-    // collision of cu (row y), the ring write of row y + 2 and the barrier.
+  if constexpr (std::is_same<S, _Float16>::value && MODE == kClosurePlain) {
+    // FP16 storage, plain closure: the row loop unrolled three times so that
+    // the three rows rotate through fixed registers (8192^2 and 16384^2: 3-7 %
+    // faster than rotating them by copies; with BF16 storage it measured 5-6 %
+    // slower, with FP32 up to 2 % slower, and with the correction or density
+    // terms it needs registers that cost a wave per SIMD).  row(): loads of
+    // row y + 2 into fr, the collision of cu (row y), the ring write of row
+    // y + 2 and the barrier.
     auto row = [&](C (&cu)[kPop<QG>], C (&fr)[kPop<QG>], int y) __attribute__((always_inline)) {
       const int s = y - y0 + 1;                 // ring slot of row y is s & 3
       const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
