@@ -25,7 +25,8 @@ learned
     closure in the same four components, the network's input patches, a
     two-hidden-layer network with the GPU's bfloat16 roundings, its loss
     gradients and Adam.  ``Oracle(closure_correction=...)`` adds a correction
-    to the analytic closure.
+    to the analytic closure, evaluated every step or, with
+    ``correction_every=K``, every K-th step and held in between.
 spectra
     Radially binned kinetic and magnetic energy spectra.
 

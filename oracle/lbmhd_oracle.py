@@ -486,7 +486,7 @@ class Oracle:
     def __init__(self, nx: int, ny: int, nu: float, eta: float, delta: float = 0.0,
                  closure_scale: float = 1.0, s5=None, s6=None, s7=None, s8=None,
                  grad_stencil: str = "iso9", closure_correction=None, closure_time: str = "sync",
-                 density_gradients: bool = False, mag_lattice: str = "d2q5"):
+                 density_gradients: bool = False, mag_lattice: str = "d2q5", correction_every: int = 1):
         if nx < 4 or ny < 4:
             raise ValueError("grid must be at least 4 x 4")
         self.nx, self.ny = int(nx), int(ny)
@@ -502,6 +502,13 @@ class Oracle:
         # optional learned correction: (rho, m_x, m_y, B_x, B_y) -> [4, ny, nx] of
         # (tau_xx, tau_xy, tau_yy, eps) added to the analytic closure terms
         self.closure_correction = closure_correction
+        # the correction is evaluated from the state being collided at every
+        # step t with t % correction_every == 0 and at the first step after an
+        # initial or injected state, and held in between
+        if int(correction_every) < 1:
+            raise ValueError("correction_every must be >= 1")
+        self.correction_every = int(correction_every)
+        self._corr = None
         # "sync": gradients of the moments of the state being collided (Sec. 2.1,
         # Sec. 3).  "lagged": gradients of the previous step's moments (the
         # single-sweep variant of the in-place schedule); the first step after
@@ -548,6 +555,7 @@ class Oracle:
                                             pert_amp_over_U0, noise_amp, seed, self.mag_lattice)
         self.t = 0
         self._prev = None
+        self._corr = None
 
     def init_sech2_jet(self, U0=4.88e-2, B0=0.005 * 4.88e-2, pert=0.01, k=4, rho0=1.0):
         """The magnetized jet of Sec. 4 on the whole grid at t = 0 (see
@@ -557,12 +565,14 @@ class Oracle:
         self.f, self.g = sech2_jet_populations(x, y, self.nx, self.ny, U0, B0, pert, k, rho0, self.mag_lattice)
         self.t = 0
         self._prev = None
+        self._corr = None
 
     def set_state(self, f, g, t: int = 0):
         self.f = np.array(f, dtype=np.float64).reshape(9, self.ny, self.nx)
         self.g = np.array(g, dtype=np.float64).reshape(self.qg, 2, self.ny, self.nx)
         self.t = int(t)
         self._prev = None
+        self._corr = None
 
     def state(self):
         """(f, g, t): copies of the post-streaming populations at time t."""
@@ -608,7 +618,9 @@ class Oracle:
         if self.closure_correction is not None:
             # tau_xy enters M3, tau_xx - tau_yy M4, -3 (tau_xx + tau_yy) M7 and M8,
             # eps the induction moment Lam[x, y] = -Lam[y, x]
-            c = self.closure_correction(rho, mx, my, Bx, By)
+            if self._corr is None or self.t % self.correction_every == 0:
+                self._corr = self.closure_correction(rho, mx, my, Bx, By)
+            c = self._corr
             meq[3] = meq[3] + c[1]
             meq[4] = meq[4] + c[0] - c[2]
             meq[7] = meq[7] - 3.0 * (c[0] + c[2])

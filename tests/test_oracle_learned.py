@@ -352,6 +352,52 @@ def test_hook_fed_the_analytic_closure_reproduces_les(stencil):
     assert np.max(np.abs(fd - fl)) > 1e-6            # the closure matters here
 
 
+def test_held_correction_composes_from_constant_segments():
+    """correction_every = K evaluates the correction at the first step after
+    an injected state and at every t with t % K == 0, and holds it in between:
+    the run equals segments of single-step oracles each fed the constant
+    correction of its own starting state."""
+    nx, ny, delta, K, t0, n = 16, 12, 2.0, 3, 2, 7
+    f, g = _random_state(nx, ny, 35)
+    calls = []
+
+    def corr_of(rho, mx, my, bx, by):
+        calls.append(1)
+        return 0.3 * L.analytic_subgrid(rho, mx, my, bx, by, delta)
+
+    kw = dict(delta=delta, s5=1.3, s6=1.5, s7=1.7, s8=1.1)
+    held = O.Oracle(nx, ny, 0.02, 0.03, closure_correction=corr_of, correction_every=K, **kw)
+    held.set_state(f, g, t=t0)
+    held.step(n)
+    assert len(calls) == 3                               # t = 2 (injected), 3, 6
+    # segments [2, 3), [3, 6), [6, 9)
+    fs, gs = f, g
+    for a, b in ((2, 3), (3, 6), (6, 9)):
+        c = 0.3 * L.analytic_subgrid(*O.Oracle._moments(fs, gs), delta)
+        seg = O.Oracle(nx, ny, 0.02, 0.03, closure_correction=lambda *args, c=c: c, **kw)
+        seg.set_state(fs, gs, t=a)
+        seg.step(b - a)
+        fs, gs, t = seg.state()
+        assert t == b
+    fh, gh, th = held.state()
+    assert th == t0 + n
+    assert np.max(np.abs(fh - fs)) < 1e-15 and np.max(np.abs(gh - gs)) < 1e-15
+    # holding matters: evaluating every step gives a different state
+    calls.clear()
+    every = O.Oracle(nx, ny, 0.02, 0.03, closure_correction=corr_of, **kw)
+    every.set_state(f, g, t=t0)
+    every.step(n)
+    assert len(calls) == n
+    assert np.max(np.abs(every.state()[0] - fh)) > 1e-9
+    # a new injected state evaluates again at once, whatever t is
+    calls.clear()
+    held.set_state(f, g, t=4)
+    held.step(1)
+    assert len(calls) == 1
+    with pytest.raises(ValueError):
+        O.Oracle(nx, ny, 0.02, 0.03, closure_correction=corr_of, correction_every=0)
+
+
 def test_learned_correction_zero_network_and_ood():
     nx, ny = 12, 10
     f, g = _random_state(nx, ny, 41)
