@@ -158,7 +158,8 @@ def variant_oracle_rates(n: int = 512, steps: int = 2) -> dict:
             o.step(steps)
             dt = time.perf_counter() - t0
             out[key] = {"oracle_mlups": round(n * n * steps / dt / 1e6, 3),
-                        "oracle_sample": f"FP64 NumPy oracle, 1 thread, {n}^2 x {steps} steps, {dt:.2f} s"}
+                        "oracle_sample": f"FP64 NumPy oracle, 1 thread, {n}^2 x {steps} steps, {dt:.2f} s"
+                                         + ("; network evaluated every step" if "closure_correction" in kw else "")}
             log(f"oracle {key}: {dt:.2f} s")
     finally:
         if ctx is not None:
@@ -347,10 +348,10 @@ def learned_study(args, dev, stream) -> int:
     DNS 4096^2 (FP32) of the jet at nu_DNS = F nu_LES (constant Reynolds
     number), Gaussian filter of width 4 F fine cells, subsampled every F-th
     cell to (4096 / F)^2 (Delta = 4 LES cells).  The network is trained on two seeds with the
-    library's kernels; on a held-out seed the LES (analytic closure, and
-    analytic plus learned correction; FP32 and BF16 storage for the learned
-    one) starts from the filtered DNS initial state and runs alongside the
-    DNS.  Reported: the relative L2 error of the total-energy spectrum
+    library's kernels; on a held-out seed the LES (analytic closure with FP32
+    and FP16 storage, analytic plus learned correction with FP32, FP16 and
+    BF16 storage, and with the network evaluated every --corr-every steps)
+    starts from the filtered DNS initial state and runs alongside the DNS.  Reported: the relative L2 error of the total-energy spectrum
     E_K + E_M over the bins 1 .. N_LES/4 against the filtered DNS at several
     times, the growth rate of the streamwise k_x = 1 mode, a-priori subgrid
     errors, and wall-clock throughput of each run.  One JSON line on stdout.
@@ -396,16 +397,22 @@ def learned_study(args, dev, stream) -> int:
     seed = 3
     dns = TR.dns(setup, seed)
     c0 = TR.filtered(setup, dns)
-    runs = {"analytic_fp32": ("analytic", "fp32"), "learned_fp32": ("learned", "fp32"),
-            "learned_fp16": ("learned", "fp16"), "learned_bf16": ("learned", "bf16")}
+    K = args.corr_every
+    runs = {"analytic_fp32": ("analytic", "fp32", 1), "learned_fp32": ("learned", "fp32", 1),
+            "learned_fp16": ("learned", "fp16", 1), "learned_bf16": ("learned", "bf16", 1),
+            "analytic_fp16": ("analytic", "fp16", 1)}
+    if K > 1:
+        runs[f"learned_fp32_every{K}"] = ("learned", "fp32", K)
+        runs[f"learned_fp16_every{K}"] = ("learned", "fp16", K)
     les = {}
-    for name, (closure, dt) in runs.items():
+    for name, (closure, dt, every_k) in runs.items():
         g = setup.ghost
         s = Sim(nx=setup.n_les, ny=setup.n_les, nu=setup.nu_les, eta=setup.eta, delta=setup.delta_les,
                 s5=g, s6=g, s7=g, s8=g, dtype=dt, b_ref=(setup.B0, 0.0), closure=closure, device=dev, stream=stream)
         s.init_from_moments(c0[:5].contiguous())
         if closure == "learned":
             s.set_closure_mlp(mlp.pack())
+            s.set_correction_interval(every_k)
         les[name] = s
     every = max(T_END // 40, 1)
     n_cmp = setup.n_les // 4
@@ -522,6 +529,9 @@ def main() -> int:
                     help="steps of the supplementary 8192^2 FP32/FP16/BF16 timings (0 = skip)")
     ap.add_argument("--learned-steps", type=int, default=300,
                     help="steps of the supplementary 1024^2 learned-closure LES timing (0 = skip)")
+    ap.add_argument("--corr-every", type=int, default=16,
+                    help="learned-closure legs and study: also time/run with the network evaluated every "
+                         "this many steps and its correction held in between (1 = only every step)")
     ap.add_argument("--production-steps", type=int, default=5,
                     help="steps of the supplementary 16384^2 learned-closure timings, BF16 and FP16 (0 = skip)")
     ap.add_argument("--cpu-les-steps", type=int, default=15)
@@ -724,11 +734,15 @@ def main() -> int:
                      scale=[1e3, 20.0, 20.0, 100.0, 100.0, 1e3, 1e3], out_scale=[1e-6] * 4)
         packed = mlp.pack()
         n_l = LES_N * LES_N
-        for dt in ("fp32", "bf16"):
+        legs = [("fp32", 1), ("bf16", 1), ("fp16", 1)]
+        if args.corr_every > 1:
+            legs += [("fp32", args.corr_every), ("fp16", args.corr_every), ("bf16", args.corr_every)]
+        for dt, every in legs:
             sl = Sim(nx=LES_N, ny=LES_N, nu=NU, eta=ETA, delta=LES_DELTA, dtype=dt, schedule="fused",
                      b_ref=bref, closure="learned", device=dev, stream=stream, **ghost)
             sl.init_kh_jet(seed=0, **KH)
             sl.set_closure_mlp(packed)
+            sl.set_correction_interval(every)
             sl.step(20)
             a, b = ev(), ev()
             a.record(stream)
@@ -738,14 +752,18 @@ def main() -> int:
             ms = a.elapsed_time(b) / args.learned_steps
             # matrix-core work of the network per cell: 63*64 + 64*64 + 64*4 multiply-adds
             flops = 2 * (63 * 64 + 64 * 64 + 64 * 4) * n_l
-            extra[f"les1024_learned_{dt}"] = {
+            key = f"les1024_learned_{dt}" + (f"_every{every}" if every > 1 else "")
+            extra[key] = {
                 "mlups": round(n_l / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 2),
-                "network_tflops_per_step_time": round(flops / (ms * 1e-3) / 1e12, 1),
+                "network_tflops_per_step_time": round(flops / every / (ms * 1e-3) / 1e12, 1),
                 "fine_equivalent_mlups": round(64 * n_l / (ms * 1e-3) / 1e6, 1),
+                "correction_every": every,
                 "note": "fine-equivalent: a 4x coarser grid (16x fewer cells) and 4x longer steps "
                         "than the 4096^2 DNS it stands for",
-                "kernels": "k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<..., CORR>"}
-            log(f"learned les 1024^2 {dt}: {ms * 1e3:.1f} us/step")
+                "kernels": ("k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<..., CORR>" if every == 1
+                            else f"k_moments5f_row + k_mlp_correct every {every} steps, "
+                                 "k_fused_les<..., CORR> every step")}
+            log(f"learned les 1024^2 {dt} (network every {every}): {ms * 1e3:.1f} us/step")
             del sl
         del mlp, packed
 

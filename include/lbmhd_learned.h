@@ -162,6 +162,19 @@ int lbm_set_closure_mlp(lbm_ctx* ctx, const void* packed_dev);
  * out_dev (4*nx*ny floats). */
 int lbm_closure_correction(lbm_ctx* ctx, float* out_dev);
 
+/* Evaluation cadence of the learned correction (the correction is this
+ * library's addition to the closure of Sec. 2.1, so the cadence is its own
+ * definition).  With every = K >= 1 (default 1: every step), lbm_step
+ * evaluates the network on the state being collided at every step t with
+ * t % K == 0 and at the first step after lbm_init_*, lbm_set_state,
+ * lbm_set_closure_mlp or this call, and holds that correction (4 FP32 planes
+ * in the context's work buffer) for the steps in between, which then launch
+ * only the collision sweep.  A run restarted from a saved state at a t that
+ * is not a multiple of K evaluates once more than the uninterrupted run.
+ * Errors: LBM_ESTATE if the context was not created with the learned
+ * closure, LBM_EINVAL if every < 1. */
+int lbm_set_correction_interval(lbm_ctx* ctx, int32_t every);
+
 /* Radially binned energy spectra of an n x n periodic field, n a power of
  * two in [8, 16384]: with a_hat(k) = N^-2 sum_x a(x) exp(-2 pi i k.x / N) and
  * integer k_a in [-n/2, n/2),

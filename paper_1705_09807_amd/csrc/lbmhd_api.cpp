@@ -23,6 +23,8 @@ struct lbm_ctx {
   bool mlp_set = false;  // learned closure: a network has been installed
   bool cus_known = false;  // compute-unit count queried
   bool lag_ready = false;  // lagged schedule: moment set t & 1 holds step t - 1
+  int32_t corr_every = 1;  // learned closure: correction evaluated every corr_every steps
+  bool corr_ready = false;  // learned closure: the correction planes hold a held correction
 };
 
 namespace {
@@ -166,6 +168,7 @@ int lbm_init_kh_jet(lbm_ctx* ctx, const lbm_kh_params* kh) {
   ctx->t = 0;
   ctx->initialized = true;
   ctx->lag_ready = false;
+  ctx->corr_ready = false;
   return LBM_OK;
 }
 
@@ -183,6 +186,7 @@ int lbm_init_sech2_jet(lbm_ctx* ctx, const lbm_sech2_params* jet) {
   ctx->t = 0;
   ctx->initialized = true;
   ctx->lag_ready = false;
+  ctx->corr_ready = false;
   return LBM_OK;
 }
 
@@ -196,6 +200,7 @@ int lbm_init_from_moments(lbm_ctx* ctx, const double* mom_dev, int64_t t) {
   ctx->t = t;
   ctx->initialized = true;
   ctx->lag_ready = false;
+  ctx->corr_ready = false;
   return LBM_OK;
 }
 
@@ -219,8 +224,10 @@ int lbm_step(lbm_ctx* ctx, int64_t n) {
     ctx->lag_ready = true;
   }
   for (int64_t k = 0; k < n; ++k) {
-    hipError_t e = lbm::launch_step(ctx->L, ctx->t);
+    const bool refresh = !ctx->corr_ready || ctx->t % ctx->corr_every == 0;
+    hipError_t e = lbm::launch_step(ctx->L, ctx->t, refresh);
     if (e != hipSuccess) return hip_fail(e, "lbm_step");
+    ctx->corr_ready = ctx->L.learned;
     ++ctx->t;
   }
   return LBM_OK;
@@ -260,6 +267,7 @@ int lbm_set_state(lbm_ctx* ctx, const double* in_dev, int64_t t) {
   ctx->t = t;
   ctx->initialized = true;
   ctx->lag_ready = false;
+  ctx->corr_ready = false;
   return LBM_OK;
 }
 
@@ -298,6 +306,17 @@ int lbm_set_closure_mlp(lbm_ctx* ctx, const void* packed_dev) {
                                 hipMemcpyDeviceToDevice, ctx->L.stream);
   if (e != hipSuccess) return hip_fail(e, "lbm_set_closure_mlp");
   ctx->mlp_set = true;
+  ctx->corr_ready = false;
+  return LBM_OK;
+}
+
+int lbm_set_correction_interval(lbm_ctx* ctx, int32_t every) {
+  int rc = check_ctx(ctx, false);
+  if (rc != LBM_OK) return rc;
+  if (!ctx->L.learned) return fail(LBM_ESTATE, "context was not created with closure = LBM_CLOSURE_LEARNED");
+  if (every < 1) return fail(LBM_EINVAL, "every must be >= 1");
+  ctx->corr_every = every;
+  ctx->corr_ready = false;
   return LBM_OK;
 }
 

@@ -58,7 +58,10 @@ size_t work_layout(Launch& L);
 hipError_t launch_init_kh(const Launch& L, const lbm_kh_params& kh);
 hipError_t launch_init_sech2(const Launch& L, const lbm_sech2_params& jet);
 hipError_t launch_init_moments(const Launch& L, int64_t t, const double* mom);
-hipError_t launch_step(const Launch& L, int64_t t);  // state at time t -> t + 1
+// State at time t -> t + 1; with the learned closure, corr_refresh = false
+// reuses the correction planes of an earlier step instead of evaluating the
+// network on this state.
+hipError_t launch_step(const Launch& L, int64_t t, bool corr_refresh = true);
 // Lagged schedule: moments of the state at time t into moment set t & 1.
 hipError_t launch_lag_prime(const Launch& L, int64_t t);
 hipError_t launch_get_state(const Launch& L, int64_t t, double* out);

@@ -1315,7 +1315,7 @@ static void launch_aa_les(const Launch& L, S* A, const C* mb, const Rates<C>& r,
 }
 
 template <typename S>
-static hipError_t step_typed(const Launch& L, int64_t t) {
+static hipError_t step_typed(const Launch& L, int64_t t, bool corr_refresh) {
   using C = typename ComputeOf<S>::type;
   const Rates<C> r = make_rates<C>(L);
   const dim3 grid = aa_grid(L);
@@ -1326,8 +1326,10 @@ static hipError_t step_typed(const Launch& L, int64_t t) {
     const float* corr = nullptr;
     if (L.learned) {
       float* c = reinterpret_cast<float*>(static_cast<char*>(L.work) + L.off_corr);
-      const hipError_t e = launch_correction(L, t, c);
-      if (e != hipSuccess) return e;
+      if (corr_refresh) {
+        const hipError_t e = launch_correction(L, t, c);
+        if (e != hipSuccess) return e;
+      }
       corr = c;
     }
     return by_lattice<S>(L, [&](auto qg) {
@@ -1407,12 +1409,12 @@ hipError_t launch_lag_prime(const Launch& L, int64_t t) {
   }
 }
 
-hipError_t launch_step(const Launch& L, int64_t t) {
+hipError_t launch_step(const Launch& L, int64_t t, bool corr_refresh) {
   switch (L.dtype) {
-    case LBM_FP64: return step_typed<double>(L, t);
-    case LBM_FP32: return step_typed<float>(L, t);
-    case LBM_FP16: return step_typed<_Float16>(L, t);
-    default: return step_typed<__bf16>(L, t);
+    case LBM_FP64: return step_typed<double>(L, t, corr_refresh);
+    case LBM_FP32: return step_typed<float>(L, t, corr_refresh);
+    case LBM_FP16: return step_typed<_Float16>(L, t, corr_refresh);
+    default: return step_typed<__bf16>(L, t, corr_refresh);
   }
 }
 

@@ -137,6 +137,7 @@ _SIGNATURES = {
     "lbm_closure_samples": (ctypes.c_int, [_P, _I32, _I32, ctypes.c_double, _I32, _P, _P, _P]),
     "lbm_set_closure_mlp": (ctypes.c_int, [_P, _P]),
     "lbm_closure_correction": (ctypes.c_int, [_P, _P]),
+    "lbm_set_correction_interval": (ctypes.c_int, [_P, ctypes.c_int32]),
     "lbm_spectra_bins": (_I32, [_I32]),
     "lbm_spectra_work_bytes": (_SZ, [_I32]),
     "lbm_spectra": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _SZ, _P]),

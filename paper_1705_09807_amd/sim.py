@@ -139,6 +139,12 @@ class Sim:
         N.check(self._lib.lbm_set_closure_mlp(self._ctx, ctypes.c_void_p(packed.data_ptr())), "lbm_set_closure_mlp")
         self._stream_sync_keep = packed
 
+    def set_correction_interval(self, every: int):
+        """Learned closure: evaluate the network every `every` steps (at steps
+        t with t % every == 0 and at the first step after a new state or
+        network) and hold its correction in between."""
+        N.check(self._lib.lbm_set_correction_interval(self._ctx, int(every)), "lbm_set_correction_interval")
+
     def closure_correction(self, out=None):
         """[4, ny, nx] float32 device tensor: the network's tau_xx, tau_xy, tau_yy,
         eps corrections of the current state."""

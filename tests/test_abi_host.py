@@ -142,6 +142,10 @@ def test_learned_closure_params_and_call_order(lib):
     try:
         assert lib.lbm_set_closure_mlp(ctx, None) == N.LBM_EINVAL
         assert lib.lbm_closure_correction(ctx, ctypes.c_void_p(1 << 22)) == N.LBM_ESTATE  # no state yet
+        assert lib.lbm_set_correction_interval(ctx, 0) == N.LBM_EINVAL
+        assert lib.lbm_set_correction_interval(ctx, -3) == N.LBM_EINVAL
+        assert lib.lbm_set_correction_interval(ctx, 16) == N.LBM_OK
+        assert lib.lbm_set_correction_interval(None, 16) == N.LBM_EINVAL
     finally:
         lib.lbm_destroy(ctx)
     assert lib.lbm_create(ctypes.byref(ctx), ctypes.byref(p0), ctypes.c_void_p(1 << 20),
@@ -149,6 +153,7 @@ def test_learned_closure_params_and_call_order(lib):
     try:
         # an analytic-closure context takes no network
         assert lib.lbm_set_closure_mlp(ctx, ctypes.c_void_p(1 << 22)) == N.LBM_ESTATE
+        assert lib.lbm_set_correction_interval(ctx, 4) == N.LBM_ESTATE
     finally:
         lib.lbm_destroy(ctx)
 

@@ -436,6 +436,56 @@ def test_learned_step_matches_oracle_given_the_correction(dtype, tol, nx, ny):
         s.set_state(torch.from_numpy(st0), 0)
 
 
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_held_correction_matches_oracle(dtype, tol):
+    """Correction interval 3 over 7 steps from a state injected at t = 2: the
+    GPU evaluates the network at t = 2 (first step after the new state), 3 and
+    6 and holds the correction in between, as the oracle with
+    correction_every = 3 does when its hook returns the correction of the
+    state the GPU holds at each step (that correction itself is checked
+    against the oracle's network above)."""
+    G = _gpu()
+    nx, ny, K, t0, n = 64, 48, 3, 2, 7
+    f, g = _smooth_state(nx, ny, 81)
+    p = _params(82)
+    shift, scale, out_scale, _, _ = _state_norm(f, g)
+    s = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale, dtype=dtype)
+    s.set_correction_interval(K)
+    st0 = s.get_state().cpu().numpy()
+    s.set_state(torch.from_numpy(st0), t0)
+    corrs = {}
+    for t in range(t0, t0 + n):
+        corrs[t] = s.closure_correction().cpu().numpy().astype(np.float64)
+        s.step(1)
+    got = s.get_state().cpu().numpy()
+    kw = dict(delta=2.0, s5=1.3, s6=1.5, s7=1.7, s8=1.1)
+    runs = {}
+    for every in (K, 1):
+        called = []
+        o = O.Oracle(nx, ny, 0.02, 0.03, correction_every=every, **kw)
+        o.closure_correction = lambda *a, o=o, called=called: (called.append(o.t), corrs[o.t])[1]
+        o.set_state(st0[:9], np.stack([st0[9:14], st0[14:19]], axis=1), t=t0)
+        o.step(n)
+        fo, go = o.state()[:2]
+        runs[every] = (np.concatenate([fo, go[:, 0], go[:, 1]], 0), called)
+    want, called = runs[K]
+    assert called == [2, 3, 6]
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    # holding the correction mattered at this tolerance
+    effect = np.linalg.norm(runs[1][0] - want) / np.linalg.norm(want)
+    print(f"{dtype}: relative L2 {err:.2e} (holding's effect {effect:.2e})", flush=True)
+    assert err <= tol
+    if dtype == "fp64":
+        assert effect > 1e3 * tol
+    # interval 1 is the every-step default, bit for bit
+    a = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale, dtype=dtype)
+    b = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale, dtype=dtype)
+    b.set_correction_interval(1)
+    a.step(3)
+    b.step(3)
+    assert torch.equal(a.get_state(), b.get_state())
+
+
 # ---------------------------------------------------------------------------
 # what the trained network gains (a priori, held-out seed)
 # ---------------------------------------------------------------------------
