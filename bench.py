@@ -533,7 +533,8 @@ def main() -> int:
                     help="learned-closure legs and study: also time/run with the network evaluated every "
                          "this many steps and its correction held in between (1 = only every step)")
     ap.add_argument("--production-steps", type=int, default=5,
-                    help="steps of the supplementary 16384^2 learned-closure timings, BF16 and FP16 (0 = skip)")
+                    help="steps of the supplementary 16384^2 learned-closure timings, BF16 and FP16; with "
+                         "the network every --corr-every steps rounded up to whole intervals (0 = skip)")
     ap.add_argument("--cpu-les-steps", type=int, default=15)
     ap.add_argument("--cpu-dns-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -744,12 +745,14 @@ def main() -> int:
             sl.set_closure_mlp(packed)
             sl.set_correction_interval(every)
             sl.step(20)
+            # a whole number of intervals: each holds exactly one network evaluation
+            nsteps = every * -(-args.learned_steps // every)
             a, b = ev(), ev()
             a.record(stream)
-            sl.step(args.learned_steps)
+            sl.step(nsteps)
             b.record(stream)
             torch.cuda.synchronize(dev)
-            ms = a.elapsed_time(b) / args.learned_steps
+            ms = a.elapsed_time(b) / nsteps
             # matrix-core work of the network per cell: 63*64 + 64*64 + 64*4 multiply-adds
             flops = 2 * (63 * 64 + 64 * 64 + 64 * 4) * n_l
             key = f"les1024_learned_{dt}" + (f"_every{every}" if every > 1 else "")
@@ -757,7 +760,7 @@ def main() -> int:
                 "mlups": round(n_l / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 2),
                 "network_tflops_per_step_time": round(flops / every / (ms * 1e-3) / 1e12, 1),
                 "fine_equivalent_mlups": round(64 * n_l / (ms * 1e-3) / 1e6, 1),
-                "correction_every": every,
+                "correction_every": every, "steps": nsteps,
                 "note": "fine-equivalent: a 4x coarser grid (16x fewer cells) and 4x longer steps "
                         "than the 4096^2 DNS it stands for",
                 "kernels": ("k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<..., CORR>" if every == 1
@@ -807,21 +810,31 @@ def main() -> int:
         mlp.set_norm(shift=[1.0, 0.0, 0.0, b16, 0.0, 0.0, 0.0],
                      scale=[1e3, 20.0, 20.0, 100.0, 100.0, 1e3, 1e3], out_scale=[1e-6] * 4)
         packed = mlp.pack()
-        for dt in ("bf16", "fp16"):
+        legs = [("bf16", 1), ("fp16", 1)]
+        if args.corr_every > 1:
+            legs += [("bf16", args.corr_every), ("fp16", args.corr_every)]
+        for dt, every in legs:
             sp = Sim(nx=n16, ny=n16, nu=5e-5, eta=5e-5, delta=LES_DELTA, dtype=dt, schedule="fused",
                      b_ref=(b16, 0.0), closure="learned", device=dev, stream=stream, **ghost)
             sp.init_kh_jet(seed=0, **kh16)
             sp.set_closure_mlp(packed)
+            sp.set_correction_interval(every)
             sp.step(2)
+            # a whole number of intervals: each holds exactly one network evaluation
+            nsteps = every * -(-args.production_steps // every)
             a, b = ev(), ev()
             a.record(stream)
-            sp.step(args.production_steps)
+            sp.step(nsteps)
             b.record(stream)
             torch.cuda.synchronize(dev)
-            ms = a.elapsed_time(b) / args.production_steps
+            ms = a.elapsed_time(b) / nsteps
             rec = {"mlups": round(lups16 / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 1),
-                   "kernels": f"k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<{dt}, ..., CORR>"}
-            if dt == "bf16":
+                   "steps": nsteps, "correction_every": every,
+                   "kernels": (f"k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<{dt}, ..., CORR>"
+                               if every == 1 else
+                               f"k_moments5f_row + k_mlp_correct every {every} steps, "
+                               f"k_fused_les<{dt}, ..., CORR> every step")}
+            if dt == "bf16" and every == 1:
                 mom16 = torch.empty((5, n16, n16), dtype=torch.float64, device=dev)
                 sp.moments(mom16)
                 G.spectra(mom16, stream=stream)  # first call: the allocator takes the work buffer
@@ -844,8 +857,8 @@ def main() -> int:
                 del mom16, ek, em
             else:
                 rec["nonfinite"] = int(sp.diagnostics()["nonfinite"])
-            extra[f"les16384_learned_{dt}"] = rec
-            log(f"production 16384^2 learned {dt}: {ms * 1e3:.0f} us/step")
+            extra[f"les16384_learned_{dt}" + (f"_every{every}" if every > 1 else "")] = rec
+            log(f"production 16384^2 learned {dt} (network every {every}): {ms * 1e3:.0f} us/step")
             del sp
             torch.cuda.empty_cache()
         del mlp, packed
