@@ -72,7 +72,7 @@ typedef struct {
 
 /* Device bytes of a packed network (bfloat16 weights in matrix-core operand
  * order, FP32 biases, the normalisation). */
-#define LBM_MLP_PACKED_BYTES 21504
+#define LBM_MLP_PACKED_BYTES 31744
 
 /* Pack FP32 parameters and a normalisation into `packed_dev`
  * (LBM_MLP_PACKED_BYTES): weights rounded to bfloat16, nearest even. */

@@ -55,7 +55,13 @@ constexpr int kPkB1 = 20480;   // 64 floats
 constexpr int kPkB2 = 20736;   // 64 floats
 constexpr int kPkB3 = 20992;   // 4 floats (+ pad)
 constexpr int kPkNorm = 21248;  // lbm_mlp_norm
-static_assert(kPkNorm + (int)sizeof(lbm_mlp_norm) <= LBM_MLP_PACKED_BYTES, "packed size");
+// Layer 1 of the state-correction kernel, whose inputs are ordered by patch
+// position: contraction index k' = pos * 8 + field (pos = 3 row + column of
+// the 3x3 patch, field 0..6, field 7 and pos 9 zero), i.e. network input
+// field * 9 + pos.  [ot 2][kb 5][lane 64][8] bf16.
+constexpr int kPkA1c = 21504;
+static_assert(kPkNorm + (int)sizeof(lbm_mlp_norm) <= kPkA1c, "packed layout");
+static_assert(kPkA1c + 2 * 5 * 64 * 16 <= LBM_MLP_PACKED_BYTES, "packed size");
 static_assert(sizeof(lbm_mlp_norm) == 128, "norm size");
 
 constexpr float kOodLimit = 6.0f;
@@ -74,9 +80,13 @@ __device__ __forceinline__ int feat_field(int k) { return (k * 57) >> 9; }
 
 __device__ __forceinline__ float bf16_round(float v) { return float(__bf16(v)); }
 
-struct MlpA {
-  bf16x8 a1[2][4], a2[2][4], a3[4];
+// A operands of the three layers; KB1 16-wide contraction blocks in layer 1.
+template <int KB1>
+struct MlpW {
+  bf16x8 a1[2][KB1], a2[2][4], a3[4];
 };
+using MlpA = MlpW<4>;
+using MlpC = MlpW<5>;
 
 __device__ __forceinline__ void load_mlp(const char* __restrict__ pk, int lane, MlpA& w) {
   const bf16x8* p1 = reinterpret_cast<const bf16x8*>(pk + kPkA1);
@@ -89,6 +99,22 @@ __device__ __forceinline__ void load_mlp(const char* __restrict__ pk, int lane, 
       w.a1[ot][kb] = p1[(ot * 4 + kb) * 64 + lane];
       w.a2[ot][kb] = p2[(ot * 4 + kb) * 64 + lane];
     }
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) w.a3[kb] = p3[kb * 64 + lane];
+}
+
+// The same with the patch-ordered layer 1 of the state-correction kernel.
+__device__ __forceinline__ void load_mlp_c(const char* __restrict__ pk, int lane, MlpC& w) {
+  const bf16x8* p1 = reinterpret_cast<const bf16x8*>(pk + kPkA1c);
+  const bf16x8* p2 = reinterpret_cast<const bf16x8*>(pk + kPkA2);
+  const bf16x8* p3 = reinterpret_cast<const bf16x8*>(pk + kPkA3);
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot) {
+#pragma unroll
+    for (int kb = 0; kb < 5; ++kb) w.a1[ot][kb] = p1[(ot * 5 + kb) * 64 + lane];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) w.a2[ot][kb] = p2[(ot * 4 + kb) * 64 + lane];
+  }
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) w.a3[kb] = p3[kb * 64 + lane];
 }
@@ -131,14 +157,15 @@ __device__ __forceinline__ void activate(const f32x16 acc[2], bf16x8 hb[4], floa
 }
 
 // The network on the 32 cells of a wave: zb = layer-1 B operands of this lane
-// (cell lane % 32, inputs kb*16 + (lane/32)*8 + j).  Returns y in lanes 0..31
-// (components 0..3).  h1, h2 (32 floats each, may be null) receive the
-// bfloat16 activations held by this lane, element kb*8 + j = hidden
-// chained_k(kb, lane/32, j).
+// (cell lane % 32, inputs kb*16 + (lane/32)*8 + j in layer 1's contraction
+// order).  Returns y in lanes 0..31 (components 0..3).  h1, h2 (32 floats
+// each, may be null) receive the bfloat16 activations held by this lane,
+// element kb*8 + j = hidden chained_k(kb, lane/32, j).
 // Biases: b points at b1 (64 floats), b2 (64) and b3 (4) back to back, in
 // LDS or global memory.
-__device__ __forceinline__ f32x4 mlp_wave(const MlpA& w, const bf16x8 zb[4], const float* __restrict__ b, int lane,
-                                          float* h1, float* h2) {
+template <int KB1>
+__device__ __forceinline__ f32x4 mlp_wave(const MlpW<KB1>& w, const bf16x8 zb[KB1], const float* __restrict__ b,
+                                          int lane, float* h1, float* h2) {
   const int h = lane >> 5;
   const float* b1 = b;
   const float* b2 = b + 64;
@@ -149,7 +176,8 @@ __device__ __forceinline__ f32x4 mlp_wave(const MlpA& w, const bf16x8 zb[4], con
   for (int ot = 0; ot < 2; ++ot) {
     acc[ot] = bias_tile(b1, ot, h);
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) acc[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a1[ot][kb], zb[kb], acc[ot], 0, 0, 0);
+    for (int kb = 0; kb < KB1; ++kb)
+      acc[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a1[ot][kb], zb[kb], acc[ot], 0, 0, 0);
   }
   activate(acc, hb, h1);
 #pragma unroll
@@ -205,6 +233,12 @@ k_mlp_pack(const float* __restrict__ p, const lbm_mlp_norm* __restrict__ norm, c
   } else if (e < 10240 + 64 + 32) {
     const int i = e - 10240 - 64;
     reinterpret_cast<float*>(pk + kPkNorm)[i] = reinterpret_cast<const float*>(norm)[i];
+  } else if (e < 10240 + 64 + 32 + 5120) {  // A1c: W1^T rows, patch-ordered inputs
+    const int f = e - (10240 + 64 + 32);
+    const int ot = f / 2560, kb = (f / 512) % 5, l = (f / 8) % 64, j = f % 8;
+    const int hid = ot * 32 + l % 32, pos = kb * 2 + l / 32;
+    __bf16* c = reinterpret_cast<__bf16*>(pk + kPkA1c);
+    c[f] = __bf16(pos < 9 && j < 7 ? p[LBM_MLP_OFF_W1 + (j * 9 + pos) * 64 + hid] : 0.0f);
   }
 }
 
@@ -272,8 +306,12 @@ k_mlp_forward(const char* __restrict__ pk, const float* __restrict__ x, int64_t 
 // B_x, B_y.  A workgroup stages a 64 x 16 tile with a two-cell halo in LDS
 // (all loads of a thread issued before any is used), forms u = m / rho, the
 // central-difference vorticity and current on the one-cell halo, normalises
-// the seven fields and flags cells with any |z| > 6 (or NaN), then evaluates the
-// network for its 1024 cells (each wave 8 groups of 32).  A cell is out of
+// the seven fields and flags cells with any |z| > 6 (or NaN), storing each
+// cell's seven normalised values (and a zero) as eight bfloat16 = 16 bytes,
+// then evaluates the network for its 1024 cells (each wave 8 groups of 32).
+// Layer 1 contracts over the patch positions in 16-input blocks (two
+// positions of eight values each; 5 blocks, the last half empty), so a
+// lane's B operand of a block is one 16-byte LDS read.  A cell is out of
 // distribution when a flagged cell lies in its 3x3 neighbourhood (its 63
 // inputs are exactly the seven fields there).  Output: four FP32 planes
 // tau_xx, tau_xy, tau_yy, eps = out_scale * y, 0 for out-of-distribution cells
@@ -282,10 +320,11 @@ k_mlp_forward(const char* __restrict__ pk, const float* __restrict__ x, int64_t 
 constexpr int kCorrTX = 64, kCorrTY = 16;
 constexpr int kCorrLX = kCorrTX + 4, kCorrLY = kCorrTY + 4, kCorrPL = kCorrLX * kCorrLY;
 
-// LDS offset of feature k (< 63) from the patch corner of cell (ty, tx):
-// plane k / 9, row (k % 9) / 3, column (k % 9) % 3, corner at (ty + 1, tx + 1).
-__host__ __device__ constexpr int corr_feature_offset(int k) {
-  return (k / 9) * kCorrPL + ((k % 9) / 3) * kCorrLX + (k % 9) % 3 + kCorrLX + 1;
+// LDS cell offset of patch position pos (< 9: row pos / 3, column pos % 3)
+// of tile cell (ty, tx) from ty * LX + tx: the patch corner is at
+// (ty + 1, tx + 1) in the tile with its two-cell halo.
+__host__ __device__ constexpr int corr_patch_offset(int pos) {
+  return (pos / 3) * kCorrLX + pos % 3 + kCorrLX + 1;
 }
 
 // Periodic wrap of v in [-2, n + kCorrLX) into [0, n).
@@ -302,6 +341,7 @@ __global__ void __launch_bounds__(256, 2)
 k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float* __restrict__ corr, int nx, int ny) {
   constexpr int LX = kCorrLX, PL = kCorrPL;
   __shared__ float fld[7 * PL];
+  __shared__ bf16x8 zc[PL];  // normalised fields 0..6 of a cell, 0
   __shared__ unsigned char bad[PL];
   __shared__ unsigned char patch_bad[kCorrTX * kCorrTY];
   __shared__ __attribute__((aligned(16))) float bias[132];
@@ -358,12 +398,15 @@ k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float*
     if (e < RN) {
       const int ly = e / RX + 1, p = ly * LX + (e - (ly - 1) * RX) + 1;
       bool b = false;
+      f32x8 zf;
 #pragma unroll
       for (int f = 0; f < 7; ++f) {
         const float z = (fld[f * PL + p] - nm->shift[f]) * nm->scale[f];
-        fld[f * PL + p] = z;
+        zf[f] = z;
         b = b || !(fabsf(z) <= kOodLimit);  // NaN counts as out of range
       }
+      zf[7] = 0.0f;
+      zc[p] = to_bf16x8(zf);
       bad[p] = b ? 1 : 0;
     }
   }
@@ -379,25 +422,18 @@ k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float*
   __syncthreads();
   // 4. the network, 32 cells per wave at a time (operands and biases held in
   // registers for the whole loop; output scales in scalar registers)
-  MlpA w;
-  load_mlp(pk, lane, w);
+  MlpC w;
+  load_mlp_c(pk, lane, w);
   const float os0 = nm->out_scale[0], os1 = nm->out_scale[1], os2 = nm->out_scale[2], os3 = nm->out_scale[3];
   for (int g = wid; g < kCorrTX * kCorrTY / 32; g += 4) {
     const int ty = g >> 1, tx = (g & 1) * 32 + (lane & 31), base = ty * LX + tx;
-    bf16x8 zb[4];
+    // block kb: patch position 2 kb (lanes 0..31) or 2 kb + 1 (lanes 32..63)
+    bf16x8 zb[5];
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      f32x8 zf;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k0 = kb * 16 + j, k1 = kb * 16 + 8 + j;  // this lane's input: k0 (h = 0) or k1 (h = 1)
-        if (k1 == 63)
-          zf[j] = h ? 0.0f : fld[base + corr_feature_offset(k0)];
-        else
-          zf[j] = fld[base + (h ? corr_feature_offset(k1) : corr_feature_offset(k0))];
-      }
-      zb[kb] = to_bf16x8(zf);
-    }
+    for (int kb = 0; kb < 4; ++kb)
+      zb[kb] = zc[base + (h ? corr_patch_offset(2 * kb + 1) : corr_patch_offset(2 * kb))];
+    const bf16x8 z8 = zc[base + corr_patch_offset(8)];
+    zb[4] = h ? bf16x8{} : z8;
     const bool pb = patch_bad[ty * kCorrTX + tx] != 0;
     const f32x4 v = mlp_wave(w, zb, bias, lane, nullptr, nullptr);
     const bool o = pb || !(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]));
@@ -1043,7 +1079,7 @@ size_t mlp_train_work_bytes(int batch) {
 }
 
 hipError_t launch_mlp_pack(const float* params, const lbm_mlp_norm* norm, void* packed, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_pack, dim3((10240 + 64 + 32 + 255) / 256), dim3(256), 0, st, params, norm,
+  hipLaunchKernelGGL(k_mlp_pack, dim3((10240 + 64 + 32 + 5120 + 255) / 256), dim3(256), 0, st, params, norm,
                      static_cast<char*>(packed));
   return hipGetLastError();
 }

@@ -50,7 +50,7 @@ LBM_MLP_OFF_B2 = 8256
 LBM_MLP_OFF_W3 = 8320
 LBM_MLP_OFF_B3 = 8576
 LBM_MLP_PARAMS = 8580
-LBM_MLP_PACKED_BYTES = 21504
+LBM_MLP_PACKED_BYTES = 31744
 
 
 class LbmParams(ctypes.Structure):
