@@ -641,7 +641,7 @@ def main() -> int:
     traffic = measured_traffic("fused_dns_fp32", dns_lups)
     roofline = {
         "bound": "hbm",
-        "kernel": "k_fused_dns<float> (4096^2 sweep)",
+        "kernel": "k_fused_dns_pair<float, float, true, 5> (4096^2 DNS sweep)",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
