@@ -159,7 +159,8 @@ int lbm_set_closure_mlp(lbm_ctx* ctx, const void* packed_dev);
 
 /* The correction of the current state: 4 FP32 planes tau_xx, tau_xy,
  * tau_yy, eps (out_scale applied, 0 in out-of-distribution cells) into
- * out_dev (4*nx*ny floats). */
+ * out_dev (4*nx*ny floats).  The correction that lbm_step holds between
+ * evaluations (lbm_set_correction_interval) is left as it is. */
 int lbm_closure_correction(lbm_ctx* ctx, float* out_dev);
 
 /* Evaluation cadence of the learned correction (the correction is this
