@@ -565,6 +565,8 @@ def main() -> int:
                     help="after timing, run a plain device-to-device copy of this many bytes "
                          "(reference kernel for the HBM byte counters)")
     args = ap.parse_args()
+    if args.corr_every < 1:
+        ap.error("--corr-every must be >= 1")
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -38,3 +38,12 @@ def test_traffic_summaries_parse(tmp_path, monkeypatch):
     assert bench.measured_traffic("k", 100) == 16000.0
     assert bench.measured_traffic("k", 101) is None
     assert bench.measured_traffic("old", 100) is None
+
+
+def test_correction_interval_must_be_positive():
+    """--corr-every below 1 is an argument error (exit 2) before touching a GPU."""
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--corr-every", "0"], capture_output=True,
+                         text=True, timeout=120, cwd=ROOT)
+    assert res.returncode == 2
+    assert "--corr-every" in res.stderr
+    assert res.stdout == ""
