@@ -762,6 +762,8 @@ def main() -> int:
                 "mlups": round(n_l / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 2),
                 "network_tflops_per_step_time": round(flops / every / (ms * 1e-3) / 1e12, 1),
                 "fine_equivalent_mlups": round(64 * n_l / (ms * 1e-3) / 1e6, 1),
+                # the analytic-closure FP32 LES of the same grid (the headline run's les1024)
+                "speed_vs_plain_fp32_les": round(les_ms / ms, 3),
                 "correction_every": every, "steps": nsteps,
                 "note": "fine-equivalent: a 4x coarser grid (16x fewer cells) and 4x longer steps "
                         "than the 4096^2 DNS it stands for",
