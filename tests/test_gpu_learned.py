@@ -486,6 +486,42 @@ def test_held_correction_matches_oracle(dtype, tol):
     assert torch.equal(a.get_state(), b.get_state())
 
 
+@pytest.mark.parametrize("every", [1, 3])
+@pytest.mark.parametrize("nx,ny", [(64, 48), (67, 33)])
+def test_learned_run_matches_oracle_network(nx, ny, every):
+    """Five FP64 learned steps (network every step, or every 3 steps with the
+    correction held) against the oracle running its own network from the
+    same host input: no value computed on the GPU enters the oracle.  The
+    two networks agree to FP32 accumulation noise except for rare rows where
+    a value within ~1e-7 of a bfloat16 rounding boundary rounds the other
+    way, so the bound is set by the correction's own effect: the GPU run
+    reproduces it to 1 % (a wrong sign, input permutation, output scale or
+    cadence misses by O(1) of it)."""
+    G = _gpu()
+    f, g = _smooth_state(nx, ny, 91)
+    p = _params(92)
+    shift, scale, out_scale, s64, c64 = _state_norm(f, g)
+    s = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale, dtype="fp64")
+    s.set_correction_interval(every)
+    s.step(5)
+    got = s.get_state().cpu().numpy()
+    kw = dict(delta=2.0, s5=1.3, s6=1.5, s7=1.7, s8=1.1)
+    hook = L.learned_correction(p, s64, c64, out_scale.astype(np.float64))
+    runs = []
+    for corr in (hook, None):
+        o = O.Oracle(nx, ny, 0.02, 0.03, closure_correction=corr, correction_every=every, **kw)
+        o.set_state(f, g)
+        o.step(5)
+        fo, go = o.state()[:2]
+        runs.append(np.concatenate([fo, go[:, 0], go[:, 1]], 0))
+    want, plain = runs
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    effect = np.linalg.norm(plain - want) / np.linalg.norm(want)
+    print(f"{nx}x{ny} every {every}: relative L2 {err:.2e} (correction's effect {effect:.2e})", flush=True)
+    assert effect > 1e-6
+    assert err <= 1e-2 * effect
+
+
 # ---------------------------------------------------------------------------
 # what the trained network gains (a priori, held-out seed)
 # ---------------------------------------------------------------------------
