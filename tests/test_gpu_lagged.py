@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 from oracle import lbmhd_oracle as O
-from seeded_inputs import perturbed, offset_noise
+from sampled_windows import check_rough_sampled
+from seeded_inputs import ROUGH_MEAN, assemble_rough_torch, offset_noise, perturbed, rough_factors
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -115,30 +116,27 @@ VARIANTS = [
 @pytest.mark.parametrize("variant", VARIANTS, ids=[v[0] for v in VARIANTS])
 def test_full_size_variants_sampled(variant):
     """4096^2 FP32 LES (Delta = 4) of the lagged and local-gradient variants in
-    the benchmark's launch configuration: 3 steps from the jet, 24 sampled
-    cells against the oracle in the same mode on the 15 x 15 window around
-    each."""
+    the benchmark's launch configuration: 3 steps from rough fields, 24
+    sampled cells against the oracle in the same mode on the 15 x 15 window
+    around each; the same windows without the closure, and with the
+    synchronous stencil closure, sit far outside the tolerance."""
     label, schedule, stencil, ctime = variant
-    n, nu, B0, steps, delta = 4096, 2e-4, 0.01, 3, 4.0
-    kh = dict(U0=0.05, delta_over_L=1 / 40, B0=B0, rho0=1.0, pert_amp_over_U0=1e-3, noise_amp=1e-5)
+    n, nu, steps, delta = 4096, 2e-4, 3, 4.0
     g4 = dict(s5=1.6, s6=1.6, s7=1.6, s8=1.6)
     s = _sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype="fp32", schedule=schedule, grad_stencil=stencil,
-             b_ref=(B0, 0.0), **g4)
-    s.init_kh_jet(seed=19, **kh)
+             b_ref=(ROUGH_MEAN[3], ROUGH_MEAN[4]), **g4)
+    factors = rough_factors(n, n, 19)
+    s.init_from_moments(assemble_rough_torch(factors, torch, s.device))
+    s._keep = None
     s.step(steps)
     rng = np.random.default_rng(31)
-    pts = [(0, 0), (n - 1, n - 1), (255, 256), (256, 255)] + [tuple(v) for v in rng.integers(0, n, size=(20, 2))]
+    pts = [(0, 0), (n - 1, n - 1), (255, 256), (256, 255), (511, 127), (512, 128)] + \
+        [tuple(int(v) for v in q) for q in rng.integers(0, n, size=(18, 2))]
     xs = torch.tensor([q[0] for q in pts], device=s.device)
     ys = torch.tensor([q[1] for q in pts], device=s.device)
     got = s.get_state()[:, ys, xs].cpu().numpy()
-    win = 2 * (2 * steps + 1) + 1
-    half = win // 2
-    for k, (x, y) in enumerate(pts):
-        X, Y = np.meshgrid((x - half + np.arange(win)) % n, (y - half + np.arange(win)) % n)
-        f, g = O.kh_jet_populations(X, Y, n, n, seed=19, **kh)
-        o = O.Oracle(win, win, nu, nu, delta=delta, grad_stencil=stencil, closure_time=ctime, **g4)
-        o.set_state(f, g)
-        o.step(steps)
-        ref = pack(*o.state()[:2])[:, half, half]
-        err = np.abs(got[:, k] - ref).max()
-        assert err <= 2e-6, (label, x, y, err)
+    gaps = [("no closure", dict(delta=0.0, grad_stencil="iso9", closure_time="sync"), 100.0),
+            ("synchronous stencil closure", dict(grad_stencil="iso9", closure_time="sync"), 30.0)]
+    check_rough_sampled(got, pts, n, steps, factors, 1e-7, gaps=gaps, say=print,
+                        nu=nu, eta=nu, delta=delta, grad_stencil=stencil, closure_time=ctime, **g4)
+    s.close()
