@@ -110,8 +110,7 @@ typedef struct lbm_ctx lbm_ctx;
 /* Run parameters, lattice units.  Rates follow Sec. 2: s3 = s4 = 2/(6 nu + 1)
  * (from nu = 1/(3 s) - 1/6), s_m = 2/(6 eta + 1); s0..s2 = 0 (conserved). */
 typedef struct {
-  int32_t nx, ny;          /* periodic grid, each >= 4 and <= 32768, with one
-                              plane (nx*ny values of the storage type) <= 4 GiB */
+  int32_t nx, ny;          /* periodic grid, each >= 4 and <= 32768          */
   double nu, eta;          /* > 0, giving rates in (0, 2)                     */
   double s5, s6, s7, s8;   /* MRT ghost rates in (0, 2); <= 0 means "= s3",
                               i.e. the single-relaxation-time runs of Sec. 3 */
@@ -167,7 +166,11 @@ typedef struct {
 
 /* Bytes of the caller-owned device buffers for these parameters (0 if the
  * parameters are invalid).  The state holds the populations in the storage
- * precision, one buffer (AA) or two (fused); the work buffer holds moment
+ * precision, one buffer (AA) or two (fused), each ny lattice rows of P
+ * population rows (P = 19, or 27 with D2Q9 g) padded to a multiple of 64
+ * elements, rounded up to 256 elements: the populations of a lattice row
+ * are stored together (an internal layout: state IO uses the natural layout
+ * above).  The work buffer holds moment
  * planes and reduction partials (and, with the learned closure, the network
  * and its input and output planes). */
 size_t lbm_state_bytes(const lbm_params* p);

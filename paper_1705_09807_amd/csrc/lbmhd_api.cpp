@@ -49,8 +49,6 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     return fail(LBM_EINVAL, "dtype must be LBM_FP64, LBM_FP32, LBM_FP16 or LBM_BF16");
   if (p->nx < 4 || p->ny < 4 || p->nx > 32768 || p->ny > 32768)
     return fail(LBM_EINVAL, "nx and ny must lie in [4, 32768]");
-  if ((int64_t)p->nx * (int64_t)p->ny * (int64_t)lbm::storage_bytes(p->dtype) > ((int64_t)1 << 32))
-    return fail(LBM_EINVAL, "one population plane (nx*ny values) must not exceed 4 GiB");
   if (!finite_pos(p->nu) || !finite_pos(p->eta)) return fail(LBM_EINVAL, "nu and eta must be finite and > 0");
   const double ghost[4] = {p->s5, p->s6, p->s7, p->s8};
   for (double g : ghost) {
@@ -87,7 +85,7 @@ int check_params(const lbm_params* p, lbm::Launch* L) {
     const double s = 2.0 / (6.0 * p->nu + 1.0);
     L->nx = p->nx;
     L->ny = p->ny;
-    L->plane = lbm::plane_elems(p->nx, p->ny);
+    L->pitch = lbm::row_pitch(p->nx);
     L->dtype = p->dtype;
     L->schedule = p->schedule;
     L->stencil = p->grad_stencil;

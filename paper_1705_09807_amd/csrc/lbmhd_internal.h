@@ -19,7 +19,8 @@ constexpr int kDiagBlocksMax = 2048;
 // Everything a launcher needs; filled once by lbm_create.
 struct Launch {
   int nx = 0, ny = 0;
-  int64_t plane = 0;              // elements per population plane (>= nx*ny, padded)
+  int64_t pitch = 0;              // elements from one population row to the next within a
+                                  // lattice row (>= nx; a lattice row holds 9 + 2 qg of them)
   int dtype = LBM_FP64;
   int schedule = LBM_SCHED_FUSED;
   int stencil = LBM_STENCIL_ISO9;
@@ -49,7 +50,10 @@ struct Launch {
 
 // Layout helpers (host).
 size_t storage_bytes(int dtype);
-int64_t plane_elems(int nx, int ny);
+int64_t row_pitch(int nx);
+// Elements of one population buffer: ny lattice rows of (9 + 2 qg) population
+// rows each, element (q, x, y) at (y * (9 + 2 qg) + q) * pitch + x.
+int64_t buffer_elems(int nx, int ny, int qg);
 size_t state_bytes(int nx, int ny, int dtype, int schedule, int qg);
 // Work layout for the given geometry; returns total bytes and fills offsets.
 size_t work_layout(Launch& L);

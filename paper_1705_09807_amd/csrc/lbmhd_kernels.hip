@@ -7,8 +7,9 @@
 // Delta-expansion FilterExampleSmall; Sec. 3: SRT runs, density gradients
 // dropped (simplified M3).
 //
-// Storage: 19 structure-of-arrays planes (f_0..f_8, g_x0..g_x4, g_y0..g_y4),
-// x fastest, plane stride padded.  FP32 stores f as the deviation
+// Storage: structure of arrays by lattice row.  Lattice row y holds the 19
+// population rows f_0..f_8, g_x0..g_x4, g_y0..g_y4 (x fastest) one after
+// another, each padded to a multiple of 64 elements.  FP32 stores f as the deviation
 // f_i - w_i rho0 from the rest equilibrium, so that the small dynamic part
 // keeps its digits; FP64 stores f itself (rho0 = 0 below); g is stored as is.
 //
@@ -281,18 +282,22 @@ __device__ __forceinline__ void local_gradients(const C v[kQ], const Mom<C>& m, 
 // Two consecutive stored values (one aligned load or store).
 template <typename S> using Vec2 = S __attribute__((ext_vector_type(2)));
 
-// Addressing: a plane base is wave-uniform (scalar registers) and every
-// access adds a 32-bit byte offset (row offset + column offset), which maps
-// onto the scalar-base + vector-offset form of global loads and stores and
-// keeps 64-bit address arithmetic out of the vector ALU.  A plane is at most
-// 4 GB (checked at creation).
+// Addressing.  A buffer is ny lattice rows, each holding the NPOP population
+// rows of that lattice row one after another, `pitch` elements apart:
+// element (q, x, y) at (y * NPOP + q) * pitch + x.  Keeping the populations
+// of a lattice row together means the workgroups that run at the same time
+// read and write a few contiguous stretches of memory instead of one stretch
+// per population plane.  An access is a wave-uniform row base (the lattice
+// row's offset, 64-bit, plus q * pitch, in scalar registers) plus a 32-bit
+// byte offset of the column, the scalar-base + vector-offset form of global
+// loads and stores.
 template <typename S>
-__device__ __forceinline__ const S* at(const S* __restrict__ base, uint32_t byte_off) {
-  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off);
+__device__ __forceinline__ const S* at(const S* __restrict__ base, int64_t row_off, uint32_t col_off) {
+  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + row_off + col_off);
 }
 template <typename S>
-__device__ __forceinline__ S* at(S* __restrict__ base, uint32_t byte_off) {
-  return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off);
+__device__ __forceinline__ S* at(S* __restrict__ base, int64_t row_off, uint32_t col_off) {
+  return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + row_off + col_off);
 }
 
 // Streaming store: non-temporal when the working set exceeds the caches.
@@ -304,18 +309,18 @@ __device__ __forceinline__ void store(T* p, T v) {
     *p = v;
 }
 
-// Byte offsets of the rows y - 1, y, y + 1 (periodic) and the columns
-// x - 1, x, x + 1 of a cell.
+// Byte offsets of the lattice rows y - 1, y, y + 1 (periodic) and of the
+// columns x - 1, x, x + 1 of a cell.
 struct Rows {
-  uint32_t s, c, n;
+  int64_t s, c, n;
 };
-template <typename S>
-__device__ __forceinline__ Rows rows_of(int y, int nx, int ny) {
-  const uint32_t rb = uint32_t(nx) * uint32_t(sizeof(S));
+template <typename S, int QG = 5>
+__device__ __forceinline__ Rows rows_of(int y, int ny, int64_t pitch) {
+  const int64_t rb = int64_t(kPop<QG>) * pitch * int64_t(sizeof(S));
   Rows r;
-  r.c = uint32_t(y) * rb;
-  r.s = uint32_t(y == 0 ? ny - 1 : y - 1) * rb;
-  r.n = uint32_t(y + 1 == ny ? 0 : y + 1) * rb;
+  r.c = int64_t(y) * rb;
+  r.s = int64_t(y == 0 ? ny - 1 : y - 1) * rb;
+  r.n = int64_t(y + 1 == ny ? 0 : y + 1) * rb;
   return r;
 }
 struct Cols {
@@ -332,20 +337,20 @@ __device__ __forceinline__ Cols cols_of(int x, int nx) {
 
 // f_q(x, y) = src[q][x - c_q][y - c_q] for one cell.
 template <typename S, typename C, int QG = 5>
-__device__ __forceinline__ void pull_cell(const S* __restrict__ src, int64_t plane, const Rows& rw, const Cols& cl,
+__device__ __forceinline__ void pull_cell(const S* __restrict__ src, int64_t pitch, const Rows& rw, const Cols& cl,
                                           C* v) {
 #pragma unroll
   for (int q = 0; q < kPop<QG>; ++q) {
     const uint32_t xo = qcx<QG>(q) > 0 ? cl.w : (qcx<QG>(q) < 0 ? cl.e : cl.c);
-    const uint32_t yo = qcy<QG>(q) > 0 ? rw.s : (qcy<QG>(q) < 0 ? rw.n : rw.c);
-    v[q] = decode<C>(*at(src + q * plane, yo + xo));
+    const int64_t yo = qcy<QG>(q) > 0 ? rw.s : (qcy<QG>(q) < 0 ? rw.n : rw.c);
+    v[q] = decode<C>(*at(src + q * pitch, yo, xo));
   }
 }
 
 // Two horizontally adjacent cells x, x + 1 (x even, nx even): the c_x = 0
 // populations come in one aligned two-element load.
 template <typename S, typename C, int QG = 5>
-__device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t plane, int nx, const Rows& rw, int x,
+__device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t pitch, int nx, const Rows& rw, int x,
                                           C* a, C* b) {
   using V2 = Vec2<S>;
   const uint32_t es = uint32_t(sizeof(S));
@@ -353,18 +358,18 @@ __device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t pla
   const uint32_t x2 = uint32_t(x + 2 == nx ? 0 : x + 2) * es;
 #pragma unroll
   for (int q = 0; q < kPop<QG>; ++q) {
-    const uint32_t yo = qcy<QG>(q) > 0 ? rw.s : (qcy<QG>(q) < 0 ? rw.n : rw.c);
-    const S* pq = src + q * plane;
+    const int64_t yo = qcy<QG>(q) > 0 ? rw.s : (qcy<QG>(q) < 0 ? rw.n : rw.c);
+    const S* pq = src + q * pitch;
     if (qcx<QG>(q) == 0) {
-      const V2 t = *reinterpret_cast<const V2*>(at(pq, yo + x0));
+      const V2 t = *reinterpret_cast<const V2*>(at(pq, yo, x0));
       a[q] = decode<C>(t.x);
       b[q] = decode<C>(t.y);
     } else if (qcx<QG>(q) > 0) {
-      a[q] = decode<C>(*at(pq, yo + xw));
-      b[q] = decode<C>(*at(pq, yo + x0));
+      a[q] = decode<C>(*at(pq, yo, xw));
+      b[q] = decode<C>(*at(pq, yo, x0));
     } else {
-      a[q] = decode<C>(*at(pq, yo + x1));
-      b[q] = decode<C>(*at(pq, yo + x2));
+      a[q] = decode<C>(*at(pq, yo, x1));
+      b[q] = decode<C>(*at(pq, yo, x2));
     }
   }
 }
@@ -373,14 +378,14 @@ __device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t pla
 // two cells per thread, aligned two-element stores.  Requires nx even.
 template <typename S, typename C, bool NT, int QG>
 __global__ void __launch_bounds__(128)
-k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
+k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t pitch, Rates<C> r) {
   using nv2 = Vec2<S>;
   const int x = (blockIdx.x * 128 + threadIdx.x) * 2;
   const int y = blockIdx.y;
   if (x >= nx) return;
-  const Rows rw = rows_of<S>(y, nx, ny);
+  const Rows rw = rows_of<S, QG>(y, ny, pitch);
   C a[kPop<QG>], b[kPop<QG>];
-  pull_pair<S, C, QG>(src, plane, nx, rw, x, a, b);
+  pull_pair<S, C, QG>(src, pitch, nx, rw, x, a, b);
   const Closure<C> cl = {C(0), C(0), C(0), C(0)};
   {
     const Mom<C> m = moments_of<QG>(a);
@@ -390,23 +395,23 @@ k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
     const Mom<C> m = moments_of<QG>(b);
     collide_q<QG>(b, m, cl, r);
   }
-  const uint32_t off = rw.c + uint32_t(x) * uint32_t(sizeof(S));
+  const uint32_t xo = uint32_t(x) * uint32_t(sizeof(S));
 #pragma unroll
   for (int q = 0; q < kPop<QG>; ++q) {
     nv2 t;
     t.x = encode<S>(a[q]);
     t.y = encode<S>(b[q]);
-    store<NT>(reinterpret_cast<nv2*>(at(dst + q * plane, off)), t);
+    store<NT>(reinterpret_cast<nv2*>(at(dst + q * pitch, rw.c, xo)), t);
   }
 }
 
 template <typename S> using Vec4 = S __attribute__((ext_vector_type(4)));
 
 // Four horizontally adjacent cells x .. x + 3 (x a multiple of 4, nx too):
-// every plane in one aligned four-element load, plus one load of the
-// neighbour column for the planes that stream along x.
+// every population in one aligned four-element load, plus one load of the
+// neighbour column for the populations that stream along x.
 template <typename S, typename C>
-__device__ __forceinline__ void pull_quad(const S* __restrict__ src, int64_t plane, int nx, const Rows& rw, int x,
+__device__ __forceinline__ void pull_quad(const S* __restrict__ src, int64_t pitch, int nx, const Rows& rw, int x,
                                           C (&v)[4][kQ]) {
   using V4 = Vec4<S>;
   const uint32_t es = uint32_t(sizeof(S));
@@ -415,16 +420,16 @@ __device__ __forceinline__ void pull_quad(const S* __restrict__ src, int64_t pla
   const uint32_t x4 = uint32_t(x + 4 == nx ? 0 : x + 4) * es;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const uint32_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
-    const S* pq = src + q * plane;
-    const V4 t = *reinterpret_cast<const V4*>(at(pq, yo + x0));
+    const int64_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
+    const S* pq = src + q * pitch;
+    const V4 t = *reinterpret_cast<const V4*>(at(pq, yo, x0));
     if (qcx(q) == 0) {
       v[0][q] = decode<C>(t.x);
       v[1][q] = decode<C>(t.y);
       v[2][q] = decode<C>(t.z);
       v[3][q] = decode<C>(t.w);
     } else if (qcx(q) > 0) {  // the cells pull from x - 1
-      v[0][q] = decode<C>(*at(pq, yo + xw));
+      v[0][q] = decode<C>(*at(pq, yo, xw));
       v[1][q] = decode<C>(t.x);
       v[2][q] = decode<C>(t.y);
       v[3][q] = decode<C>(t.z);
@@ -432,34 +437,33 @@ __device__ __forceinline__ void pull_quad(const S* __restrict__ src, int64_t pla
       v[0][q] = decode<C>(t.y);
       v[1][q] = decode<C>(t.z);
       v[2][q] = decode<C>(t.w);
-      v[3][q] = decode<C>(*at(pq, yo + x4));
+      v[3][q] = decode<C>(*at(pq, yo, x4));
     }
   }
 }
 
 // Closure off, 16-bit storage, nx a multiple of 4: four cells per thread, so
-// every plane moves in one aligned 8-byte load and store per thread (plus one
-// 2-byte load of the neighbour column for the planes that stream along x).
+// every population moves in one aligned 8-byte load and store per thread (plus
+// one 2-byte load of the neighbour column for those that stream along x).
 // Measured 7-9 % faster than the pair kernel at 8192^2 with FP16 and BF16
 // storage (slower with FP32, whose pair loads are already 8 bytes).
 template <typename S, typename C, bool NT>
 __global__ void __launch_bounds__(64)
-k_fused_dns_quad(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
+k_fused_dns_quad(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t pitch, Rates<C> r) {
   using V4 = Vec4<S>;
   const int x = (blockIdx.x * 64 + threadIdx.x) * 4;
   const int y = blockIdx.y;
   if (x >= nx) return;
-  const Rows rw = rows_of<S>(y, nx, ny);
+  const Rows rw = rows_of<S>(y, ny, pitch);
   const uint32_t x0 = uint32_t(x) * uint32_t(sizeof(S));
   C v[4][kQ];
-  pull_quad<S, C>(src, plane, nx, rw, x, v);
+  pull_quad<S, C>(src, pitch, nx, rw, x, v);
   const Closure<C> cl = {C(0), C(0), C(0), C(0)};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const Mom<C> m = moments19(v[k]);
     collide19(v[k], m, cl, r);
   }
-  const uint32_t off = rw.c + x0;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     V4 t;
@@ -467,26 +471,26 @@ k_fused_dns_quad(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
     t.y = encode<S>(v[1][q]);
     t.z = encode<S>(v[2][q]);
     t.w = encode<S>(v[3][q]);
-    store<NT>(reinterpret_cast<V4*>(at(dst + q * plane, off)), t);
+    store<NT>(reinterpret_cast<V4*>(at(dst + q * pitch, rw.c, x0)), t);
   }
 }
 
 // Closure off, any nx: one cell per thread, row segments of 256 cells.
 template <typename S, typename C, bool NT, int QG>
 __global__ void __launch_bounds__(256)
-k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, Rates<C> r) {
+k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t pitch, Rates<C> r) {
   const int x = blockIdx.x * 256 + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= nx) return;
-  const Rows rw = rows_of<S>(y, nx, ny);
+  const Rows rw = rows_of<S, QG>(y, ny, pitch);
   const Cols cl = cols_of<S>(x, nx);
   C v[kPop<QG>];
-  pull_cell<S, C, QG>(src, plane, rw, cl, v);
+  pull_cell<S, C, QG>(src, pitch, rw, cl, v);
   const Mom<C> m = moments_of<QG>(v);
   const Closure<C> zero = {C(0), C(0), C(0), C(0)};
   collide_q<QG>(v, m, zero, r);
 #pragma unroll
-  for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * plane, rw.c + cl.c), encode<S>(v[q]));
+  for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * pitch, rw.c, cl.c), encode<S>(v[q]));
 }
 
 // Closure on.  A workgroup of W + 64 lanes owns the column strip
@@ -508,7 +512,7 @@ enum { kClosurePlain = 0, kClosureCorr = 1, kClosureFull = 2 };
 
 template <typename S, typename C, int W, int STENCIL, bool NT, int MODE, int QG>
 __global__ void __launch_bounds__(W + 64)
-k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t plane, int ry, Rates<C> r,
+k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t pitch, int ry, Rates<C> r,
             const float* __restrict__ corr) {
   constexpr int NF = MODE == kClosureFull ? 5 : 4;
   __shared__ C ring[4][NF][W + 2];
@@ -541,11 +545,11 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
 
   C cur[kPop<QG>], nxt[kPop<QG>], nn[kPop<QG>];
   if (loader) {
-    pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y0 - 1), nx, ny), cx, nn);
+    pull_cell<S, C, QG>(src, pitch, rows_of<S, QG>(wrapy(y0 - 1), ny, pitch), cx, nn);
     if (writer) put(0, nn);
-    pull_cell<S, C, QG>(src, plane, rows_of<S>(y0, nx, ny), cx, cur);
+    pull_cell<S, C, QG>(src, pitch, rows_of<S, QG>(y0, ny, pitch), cx, cur);
     if (writer) put(1, cur);
-    pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y0 + 1), nx, ny), cx, nxt);
+    pull_cell<S, C, QG>(src, pitch, rows_of<S, QG>(wrapy(y0 + 1), ny, pitch), cx, nxt);
     if (writer) put(2, nxt);
   }
   __syncthreads();
@@ -560,7 +564,7 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
     auto row = [&](C (&cu)[kPop<QG>], C (&fr)[kPop<QG>], int y) __attribute__((always_inline)) {
       const int s = y - y0 + 1;                 // ring slot of row y is s & 3
       const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
-      if (more && loader) pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y + 2), nx, ny), cx, fr);
+      if (more && loader) pull_cell<S, C, QG>(src, pitch, rows_of<S, QG>(wrapy(y + 2), ny, pitch), cx, fr);
       if (valid) {
         const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
         C gr[NF][2];
@@ -590,9 +594,9 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
           cl.eps += eps;
         }
         collide_q<QG>(cu, m, cl, r);
-        const uint32_t off = uint32_t(y) * uint32_t(nx) * uint32_t(sizeof(S)) + cx.c;
+        const int64_t yo = int64_t(y) * int64_t(kPop<QG>) * pitch * int64_t(sizeof(S));
 #pragma unroll
-        for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * plane, off), encode<S>(cu[q]));
+        for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * pitch, yo, cx.c), encode<S>(cu[q]));
       }
       if (more && writer) put((s + 2) & 3, fr);
       __syncthreads();
@@ -610,7 +614,7 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
     for (int y = y0; y < y1; ++y) {
       const int s = y - y0 + 1;                 // ring slot of row y is s & 3
       const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
-      if (more && loader) pull_cell<S, C, QG>(src, plane, rows_of<S>(wrapy(y + 2), nx, ny), cx, nn);
+      if (more && loader) pull_cell<S, C, QG>(src, pitch, rows_of<S, QG>(wrapy(y + 2), ny, pitch), cx, nn);
       if (valid) {
         const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
         C gr[NF][2];
@@ -640,9 +644,9 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
           cl.eps += eps;
         }
         collide_q<QG>(cur, m, cl, r);
-        const uint32_t off = uint32_t(y) * uint32_t(nx) * uint32_t(sizeof(S)) + cx.c;
+        const int64_t yo = int64_t(y) * int64_t(kPop<QG>) * pitch * int64_t(sizeof(S));
 #pragma unroll
-        for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * plane, off), encode<S>(cur[q]));
+        for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * pitch, yo, cx.c), encode<S>(cur[q]));
       }
       if (more && writer) put((s + 2) & 3, nn);
       __syncthreads();
@@ -662,67 +666,67 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
 // Every kernel of the schedule runs one row segment of kAARow cells per
 // workgroup (1-D row blocks keep each wave's accesses within DRAM rows;
 // measured 1.1-1.25x faster than 64 x 4 tiles at 4096^2) and addresses a
-// plane by its wave-uniform base plus a 32-bit byte offset.
+// population row by its wave-uniform base plus a 32-bit byte offset.
 // ---------------------------------------------------------------------------
 constexpr int kAARow = 256;
 
 template <typename S, typename C, bool ODD>
-__device__ __forceinline__ void aa_load(const S* __restrict__ A, int64_t plane, const Rows& rw, const Cols& cl,
+__device__ __forceinline__ void aa_load(const S* __restrict__ A, int64_t pitch, const Rows& rw, const Cols& cl,
                                         C v[kQ]) {
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     if (!ODD) {
-      v[q] = decode<C>(*at(A + q * plane, rw.c + cl.c));
+      v[q] = decode<C>(*at(A + q * pitch, rw.c, cl.c));
     } else {
       const uint32_t xo = qcx(q) > 0 ? cl.w : (qcx(q) < 0 ? cl.e : cl.c);  // x - c_q
-      const uint32_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
-      v[q] = decode<C>(*at(A + qopp(q) * plane, yo + xo));
+      const int64_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
+      v[q] = decode<C>(*at(A + qopp(q) * pitch, yo, xo));
     }
   }
 }
 
 template <typename S, typename C, bool ODD>
-__device__ __forceinline__ void aa_store(S* __restrict__ A, int64_t plane, const Rows& rw, const Cols& cl,
+__device__ __forceinline__ void aa_store(S* __restrict__ A, int64_t pitch, const Rows& rw, const Cols& cl,
                                          const C v[kQ]) {
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     if (!ODD) {
-      *at(A + qopp(q) * plane, rw.c + cl.c) = encode<S>(v[q]);
+      *at(A + qopp(q) * pitch, rw.c, cl.c) = encode<S>(v[q]);
     } else {
       const uint32_t xo = qcx(q) > 0 ? cl.e : (qcx(q) < 0 ? cl.w : cl.c);  // x + c_q
-      const uint32_t yo = qcy(q) > 0 ? rw.n : (qcy(q) < 0 ? rw.s : rw.c);
-      *at(A + q * plane, yo + xo) = encode<S>(v[q]);
+      const int64_t yo = qcy(q) > 0 ? rw.n : (qcy(q) < 0 ? rw.s : rw.c);
+      *at(A + q * pitch, yo, xo) = encode<S>(v[q]);
     }
   }
 }
 
 template <typename S, typename C, bool ODD>
-__global__ void __launch_bounds__(kAARow) k_aa_dns(S* __restrict__ A, int nx, int ny, int64_t plane, Rates<C> r) {
+__global__ void __launch_bounds__(kAARow) k_aa_dns(S* __restrict__ A, int nx, int ny, int64_t pitch, Rates<C> r) {
   const int x = blockIdx.x * kAARow + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= nx) return;
-  const Rows rw = rows_of<S>(y, nx, ny);
+  const Rows rw = rows_of<S>(y, ny, pitch);
   const Cols cl = cols_of<S>(x, nx);
   C v[kQ];
-  aa_load<S, C, ODD>(A, plane, rw, cl, v);
+  aa_load<S, C, ODD>(A, pitch, rw, cl, v);
   const Mom<C> m = moments19(v);
   const Closure<C> zero = {C(0), C(0), C(0), C(0)};
   collide19(v, m, zero, r);
-  aa_store<S, C, ODD>(A, plane, rw, cl, v);
+  aa_store<S, C, ODD>(A, pitch, rw, cl, v);
 }
 
 // Moment sweep of the in-place closure schedule: m_x, m_y, B_x, B_y of the
 // state at time t into four dense planes of the compute type.
 template <typename S, typename C, bool ODD>
 __global__ void __launch_bounds__(kAARow)
-k_aa_moments(const S* __restrict__ A, C* __restrict__ mb, int nx, int ny, int64_t plane) {
+k_aa_moments(const S* __restrict__ A, C* __restrict__ mb, int nx, int ny, int64_t pitch) {
   const int x = blockIdx.x * kAARow + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= nx) return;
-  const Rows rw = rows_of<S>(y, nx, ny);
+  const Rows rw = rows_of<S>(y, ny, pitch);
   const Cols cl = cols_of<S>(x, nx);
   C v[kQ];
-  aa_load<S, C, ODD>(A, plane, rw, cl, v);
+  aa_load<S, C, ODD>(A, pitch, rw, cl, v);
   const Mom<C> m = moments19(v);
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
   mb[c0] = m.mx;
@@ -763,17 +767,17 @@ __device__ __forceinline__ void tile_gradients(const C (&tile)[4][3][kAARow + 2]
 // the moment planes written by k_aa_moments).
 template <typename S, typename C, bool ODD, int STENCIL>
 __global__ void __launch_bounds__(kAARow)
-k_aa_les(S* __restrict__ A, const C* __restrict__ mb, int nx, int ny, int64_t plane, Rates<C> r) {
+k_aa_les(S* __restrict__ A, const C* __restrict__ mb, int nx, int ny, int64_t pitch, Rates<C> r) {
   __shared__ C tile[4][3][kAARow + 2];
   const int x0 = blockIdx.x * kAARow, y = blockIdx.y;
   stage_tile(tile, mb, nx, ny, x0, y);
   __syncthreads();
   const int x = x0 + threadIdx.x;
   if (x >= nx) return;
-  const Rows rw = rows_of<S>(y, nx, ny);
+  const Rows rw = rows_of<S>(y, ny, pitch);
   const Cols cl = cols_of<S>(x, nx);
   C v[kQ];
-  aa_load<S, C, ODD>(A, plane, rw, cl, v);
+  aa_load<S, C, ODD>(A, pitch, rw, cl, v);
   const Mom<C> m = moments19(v);
   C gr[4][2];
   tile_gradients<C, STENCIL>(tile, threadIdx.x + 1, gr);
@@ -782,7 +786,7 @@ k_aa_les(S* __restrict__ A, const C* __restrict__ mb, int nx, int ny, int64_t pl
   const Closure<C> cls = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
                                        gr[3][1], ir, r.k2);
   collide19(v, m, cls, r);
-  aa_store<S, C, ODD>(A, plane, rw, cl, v);
+  aa_store<S, C, ODD>(A, pitch, rw, cl, v);
 }
 
 // Single-sweep in-place closure schedule (lagged gradients): the halo tile
@@ -792,17 +796,17 @@ k_aa_les(S* __restrict__ A, const C* __restrict__ mb, int nx, int ny, int64_t pl
 template <typename S, typename C, bool ODD, int STENCIL>
 __global__ void __launch_bounds__(kAARow)
 k_aa_les_lagged(S* __restrict__ A, const C* __restrict__ mb_prev, C* __restrict__ mb_next, int nx, int ny,
-                int64_t plane, Rates<C> r) {
+                int64_t pitch, Rates<C> r) {
   __shared__ C tile[4][3][kAARow + 2];
   const int x0 = blockIdx.x * kAARow, y = blockIdx.y;
   stage_tile(tile, mb_prev, nx, ny, x0, y);
   __syncthreads();
   const int x = x0 + threadIdx.x;
   if (x >= nx) return;
-  const Rows rw = rows_of<S>(y, nx, ny);
+  const Rows rw = rows_of<S>(y, ny, pitch);
   const Cols cl = cols_of<S>(x, nx);
   C v[kQ];
-  aa_load<S, C, ODD>(A, plane, rw, cl, v);
+  aa_load<S, C, ODD>(A, pitch, rw, cl, v);
   const Mom<C> m = moments19(v);
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
   mb_next[c0] = m.mx;
@@ -815,7 +819,7 @@ k_aa_les_lagged(S* __restrict__ A, const C* __restrict__ mb_prev, C* __restrict_
   const Closure<C> cls = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0],
                                        gr[3][1], ir, r.k2);
   collide19(v, m, cls, r);
-  aa_store<S, C, ODD>(A, plane, rw, cl, v);
+  aa_store<S, C, ODD>(A, pitch, rw, cl, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -831,10 +835,10 @@ constexpr int kLayoutAAOdd = 1;
 constexpr int kLayoutPull = 2;
 
 template <int QG = 5>
-__device__ __forceinline__ int64_t natural_index(int q, int x, int y, int nx, int ny, int64_t plane, int layout) {
-  if (layout == kLayoutNatural) return q * plane + (int64_t)y * nx + x;
+__device__ __forceinline__ int64_t natural_index(int q, int x, int y, int nx, int ny, int64_t pitch, int layout) {
+  if (layout == kLayoutNatural) return ((int64_t)y * kPop<QG> + q) * pitch + x;
   const int xs = wrap1(x - qcx<QG>(q), nx), ys = wrap1(y - qcy<QG>(q), ny);
-  return (layout == kLayoutAAOdd ? qopp<QG>(q) : q) * plane + (int64_t)ys * nx + xs;
+  return ((int64_t)ys * kPop<QG> + (layout == kLayoutAAOdd ? qopp<QG>(q) : q)) * pitch + xs;
 }
 
 // Rest values subtracted from the stored populations: w_q rho0 for f,
@@ -860,7 +864,7 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t counte
 // Unfiltered equilibria feq / geq (Sec. 2) of one cell's fields, evaluated in
 // FP64 and rounded to the storage type.
 template <typename S, int QG = 5>
-__device__ __forceinline__ void write_equilibrium(S* __restrict__ base, int x, int y, int nx, int ny, int64_t plane,
+__device__ __forceinline__ void write_equilibrium(S* __restrict__ base, int x, int y, int nx, int ny, int64_t pitch,
                                                   int layout, const RestRef& ref, double rho, double ux, double uy,
                                                   double bx, double by) {
   const double usq = ux * ux + uy * uy, bsq = bx * bx + by * by;
@@ -870,7 +874,7 @@ __device__ __forceinline__ void write_equilibrium(S* __restrict__ base, int x, i
     const double cb = cx9(i) * bx + cy9(i) * by;
     const double c2 = double(cx9(i) * cx9(i) + cy9(i) * cy9(i));
     const double feq = w9(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) + 4.5 * w9(i) * (0.5 * bsq * c2 - cb * cb);
-    base[natural_index<QG>(i, x, y, nx, ny, plane, layout)] = encode<S>(feq - rest_value<QG>(i, ref));
+    base[natural_index<QG>(i, x, y, nx, ny, pitch, layout)] = encode<S>(feq - rest_value<QG>(i, ref));
   }
 #pragma unroll
   for (int i = 0; i < QG; ++i) {
@@ -878,8 +882,8 @@ __device__ __forceinline__ void write_equilibrium(S* __restrict__ base, int x, i
     const double cb = cx9(i) * bx + cy9(i) * by;
     const double gx = wg<QG>(i) * (bx + 3.0 * (cu * bx - cb * ux));
     const double gy = wg<QG>(i) * (by + 3.0 * (cu * by - cb * uy));
-    base[natural_index<QG>(9 + i, x, y, nx, ny, plane, layout)] = encode<S>(gx - rest_value<QG>(9 + i, ref));
-    base[natural_index<QG>(9 + QG + i, x, y, nx, ny, plane, layout)] =
+    base[natural_index<QG>(9 + i, x, y, nx, ny, pitch, layout)] = encode<S>(gx - rest_value<QG>(9 + i, ref));
+    base[natural_index<QG>(9 + QG + i, x, y, nx, ny, pitch, layout)] =
         encode<S>(gy - rest_value<QG>(9 + QG + i, ref));
   }
 }
@@ -887,7 +891,7 @@ __device__ __forceinline__ void write_equilibrium(S* __restrict__ base, int x, i
 // Kelvin-Helmholtz double shear layer at the unfiltered equilibria.
 template <typename S, int QG>
 __global__ void __launch_bounds__(256)
-k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestRef ref, lbm_kh_params kh) {
+k_init_kh(S* __restrict__ base, int nx, int ny, int64_t pitch, int layout, RestRef ref, lbm_kh_params kh) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= nx || y >= ny) return;
@@ -897,13 +901,13 @@ k_init_kh(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestR
   const uint64_t z = splitmix64_at(kh.seed, (uint64_t)y * (uint64_t)nx + (uint64_t)x);
   const double xi = 2.0 * (double(z >> 11) * 0x1.0p-53) - 1.0;
   const double uy = kh.pert_amp_over_U0 * kh.U0 * sin(2.0 * M_PI * xx / double(nx)) + kh.noise_amp * xi;
-  write_equilibrium<S, QG>(base, x, y, nx, ny, plane, layout, ref, kh.rho0, ux, uy, kh.B0, 0.0);
+  write_equilibrium<S, QG>(base, x, y, nx, ny, pitch, layout, ref, kh.rho0, ux, uy, kh.B0, 0.0);
 }
 
 // The magnetized jet of Sec. 4 at the unfiltered equilibria.
 template <typename S, int QG>
 __global__ void __launch_bounds__(256)
-k_init_sech2(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, RestRef ref, lbm_sech2_params jet) {
+k_init_sech2(S* __restrict__ base, int nx, int ny, int64_t pitch, int layout, RestRef ref, lbm_sech2_params jet) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= nx || y >= ny) return;
@@ -914,26 +918,26 @@ k_init_sech2(S* __restrict__ base, int nx, int ny, int64_t plane, int layout, Re
   const double ux = jet.pert * jet.U0 * sin(ky * yf);
   const double bx = jet.pert * jet.B0 * sin(ky * yf);
   const double by = jet.B0 + jet.pert * jet.B0 * sin(kx * xf);
-  write_equilibrium<S, QG>(base, x, y, nx, ny, plane, layout, ref, jet.rho0, ux, uy, bx, by);
+  write_equilibrium<S, QG>(base, x, y, nx, ny, pitch, layout, ref, jet.rho0, ux, uy, bx, by);
 }
 
 // Equilibria of given fields: 5 FP64 planes rho, m_x, m_y, B_x, B_y.
 template <typename S, int QG>
 __global__ void __launch_bounds__(256)
-k_init_moments(S* __restrict__ base, const double* __restrict__ mom, int nx, int ny, int64_t plane, int layout,
+k_init_moments(S* __restrict__ base, const double* __restrict__ mom, int nx, int ny, int64_t pitch, int layout,
                RestRef ref) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   if (x >= nx || y >= ny) return;
   const int64_t n = (int64_t)nx * ny, c = (int64_t)y * nx + x;
   const double rho = mom[c];
-  write_equilibrium<S, QG>(base, x, y, nx, ny, plane, layout, ref, rho, mom[n + c] / rho, mom[2 * n + c] / rho,
+  write_equilibrium<S, QG>(base, x, y, nx, ny, pitch, layout, ref, rho, mom[n + c] / rho, mom[2 * n + c] / rho,
                        mom[3 * n + c], mom[4 * n + c]);
 }
 
 template <typename S, int QG>
 __global__ void __launch_bounds__(256)
-k_get_state(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, int layout,
+k_get_state(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t pitch, int layout,
             RestRef ref) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
@@ -941,14 +945,14 @@ k_get_state(const S* __restrict__ base, double* __restrict__ out, int nx, int ny
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
 #pragma unroll
   for (int q = 0; q < kPop<QG>; ++q) {
-    const double v = decode<double>(base[natural_index<QG>(q, x, y, nx, ny, plane, layout)]);
+    const double v = decode<double>(base[natural_index<QG>(q, x, y, nx, ny, pitch, layout)]);
     out[q * n + c0] = v + rest_value<QG>(q, ref);
   }
 }
 
 template <typename S, int QG>
 __global__ void __launch_bounds__(256)
-k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny, int64_t plane, int layout,
+k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny, int64_t pitch, int layout,
             RestRef ref) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
@@ -957,7 +961,7 @@ k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny,
 #pragma unroll
   for (int q = 0; q < kPop<QG>; ++q) {
     const double v = in[q * n + c0];
-    base[natural_index<QG>(q, x, y, nx, ny, plane, layout)] = encode<S>(v - rest_value<QG>(q, ref));
+    base[natural_index<QG>(q, x, y, nx, ny, pitch, layout)] = encode<S>(v - rest_value<QG>(q, ref));
   }
 }
 
@@ -967,7 +971,7 @@ k_set_state(S* __restrict__ base, const double* __restrict__ in, int nx, int ny,
 // gathers).
 template <typename S, int QG>
 __global__ void __launch_bounds__(256)
-k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t plane, int layout,
+k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int ny, int64_t pitch, int layout,
               RestRef ref, bool mark_nonfinite) {
   const int x = blockIdx.x * 256 + threadIdx.x;
   const int y = blockIdx.y;
@@ -976,7 +980,7 @@ k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int 
   bool finite = true;
 #pragma unroll
   for (int q = 0; q < kPop<QG>; ++q) {
-    v[q] = decode<double>(base[natural_index<QG>(q, x, y, nx, ny, plane, layout)]);
+    v[q] = decode<double>(base[natural_index<QG>(q, x, y, nx, ny, pitch, layout)]);
     finite = finite && isfinite(v[q]);
   }
   const Mom<double> m = moments_of<QG>(v);
@@ -996,13 +1000,13 @@ k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int 
 // 8-byte loads was 6-8 % slower than one).
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_moments5f_row(const S* __restrict__ src, float* __restrict__ out, int nx, int ny, int64_t plane, RestRef ref) {
+k_moments5f_row(const S* __restrict__ src, float* __restrict__ out, int nx, int ny, int64_t pitch, RestRef ref) {
   using C = typename ComputeOf<S>::type;
   const int x = blockIdx.x * 256 + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= nx) return;
   C v[kQ];
-  pull_cell<S, C, 5>(src, plane, rows_of<S>(y, nx, ny), cols_of<S>(x, nx), v);
+  pull_cell<S, C, 5>(src, pitch, rows_of<S>(y, ny, pitch), cols_of<S>(x, nx), v);
   const Mom<C> m = moments19(v);
   const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
   out[c0] = float(C(ref.rho0) + m.drho);
@@ -1105,16 +1109,22 @@ size_t storage_bytes(int dtype) {
   return dtype == LBM_FP64 ? 8 : (dtype == LBM_FP32 ? 4 : 2);
 }
 
-int64_t plane_elems(int nx, int ny) {
-  // Round each plane up to 1024 elements and add an odd multiple of 256 so
-  // that the 19 planes start at staggered offsets rather than at the same
-  // position of every large power-of-two stride.
-  const int64_t n = (int64_t)nx * ny;
-  return ((n + 1023) / 1024) * 1024 + 256;
+int64_t row_pitch(int nx) {
+  // Population rows padded to a multiple of 64 elements (whole cache lines);
+  // no padding at the power-of-two sizes of the benchmarks, where measured
+  // paddings of 64 and 256 elements were slower.
+  return ((int64_t)nx + 63) / 64 * 64;
+}
+
+int64_t buffer_elems(int nx, int ny, int qg) {
+  // ny lattice rows of 9 + 2 qg population rows; rounded to 256 elements so
+  // that the second buffer of the fused schedule starts aligned.
+  const int64_t e = (int64_t)ny * (9 + 2 * qg) * row_pitch(nx);
+  return (e + 255) / 256 * 256;
 }
 
 size_t state_bytes(int nx, int ny, int dtype, int schedule, int qg) {
-  const size_t one = (size_t)(9 + 2 * qg) * (size_t)plane_elems(nx, ny) * storage_bytes(dtype);
+  const size_t one = (size_t)buffer_elems(nx, ny, qg) * storage_bytes(dtype);
   return schedule == LBM_SCHED_FUSED ? 2 * one : one;
 }
 
@@ -1166,7 +1176,7 @@ static dim3 aa_grid(const Launch& L) { return dim3((L.nx + kAARow - 1) / kAARow,
 template <typename S>
 static S* buffer_at(const Launch& L, int64_t t) {
   S* base = static_cast<S*>(L.state);
-  if (L.schedule == LBM_SCHED_FUSED && (t & 1)) base += (size_t)(9 + 2 * L.qg) * (size_t)L.plane;
+  if (L.schedule == LBM_SCHED_FUSED && (t & 1)) base += (size_t)buffer_elems(L.nx, L.ny, L.qg);
   return base;
 }
 
@@ -1186,12 +1196,12 @@ static C* moment_set(const Launch& L, int k) {
 }
 
 // Rows per workgroup of the fused closure kernel.  Measured on MI355X over
-// 1024^2 .. 8192^2 (FP32 and FP64 strips): one workgroup per compute unit is
+// 1024^2 .. 16384^2 (512-lane FP32 strips): one workgroup per compute unit is
 // fastest (every strip segment runs concurrently from start to end, and the
 // two halo rows re-read per segment are amortised over many rows) as long as
 // a segment then holds at most 128 rows (FP32) or 64 rows (FP64); larger
-// grids run more, 64-row segments (8192^2 FP32: 1952 us at 64 rows, 2041 us
-// at 128, 2180 us at 512 = one per compute unit).
+// grids run more, 64-row segments (4096^2: 440 us at 128 rows = one per
+// compute unit, 444 us at 64; 8192^2: 1764 us at 64 rows, 1781 us at 512).
 static int fused_rows(int nx, int ny, int strip, int cus, int cap) {
   const int64_t strips = (nx + strip - 1) / strip;
   const int64_t blocks = cus / strips > 1 ? cus / strips : 1;  // segments per strip column
@@ -1215,21 +1225,21 @@ static void launch_les_k(const Launch& L, const S* src, S* dst, const Rates<C>& 
   if constexpr (MODE != kClosureFull && QG == 5) {
     if (L.stencil == LBM_STENCIL_LOCAL_ISO9) {
       hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_ISO9, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream,
-                         src, dst, L.nx, L.ny, L.plane, ry, r, corr);
+                         src, dst, L.nx, L.ny, L.pitch, ry, r, corr);
       return;
     }
     if (L.stencil == LBM_STENCIL_LOCAL_CENTRAL5) {
       hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_CENTRAL5, NT, MODE, QG>), g, dim3(W + 64), 0,
-                         L.stream, src, dst, L.nx, L.ny, L.plane, ry, r, corr);
+                         L.stream, src, dst, L.nx, L.ny, L.pitch, ry, r, corr);
       return;
     }
   }
   if (L.stencil == LBM_STENCIL_CENTRAL5)
     hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream, src,
-                       dst, L.nx, L.ny, L.plane, ry, r, corr);
+                       dst, L.nx, L.ny, L.pitch, ry, r, corr);
   else
     hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream, src,
-                       dst, L.nx, L.ny, L.plane, ry, r, corr);
+                       dst, L.nx, L.ny, L.pitch, ry, r, corr);
 }
 
 template <typename S, typename C, int W, bool NT, int QG>
@@ -1252,24 +1262,23 @@ static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& 
     if constexpr (sizeof(S) == 2 && QG == 5) {
       if ((L.nx & 3) == 0) {
         hipLaunchKernelGGL((k_fused_dns_quad<S, C, NT>), dim3((L.nx + 255) / 256, L.ny), dim3(64), 0, L.stream, src,
-                           dst, L.nx, L.ny, L.plane, r);
+                           dst, L.nx, L.ny, L.pitch, r);
         return;
       }
     }
     if ((L.nx & 1) == 0)
       hipLaunchKernelGGL((k_fused_dns_pair<S, C, NT, QG>), dim3((L.nx + 255) / 256, L.ny), dim3(128), 0, L.stream,
-                         src, dst, L.nx, L.ny, L.plane, r);
+                         src, dst, L.nx, L.ny, L.pitch, r);
     else
       hipLaunchKernelGGL((k_fused_dns<S, C, NT, QG>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream, src,
-                         dst, L.nx, L.ny, L.plane, r);
+                         dst, L.nx, L.ny, L.pitch, r);
     return;
   }
   // Strip width: 512 lanes for wide grids with FP32 compute, 256 otherwise (the
   // LDS ring of a 512-lane FP64 strip would exceed 64 KB), 64 for narrow
-  // grids.  With 16-bit storage and the state beyond the caches the smaller
-  // workgroups measured 13-21 % faster (4096^2, 8192^2); cache-resident grids
-  // keep 512 lanes.
-  if constexpr (sizeof(C) == 4 && (sizeof(S) == 4 || !NT)) {
+  // grids.  Measured with the lattice-row layout at 4096^2 .. 16384^2: 512
+  // lanes beat 256 by 2-4 % with FP32 storage and by up to 1.6x with FP16.
+  if constexpr (sizeof(C) == 4) {
     if (L.nx >= 1024) {
       launch_les<S, C, 512, NT, QG>(L, src, dst, r, corr);
       return;
@@ -1287,7 +1296,7 @@ template <typename S>
 static hipError_t mom5f_typed(const Launch& L, int64_t t, float* out) {
   if (layout_at(L, t) != kLayoutPull) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_moments5f_row<S>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream,
-                     buffer_at<S>(L, t), out, L.nx, L.ny, L.plane, rest_ref(L));
+                     buffer_at<S>(L, t), out, L.nx, L.ny, L.pitch, rest_ref(L));
   return hipGetLastError();
 }
 
@@ -1308,10 +1317,10 @@ template <typename S, typename C, int STENCIL>
 static void launch_aa_les(const Launch& L, S* A, const C* mb, const Rates<C>& r, bool odd) {
   if (odd)
     hipLaunchKernelGGL((k_aa_les<S, C, true, STENCIL>), aa_grid(L), dim3(kAARow), 0, L.stream, A, mb, L.nx, L.ny,
-                       L.plane, r);
+                       L.pitch, r);
   else
     hipLaunchKernelGGL((k_aa_les<S, C, false, STENCIL>), aa_grid(L), dim3(kAARow), 0, L.stream, A, mb, L.nx,
-                       L.ny, L.plane, r);
+                       L.ny, L.pitch, r);
 }
 
 template <typename S>
@@ -1349,32 +1358,32 @@ static hipError_t step_typed(const Launch& L, int64_t t, bool corr_refresh) {
     if (L.stencil == LBM_STENCIL_ISO9) {
       if (odd)
         hipLaunchKernelGGL((k_aa_les_lagged<S, C, true, LBM_STENCIL_ISO9>), grid, dim3(kAARow), 0, L.stream, A, prev, next,
-                           L.nx, L.ny, L.plane, r);
+                           L.nx, L.ny, L.pitch, r);
       else
         hipLaunchKernelGGL((k_aa_les_lagged<S, C, false, LBM_STENCIL_ISO9>), grid, dim3(kAARow), 0, L.stream, A, prev, next,
-                           L.nx, L.ny, L.plane, r);
+                           L.nx, L.ny, L.pitch, r);
     } else {
       if (odd)
         hipLaunchKernelGGL((k_aa_les_lagged<S, C, true, LBM_STENCIL_CENTRAL5>), grid, dim3(kAARow), 0, L.stream, A, prev,
-                           next, L.nx, L.ny, L.plane, r);
+                           next, L.nx, L.ny, L.pitch, r);
       else
         hipLaunchKernelGGL((k_aa_les_lagged<S, C, false, LBM_STENCIL_CENTRAL5>), grid, dim3(kAARow), 0, L.stream, A, prev,
-                           next, L.nx, L.ny, L.plane, r);
+                           next, L.nx, L.ny, L.pitch, r);
     }
     return hipGetLastError();
   }
   if (!les) {
     if (odd)
-      hipLaunchKernelGGL((k_aa_dns<S, C, true>), grid, dim3(kAARow), 0, L.stream, A, L.nx, L.ny, L.plane, r);
+      hipLaunchKernelGGL((k_aa_dns<S, C, true>), grid, dim3(kAARow), 0, L.stream, A, L.nx, L.ny, L.pitch, r);
     else
-      hipLaunchKernelGGL((k_aa_dns<S, C, false>), grid, dim3(kAARow), 0, L.stream, A, L.nx, L.ny, L.plane, r);
+      hipLaunchKernelGGL((k_aa_dns<S, C, false>), grid, dim3(kAARow), 0, L.stream, A, L.nx, L.ny, L.pitch, r);
     return hipGetLastError();
   }
   C* mb = reinterpret_cast<C*>(static_cast<char*>(L.work) + L.off_mb);
   if (odd)
-    hipLaunchKernelGGL((k_aa_moments<S, C, true>), grid, dim3(kAARow), 0, L.stream, A, mb, L.nx, L.ny, L.plane);
+    hipLaunchKernelGGL((k_aa_moments<S, C, true>), grid, dim3(kAARow), 0, L.stream, A, mb, L.nx, L.ny, L.pitch);
   else
-    hipLaunchKernelGGL((k_aa_moments<S, C, false>), grid, dim3(kAARow), 0, L.stream, A, mb, L.nx, L.ny, L.plane);
+    hipLaunchKernelGGL((k_aa_moments<S, C, false>), grid, dim3(kAARow), 0, L.stream, A, mb, L.nx, L.ny, L.pitch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (L.stencil) {
@@ -1393,10 +1402,10 @@ static hipError_t lag_prime_typed(const Launch& L, int64_t t) {
   C* mb = moment_set<C>(L, int(t & 1));
   if (t & 1)
     hipLaunchKernelGGL((k_aa_moments<S, C, true>), aa_grid(L), dim3(kAARow), 0, L.stream, A, mb, L.nx, L.ny,
-                       L.plane);
+                       L.pitch);
   else
     hipLaunchKernelGGL((k_aa_moments<S, C, false>), aa_grid(L), dim3(kAARow), 0, L.stream, A, mb, L.nx, L.ny,
-                       L.plane);
+                       L.pitch);
   return hipGetLastError();
 }
 
@@ -1422,7 +1431,7 @@ template <typename S>
 static hipError_t init_typed(const Launch& L, const lbm_kh_params& kh) {
   return by_lattice<S>(L, [&](auto qg) {
     hipLaunchKernelGGL((k_init_kh<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
-                       buffer_at<S>(L, 0), L.nx, L.ny, L.plane, layout_at(L, 0), rest_ref(L), kh);
+                       buffer_at<S>(L, 0), L.nx, L.ny, L.pitch, layout_at(L, 0), rest_ref(L), kh);
     return hipGetLastError();
   });
 }
@@ -1440,7 +1449,7 @@ template <typename S>
 static hipError_t init_sech2_typed(const Launch& L, const lbm_sech2_params& jet) {
   return by_lattice<S>(L, [&](auto qg) {
     hipLaunchKernelGGL((k_init_sech2<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
-                       buffer_at<S>(L, 0), L.nx, L.ny, L.plane, layout_at(L, 0), rest_ref(L), jet);
+                       buffer_at<S>(L, 0), L.nx, L.ny, L.pitch, layout_at(L, 0), rest_ref(L), jet);
     return hipGetLastError();
   });
 }
@@ -1458,7 +1467,7 @@ template <typename S>
 static hipError_t init_moments_typed(const Launch& L, int64_t t, const double* mom) {
   return by_lattice<S>(L, [&](auto qg) {
     hipLaunchKernelGGL((k_init_moments<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
-                       buffer_at<S>(L, t), mom, L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L));
+                       buffer_at<S>(L, t), mom, L.nx, L.ny, L.pitch, layout_at(L, t), rest_ref(L));
     return hipGetLastError();
   });
 }
@@ -1476,7 +1485,7 @@ template <typename S>
 static hipError_t get_typed(const Launch& L, int64_t t, double* out) {
   return by_lattice<S>(L, [&](auto qg) {
     hipLaunchKernelGGL((k_get_state<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
-                       buffer_at<S>(L, t), out, L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L));
+                       buffer_at<S>(L, t), out, L.nx, L.ny, L.pitch, layout_at(L, t), rest_ref(L));
     return hipGetLastError();
   });
 }
@@ -1494,7 +1503,7 @@ template <typename S>
 static hipError_t set_typed(const Launch& L, int64_t t, const double* in) {
   return by_lattice<S>(L, [&](auto qg) {
     hipLaunchKernelGGL((k_set_state<S, decltype(qg)::value>), tile_grid(L.nx, L.ny), kTile, 0, L.stream,
-                       buffer_at<S>(L, t), in, L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L));
+                       buffer_at<S>(L, t), in, L.nx, L.ny, L.pitch, layout_at(L, t), rest_ref(L));
     return hipGetLastError();
   });
 }
@@ -1512,7 +1521,7 @@ template <typename S>
 static hipError_t moments_typed(const Launch& L, int64_t t, double* out, bool mark) {
   return by_lattice<S>(L, [&](auto qg) {
     hipLaunchKernelGGL((k_moments_out<S, decltype(qg)::value>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0,
-                       L.stream, buffer_at<S>(L, t), out, L.nx, L.ny, L.plane, layout_at(L, t), rest_ref(L), mark);
+                       L.stream, buffer_at<S>(L, t), out, L.nx, L.ny, L.pitch, layout_at(L, t), rest_ref(L), mark);
     return hipGetLastError();
   });
 }

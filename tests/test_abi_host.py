@@ -43,18 +43,27 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(N.LbmDiag) == 8 + 11 * 8 + 8
 
 
+def _buffer_elems(nx, ny, npop):
+    """One population buffer: ny lattice rows of npop population rows, each
+    padded to a multiple of 64 elements; the total rounded to 256 elements."""
+    e = ny * npop * ((nx + 63) // 64 * 64)
+    return (e + 255) // 256 * 256
+
+
 def test_buffer_sizes(lib):
     p = _params()
-    n_plane = ((64 * 48 + 1023) // 1024) * 1024 + 256
-    assert lib.lbm_state_bytes(ctypes.byref(p)) == 2 * 19 * n_plane * 8
+    one = _buffer_elems(p.nx, p.ny, 19)
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 2 * one * 8
     p.schedule = N.LBM_SCHED_AA
-    assert lib.lbm_state_bytes(ctypes.byref(p)) == 19 * n_plane * 8
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == one * 8
     p.dtype = N.LBM_FP32
-    assert lib.lbm_state_bytes(ctypes.byref(p)) == 19 * n_plane * 4
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == one * 4
+    q = _params(nx=70, ny=9)   # padded rows, total rounded up
+    assert lib.lbm_state_bytes(ctypes.byref(q)) == 2 * _buffer_elems(70, 9, 19) * 8 == 2 * 22016 * 8
     w = lib.lbm_work_bytes(ctypes.byref(p))
     assert w >= 4 * 64 * 48 * 4 + 5 * 64 * 48 * 8
     p.schedule = N.LBM_SCHED_AA_LAGGED
-    assert lib.lbm_state_bytes(ctypes.byref(p)) == 19 * n_plane * 4
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == one * 4
     assert lib.lbm_work_bytes(ctypes.byref(p)) >= w + 4 * 64 * 48 * 4   # two sets of moment planes
     p.schedule = N.LBM_SCHED_FUSED
     assert lib.lbm_work_bytes(ctypes.byref(p)) < w  # no moment planes without the in-place closure sweep
@@ -240,10 +249,10 @@ def test_header_constants_match_the_binding():
 
 def test_d2q9_magnetic_lattice_params(lib):
     p = _params(mag_lattice=N.LBM_MAG_D2Q9)
-    n_plane = ((64 * 48 + 1023) // 1024) * 1024 + 256
-    assert lib.lbm_state_bytes(ctypes.byref(p)) == 2 * 27 * n_plane * 8
+    one = _buffer_elems(p.nx, p.ny, 27)
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 2 * one * 8
     p.dtype = N.LBM_FP32
-    assert lib.lbm_state_bytes(ctypes.byref(p)) == 2 * 27 * n_plane * 4
+    assert lib.lbm_state_bytes(ctypes.byref(p)) == 2 * one * 4
     assert lib.lbm_work_bytes(ctypes.byref(_params(mag_lattice=N.LBM_MAG_D2Q9, closure=N.LBM_CLOSURE_FULL))) > 0
     for bad in (dict(schedule=N.LBM_SCHED_AA), dict(schedule=N.LBM_SCHED_AA_LAGGED),
                 dict(closure=N.LBM_CLOSURE_LEARNED), dict(grad_stencil=N.LBM_STENCIL_LOCAL_ISO9),
