@@ -76,40 +76,91 @@ def measured_traffic(kernel: str, lups: int):
         return None
 
 
-def cpu_baseline(les_steps: int, dns_steps: int) -> dict:
-    """The FP64 NumPy oracle on a bounded sample of the same workload, one thread."""
+def host_cpu() -> dict:
+    """CPU model (/proc/cpuinfo), os.cpu_count() and the cores this process may
+    run on (its affinity mask)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cores": usable}
+
+
+def _oracle_run(n: int, delta: float, steps: int, seed: int) -> tuple:
+    """One single-threaded oracle run of the benchmark jet (worker of the
+    all-core leg): lattice updates and seconds."""
     try:
         from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(limits=1)
     except ImportError:  # pragma: no cover
-        threadpool_limits = None
+        lim = None
     from oracle.lbmhd_oracle import Oracle
 
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    try:
-        lups = 0
-        elapsed = 0.0
-        for n, delta, steps in ((LES_N, LES_DELTA, les_steps), (DNS_N, 0.0, dns_steps)):
-            if steps <= 0:
-                continue
-            o = Oracle(n, n, NU, ETA, delta=delta, s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
-            o.init_kh_jet(seed=0, **KH)
-            t0 = time.perf_counter()
-            o.step(steps)
-            elapsed += time.perf_counter() - t0
-            lups += n * n * steps
-            log(f"oracle {n}^2 delta={delta}: {steps} steps in {time.perf_counter() - t0:.2f} s")
-            del o
-    finally:
-        if ctx is not None:
-            ctx.unregister() if hasattr(ctx, "unregister") else None
-    return {
+    o = Oracle(n, n, NU, ETA, delta=delta, s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
+    o.init_kh_jet(seed=seed, **KH)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    del lim
+    return n * n * steps, dt
+
+
+def cpu_baseline(les_steps: int, dns_steps: int, all_steps: int, max_procs: int = 16) -> dict:
+    """The FP64 NumPy oracle on a bounded sample of the same workload: one
+    thread (les_steps of the 1024^2 LES + dns_steps of the 4096^2 DNS), and
+    all host cores (one single-threaded process per usable core, at most
+    max_procs, each running all_steps of the 1024^2 LES on its own seed;
+    aggregate = total lattice updates / wall time of the slowest).  Runs
+    before the GPU is touched, so the worker processes start from a clean
+    parent."""
+    import multiprocessing as mp
+
+    host = host_cpu()
+    lups = 0
+    elapsed = 0.0
+    for n, delta, steps in ((LES_N, LES_DELTA, les_steps), (DNS_N, 0.0, dns_steps)):
+        if steps <= 0:
+            continue
+        l, dt = _oracle_run(n, delta, steps, 0)
+        lups += l
+        elapsed += dt
+        log(f"oracle {n}^2 delta={delta}: {steps} steps in {dt:.2f} s")
+    out = {
         "value": lups / elapsed / 1e6,
         "unit": "MLUPS",
         "cores": 1,
         "kind": "oracle",
         "sample": f"FP64 NumPy oracle, 1 thread: {LES_N}^2 LES (Delta={LES_DELTA:g}) x {les_steps} steps "
                   f"+ {DNS_N}^2 DNS x {dns_steps} step(s), {elapsed:.1f} s",
+        **host,
     }
+    procs = max(1, min(max_procs, host["affinity_cores"]))
+    if all_steps > 0 and procs > 1:
+        ctx = mp.get_context("spawn")
+        t0 = time.perf_counter()
+        with ctx.Pool(procs) as pool:
+            res = pool.starmap(_oracle_run, [(LES_N, LES_DELTA, all_steps, k) for k in range(procs)])
+        wall = time.perf_counter() - t0
+        tot = sum(r[0] for r in res)
+        slowest = max(r[1] for r in res)
+        out.update({
+            "cores_all": procs,
+            "mlups_all": tot / slowest / 1e6,
+            "sample_all": f"{procs} single-threaded FP64 oracle processes, each {LES_N}^2 LES "
+                          f"(Delta={LES_DELTA:g}) x {all_steps} steps on its own seed; slowest {slowest:.1f} s "
+                          f"({wall:.1f} s with process start)",
+        })
+        log(f"oracle on {procs} cores: {out['mlups_all']:.1f} MLUPS aggregate")
+    return out
 
 
 def variant_oracle_rates(n: int = 512, steps: int = 2) -> dict:
@@ -127,10 +178,13 @@ def variant_oracle_rates(n: int = 512, steps: int = 2) -> dict:
     from oracle import learned as OL
 
     def learned_hook():
-        from paper_1705_09807_amd import learned as G
-        flat = G.glorot_params(0).double().numpy()
-        nm = {"w1": flat[:4096].reshape(64, 64), "b1": flat[4096:4160], "w2": flat[4160:8256].reshape(64, 64),
-              "b2": flat[8256:8320], "w3": flat[8320:8576].reshape(64, 4), "b3": flat[8576:8580]}
+        # a seeded random network (the oracle's cost per cell does not depend
+        # on the weights); the pad row of w1 is zero
+        rng = np.random.default_rng(0)
+        nm = {"w1": rng.normal(0.0, 0.125, (64, 64)), "b1": rng.normal(0.0, 0.01, 64),
+              "w2": rng.normal(0.0, 0.125, (64, 64)), "b2": rng.normal(0.0, 0.01, 64),
+              "w3": rng.normal(0.0, 0.125, (64, 4)), "b3": rng.normal(0.0, 0.01, 4)}
+        nm["w1"][63] = 0.0
         # per-feature normalisation: each field's value on its nine patch columns, pad 0 / 1
         shift = np.append(np.repeat([1.0, 0.0, 0.0, KH["B0"], 0.0, 0.0, 0.0], 9), 0.0)
         scale = np.append(np.repeat([1e3, 20.0, 20.0, 100.0, 100.0, 1e3, 1e3], 9), 1.0)
@@ -353,7 +407,7 @@ def learned_study(args, dev, stream) -> int:
     BF16 storage, and with the network evaluated every --corr-every steps)
     starts from the filtered DNS initial state and runs alongside the DNS.  Reported: the relative L2 error of the total-energy spectrum
     E_K + E_M over the bins 1 .. N_LES/4 against the filtered DNS at several
-    times, the growth rate of the streamwise k_x = 1 mode, a-priori subgrid
+    times, the growth rate of the streamwise k_x = 3 mode, a-priori subgrid
     errors, and wall-clock throughput of each run.  One JSON line on stdout.
     """
     import math
@@ -537,6 +591,8 @@ def main() -> int:
                          "the network every --corr-every steps rounded up to whole intervals (0 = skip)")
     ap.add_argument("--cpu-les-steps", type=int, default=15)
     ap.add_argument("--cpu-dns-steps", type=int, default=3)
+    ap.add_argument("--cpu-all-steps", type=int, default=20,
+                    help="steps of the 1024^2 LES per process in the all-core oracle leg (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="instead of the benchmark: run the 8192^2 jet (nu = eta = 1e-4, B0 = 0.01) "
@@ -573,6 +629,15 @@ def main() -> int:
         print("bench.py runs on exactly one GPU (the library has no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         return 2
+
+    # the CPU legs run first, before anything touches the GPU (their worker
+    # processes start from a clean parent)
+    study = args.precision_study > 0 or args.learned_study > 0 or args.jet_study > 0
+    cpu = None
+    variant_rates = {}
+    if not args.no_cpu_baseline and not study:
+        cpu = cpu_baseline(args.cpu_les_steps, args.cpu_dns_steps, args.cpu_all_steps)
+        variant_rates = variant_oracle_rates()
 
     import torch
 
@@ -627,7 +692,9 @@ def main() -> int:
         e2.record(stream)
         chunks.append((c, e0, e1, e2))
         done += c
-        if done % args.diag_every == 0:
+        # every diag_every steps and at the end of the timed window, so a
+        # window shorter than diag_every still contains the diagnostics
+        if done % args.diag_every == 0 or done == K:
             diag_log.append((dns.diagnostics(), les.diagnostics()))
     torch.cuda.synchronize(dev)
     t1 = time.perf_counter()
@@ -660,6 +727,7 @@ def main() -> int:
         "dns4096": {"mlups": round(dns_lups / (dns_ms * 1e-3) / 1e6, 1)},
     }
 
+    roofline_plain = None
     if args.les4096_steps > 0:
         del les
         # 4096^2 LES (Delta = 4) in every closure variant and schedule, each
@@ -721,6 +789,20 @@ def main() -> int:
                 rec[name] = {k: float(f"{v:.3e}") for k, v in field_rel(mom, ref).items()}
                 del mom
             extra[key] = rec
+            if key == "les4096":
+                # the plain closure beyond the caches: one k_fused_les launch per step
+                roofline_plain = {
+                    "bound": "hbm",
+                    "kernel": "k_fused_les<float, float, 512, 0, true, 0, 5> (4096^2 LES sweep, plain closure)",
+                    "achieved": round(bw, 1),
+                    "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s",
+                    "frac": round(bw / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic("fused_les4096_fp32", dns_lups),
+                    "algorithmic_bytes_per_launch": BYTES_PER_LUP_FP32 * dns_lups,
+                    "avg_launch_us": round(ms * 1e3, 2),
+                    "target_frac": 0.70,
+                }
             log(f"{key}: {ms * 1e3:.1f} us/step, {bw:.0f} GB/s algorithmic")
             del sv
         del mom_off, mom_sync
@@ -884,7 +966,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": "Kelvin-Helmholtz jet, LES 1024^2 Delta=4 + DNS 4096^2, FP32, "
-                        "diagnostics every 100 steps",
+                        "diagnostics every 100 steps and at the end of the timed window",
+            "diagnostics_in_timed_window": len(diag_log),
             "grids": [LES_N, DNS_N],
             "delta": [LES_DELTA, 0.0],
             "U0": KH["U0"], "delta_over_L": KH["delta_over_L"], "B0": KH["B0"], "nu": NU, "eta": ETA,
@@ -894,6 +977,7 @@ def main() -> int:
             "parallelism": "single GPU",
         },
         "roofline": roofline,
+        "roofline_plain_closure": roofline_plain,
         "extra": extra,
         "diagnostics_last": {"dns": {k: last_dns.get(k) for k in ("t", "e_kin", "e_mag", "enstrophy", "j2")},
                              "les": {k: last_les.get(k) for k in ("t", "e_kin", "e_mag", "enstrophy", "j2")}},
@@ -909,10 +993,10 @@ def main() -> int:
         torch.cuda.synchronize(dev)
         del a, b
         torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_les_steps, args.cpu_dns_steps)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
         # the oracle beside each variant leg (its own mode, a 512^2 sample)
-        for key, rec in variant_oracle_rates().items():
+        for key, rec in variant_rates.items():
             for k, v in out["extra"].items():
                 if k == key or (key == "les1024_learned" and k.startswith(key)):
                     v.update(rec)

@@ -47,3 +47,24 @@ def test_correction_interval_must_be_positive():
     assert res.returncode == 2
     assert "--corr-every" in res.stderr
     assert res.stdout == ""
+
+
+def test_cpu_legs_report_host_and_do_not_import_the_product():
+    """The oracle legs: one thread and every usable core (bounded to two here),
+    with the CPU model and core counts, and without importing the library's
+    package (the oracle leg is test infrastructure only)."""
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+            "c = bench.cpu_baseline(1, 0, 1, max_procs=2); "
+            "v = bench.variant_oracle_rates(n=32, steps=1); "
+            "print(json.dumps({'c': c, 'v': sorted(v), 'product': 'paper_1705_09807_amd' in sys.modules}))" % ROOT)
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert res.returncode == 0, res.stderr
+    import json
+    out = json.loads(res.stdout.strip().splitlines()[-1])
+    c = out["c"]
+    assert c["kind"] == "oracle" and c["cores"] == 1 and c["value"] > 0
+    assert c["nproc"] >= 1 and c["affinity_cores"] >= 1 and "cpu_model" in c
+    if c["affinity_cores"] > 1:
+        assert c["cores_all"] == 2 and c["mlups_all"] > 0
+    assert "les1024_learned" in out["v"]
+    assert out["product"] is False
