@@ -109,6 +109,24 @@ int lbm_mlp_train_step(float* params_dev, float* adam_m_dev, float* adam_v_dev, 
                        const int32_t* idx_dev, int32_t batch, void* work_dev, size_t work_bytes,
                        float* loss_dev, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc): the same
+ * Adam step as lbm_mlp_train_step, with the same kernels and bit-identical
+ * results, but no work buffer.  Its work lives in a fixed array of
+ * LBM_MLP_TRAIN_NOALLOC_BYTES bytes of device memory that the library holds
+ * on every GPU it runs on until the process ends; the call allocates and
+ * frees nothing.  1 <= batch <= LBM_MLP_TRAIN_NOALLOC_BATCH; a larger batch
+ * returns LBM_EINVAL before any work is enqueued.  hip_stream must belong to
+ * the current device.  All calls on one GPU share that GPU's array: calls
+ * that overlap on one GPU (other streams or host threads) race and must be
+ * serialised by the caller.  Other arguments and rules as for
+ * lbm_mlp_train_step. */
+#define LBM_MLP_TRAIN_NOALLOC_BATCH 16384
+#define LBM_MLP_TRAIN_NOALLOC_BYTES 9437184
+int lbm_mlp_train_step_noalloc(float* params_dev, float* adam_m_dev, float* adam_v_dev, int64_t step, double lr,
+                               const lbm_mlp_norm* norm_dev, const float* x_dev, const float* t_dev,
+                               const int32_t* idx_dev, int32_t batch, float* loss_dev, void* hip_stream);
+
 /* The two halves of lbm_mlp_train_step, for callers that combine gradients
  * (e.g. summed over data-parallel replicas) before the update:
  * lbm_mlp_gradient writes the batch gradient (LBM_MLP_PARAMS floats) to

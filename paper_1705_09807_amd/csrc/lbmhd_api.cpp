@@ -407,6 +407,21 @@ int lbm_mlp_train_step(float* params_dev, float* adam_m_dev, float* adam_v_dev, 
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_mlp_train_step");
 }
 
+int lbm_mlp_train_step_noalloc(float* params_dev, float* adam_m_dev, float* adam_v_dev, int64_t step, double lr,
+                               const lbm_mlp_norm* norm_dev, const float* x_dev, const float* t_dev,
+                               const int32_t* idx_dev, int32_t batch, float* loss_dev, void* hip_stream) {
+  if (batch < 1 || batch > LBM_MLP_TRAIN_NOALLOC_BATCH || !lbm::mlp_train_noalloc_limit_ok(batch))
+    return fail(LBM_EINVAL, "batch must lie in [1, LBM_MLP_TRAIN_NOALLOC_BATCH = 16384] without a work buffer");
+  if (step < 1) return fail(LBM_EINVAL, "step must be >= 1");
+  if (!std::isfinite(lr) || lr <= 0.0) return fail(LBM_EINVAL, "lr must be finite and > 0");
+  const void* ptrs[] = {params_dev, adam_m_dev, adam_v_dev, norm_dev, x_dev, t_dev, idx_dev};
+  for (const void* q : ptrs)
+    if (!q || !aligned(q)) return fail(LBM_EINVAL, "device pointers must be non-NULL and 256-byte aligned");
+  hipError_t e = lbm::launch_mlp_train_noalloc(params_dev, adam_m_dev, adam_v_dev, step, lr, norm_dev, x_dev, t_dev,
+                                               idx_dev, batch, loss_dev, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_mlp_train_step_noalloc");
+}
+
 namespace {
 int check_filter(int32_t nx, int32_t ny, int32_t factor, double delta) {
   if (nx < 4 || ny < 4 || nx > 32768 || ny > 32768) return fail(LBM_EINVAL, "nx and ny must lie in [4, 32768]");

@@ -87,6 +87,12 @@ hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad,
 hipError_t launch_mlp_train(float* params, float* m, float* v, int64_t step, double lr, const lbm_mlp_norm* norm,
                             const float* x, const float* t, const int32_t* idx, int batch, void* work, float* loss,
                             hipStream_t st);
+// The same step with its work in the library's fixed per-device array
+// (batch <= LBM_MLP_TRAIN_NOALLOC_BATCH; hipErrorInvalidValue beyond).
+bool mlp_train_noalloc_limit_ok(int batch);
+hipError_t launch_mlp_train_noalloc(float* params, float* m, float* v, int64_t step, double lr,
+                                    const lbm_mlp_norm* norm, const float* x, const float* t, const int32_t* idx,
+                                    int batch, float* loss, hipStream_t st);
 size_t mlp_stats_work_bytes();
 hipError_t launch_mlp_stats(const float* x, const float* t, int64_t n, lbm_mlp_norm* norm, void* work,
                             hipStream_t st);

@@ -22,6 +22,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "lbmhd_device.h"
 #include "lbmhd_internal.h"
 #include "lbmhd_learned.h"
@@ -1128,6 +1130,52 @@ hipError_t launch_mlp_train(float* params, float* m, float* v, int64_t step, dou
   hipError_t e = launch_mlp_gradient(params, norm, x, t, idx, batch, work, grad, loss, st);
   if (e != hipSuccess) return e;
   return launch_mlp_adam(params, m, v, grad, step, lr, st);
+}
+
+// Training step without a caller-provided work buffer.  Its work (packed
+// network, per-workgroup partial gradients, loss partials, reduced gradient;
+// every byte the kernels read is written earlier in the same step, so nothing
+// needs clearing) lives in this fixed device array, one copy per GPU that the
+// library runs on, held until the process ends.  In host code `scratch` names
+// a host-side stand-in, not device memory: kernels get the address that
+// hipGetSymbolAddress returns on the current device, looked up once per device
+// at the first call there.
+static __device__ __align__(256) char scratch[LBM_MLP_TRAIN_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_on_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+bool mlp_train_noalloc_limit_ok(int batch) {
+  return batch >= 1 && batch <= LBM_MLP_TRAIN_NOALLOC_BATCH && mlp_train_work_bytes(batch) <= sizeof(scratch);
+}
+
+hipError_t launch_mlp_train_noalloc(float* params, float* m, float* v, int64_t step, double lr,
+                                    const lbm_mlp_norm* norm, const float* x, const float* t, const int32_t* idx,
+                                    int batch, float* loss, hipStream_t st) {
+  if (!mlp_train_noalloc_limit_ok(batch)) return hipErrorInvalidValue;
+  void* work = nullptr;
+  const hipError_t e = scratch_on_current_device(&work);
+  if (e != hipSuccess) return e;
+  return launch_mlp_train(params, m, v, step, lr, norm, x, t, idx, batch, work, loss, st);
 }
 
 size_t mlp_stats_work_bytes() { return (size_t)(kStatBlocks * 11 + 16) * sizeof(double); }

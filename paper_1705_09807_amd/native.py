@@ -51,6 +51,8 @@ LBM_MLP_OFF_W3 = 8320
 LBM_MLP_OFF_B3 = 8576
 LBM_MLP_PARAMS = 8580
 LBM_MLP_PACKED_BYTES = 31744
+LBM_MLP_TRAIN_NOALLOC_BATCH = 16384
+LBM_MLP_TRAIN_NOALLOC_BYTES = 9437184
 
 
 class LbmParams(ctypes.Structure):
@@ -132,6 +134,7 @@ _SIGNATURES = {
     "lbm_mlp_gradient": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _SZ, _P, _P, _P]),
     "lbm_mlp_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_double, _P]),
     "lbm_mlp_train_step": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_double, _P, _P, _P, _P, _I32, _P, _SZ, _P, _P]),
+    "lbm_mlp_train_step_noalloc": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_double, _P, _P, _P, _P, _I32, _P, _P]),
     "lbm_filter_work_bytes": (_SZ, [_I32, _I32, _I32, ctypes.c_double]),
     "lbm_filter_subsample": (ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_double, _P, _P, _SZ, _P]),
     "lbm_closure_samples": (ctypes.c_int, [_P, _I32, _I32, ctypes.c_double, _I32, _P, _P, _P]),

@@ -260,3 +260,21 @@ def test_d2q9_magnetic_lattice_params(lib):
         assert lib.lbm_state_bytes(ctypes.byref(_params(mag_lattice=N.LBM_MAG_D2Q9, **bad))) == 0, bad
     assert lib.lbm_state_bytes(ctypes.byref(_params(mag_lattice=2))) == 0
     assert lib.lbm_state_bytes(ctypes.byref(_params(reserved=1))) == 0
+
+
+def test_train_step_noalloc_rejects_bad_arguments_without_a_gpu(lib):
+    """The allocation-free training step checks its arguments on the host
+    before touching a device: batches beyond its fixed work array, a bad step
+    or learning rate, and NULL or misaligned pointers are LBM_EINVAL."""
+    f = ctypes.c_void_p(1 << 22)
+    args = [f, f, f, 1, 1e-3, f, f, f, f]
+    fn = lib.lbm_mlp_train_step_noalloc
+    assert fn(*args, N.LBM_MLP_TRAIN_NOALLOC_BATCH + 1, None, None) == N.LBM_EINVAL
+    assert b"16384" in lib.lbm_last_error()
+    assert fn(*args, 0, None, None) == N.LBM_EINVAL
+    assert fn(f, f, f, 0, 1e-3, f, f, f, f, 64, None, None) == N.LBM_EINVAL
+    assert fn(f, f, f, 1, -1.0, f, f, f, f, 64, None, None) == N.LBM_EINVAL
+    assert fn(f, f, f, 1, 1e-3, None, f, f, f, 64, None, None) == N.LBM_EINVAL
+    assert fn(f, f, f, 1, 1e-3, f, ctypes.c_void_p((1 << 22) + 4), f, f, 64, None, None) == N.LBM_EINVAL
+    # the fixed array holds the work of the largest batch it accepts
+    assert lib.lbm_mlp_train_work_bytes(N.LBM_MLP_TRAIN_NOALLOC_BATCH) <= N.LBM_MLP_TRAIN_NOALLOC_BYTES
