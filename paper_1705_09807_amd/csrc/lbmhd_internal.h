@@ -54,6 +54,8 @@ int64_t row_pitch(int nx);
 // Elements of one population buffer: ny lattice rows of (9 + 2 qg) population
 // rows each, element (q, x, y) at (y * (9 + 2 qg) + q) * pitch + x.
 int64_t buffer_elems(int nx, int ny, int qg);
+// Byte offset of the second population buffer of the fused schedule.
+size_t buffer_offset_bytes(int nx, int ny, int dtype, int qg);
 size_t state_bytes(int nx, int ny, int dtype, int schedule, int qg);
 // Work layout for the given geometry; returns total bytes and fills offsets.
 size_t work_layout(Launch& L);

@@ -38,10 +38,11 @@ static lbm_params params(void) {
 
 int main(void) {
   lbm_params p = params();
-  /* one buffer: 48 lattice rows of 19 (27) population rows of 64 elements */
-  CHECK(lbm_state_bytes(&p) == 2 * (size_t)(48 * 19 * 64) * 4);
+  /* one buffer: 48 lattice rows of 19 (27) population rows of 64 elements;
+     the second starts 4 KB past the 64 KB boundary after the first */
+  CHECK(lbm_state_bytes(&p) == 4 * 65536 + 4096 + (size_t)(48 * 19 * 64) * 4);
   p.mag_lattice = LBM_MAG_D2Q9;
-  CHECK(lbm_state_bytes(&p) == 2 * (size_t)(48 * 27 * 64) * 4);
+  CHECK(lbm_state_bytes(&p) == 6 * 65536 + 4096 + (size_t)(48 * 27 * 64) * 4);
   p.schedule = LBM_SCHED_AA;
   CHECK(lbm_state_bytes(&p) == 0);  /* D2Q9 g runs with the fused schedule only */
   CHECK(strlen(lbm_last_error()) > 0);
