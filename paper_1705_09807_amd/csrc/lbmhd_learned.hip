@@ -27,184 +27,9 @@
 #include "lbmhd_device.h"
 #include "lbmhd_internal.h"
 #include "lbmhd_learned.h"
+#include "lbmhd_mlp_device.h"
 
 namespace lbm {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x8 __attribute__((ext_vector_type(8)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-
-// Eight floats rounded to bfloat16 (nearest even), two per conversion.
-__device__ __forceinline__ unsigned pack2_bf16(float a, float b) {
-  const f32x2 v = {a, b};
-  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
-}
-__device__ __forceinline__ bf16x8 to_bf16x8(const f32x8& v) {
-  const u32x4 u = {pack2_bf16(v[0], v[1]), pack2_bf16(v[2], v[3]), pack2_bf16(v[4], v[5]), pack2_bf16(v[6], v[7])};
-  return __builtin_bit_cast(bf16x8, u);
-}
-
-// Packed network (LBM_MLP_PACKED_BYTES): bfloat16 A operands in lane order,
-// FP32 biases, the normalisation.
-constexpr int kPkA1 = 0;       // [ot 2][kb 4][lane 64][8] bf16
-constexpr int kPkA2 = 8192;    // [ot 2][kb 4][lane 64][8] bf16
-constexpr int kPkA3 = 16384;   // [kb 4][lane 64][8] bf16 (rows >= 4 zero)
-constexpr int kPkB1 = 20480;   // 64 floats
-constexpr int kPkB2 = 20736;   // 64 floats
-constexpr int kPkB3 = 20992;   // 4 floats (+ pad)
-constexpr int kPkNorm = 21248;  // lbm_mlp_norm
-// Layer 1 of the state-correction kernel, whose inputs are ordered by patch
-// position: contraction index k' = pos * 8 + field (pos = 3 row + column of
-// the 3x3 patch, field 0..6, field 7 and pos 9 zero), i.e. network input
-// field * 9 + pos.  [ot 2][kb 5][lane 64][8] bf16.
-constexpr int kPkA1c = 21504;
-static_assert(kPkNorm + (int)sizeof(lbm_mlp_norm) <= kPkA1c, "packed layout");
-static_assert(kPkA1c + 2 * 5 * 64 * 16 <= LBM_MLP_PACKED_BYTES, "packed size");
-static_assert(sizeof(lbm_mlp_norm) == 128, "norm size");
-
-constexpr float kOodLimit = 6.0f;
-
-// Hidden row held by accumulator register i of lane half h (one 32-row tile).
-__host__ __device__ constexpr int acc_row(int i, int h) { return (i / 4) * 8 + h * 4 + i % 4; }
-// Contraction index of element j of lane half h in 16-wide block kb of a
-// layer fed by accumulator registers (layers 2 and 3).
-__host__ __device__ constexpr int chained_k(int kb, int h, int j) {
-  return (kb / 2) * 32 + (2 * (kb % 2) + j / 4) * 8 + h * 4 + j % 4;
-}
-static_assert(chained_k(1, 0, 0) == 16 && chained_k(0, 1, 4) == 12 && chained_k(3, 1, 7) == 63, "chain");
-
-// Field of feature k < 63 (k / 9) and its 3x3 offset, by multiply-shift.
-__device__ __forceinline__ int feat_field(int k) { return (k * 57) >> 9; }
-
-__device__ __forceinline__ float bf16_round(float v) { return float(__bf16(v)); }
-
-// A operands of the three layers; KB1 16-wide contraction blocks in layer 1.
-template <int KB1>
-struct MlpW {
-  bf16x8 a1[2][KB1], a2[2][4], a3[4];
-};
-using MlpA = MlpW<4>;
-using MlpC = MlpW<5>;
-
-__device__ __forceinline__ void load_mlp(const char* __restrict__ pk, int lane, MlpA& w) {
-  const bf16x8* p1 = reinterpret_cast<const bf16x8*>(pk + kPkA1);
-  const bf16x8* p2 = reinterpret_cast<const bf16x8*>(pk + kPkA2);
-  const bf16x8* p3 = reinterpret_cast<const bf16x8*>(pk + kPkA3);
-#pragma unroll
-  for (int ot = 0; ot < 2; ++ot)
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      w.a1[ot][kb] = p1[(ot * 4 + kb) * 64 + lane];
-      w.a2[ot][kb] = p2[(ot * 4 + kb) * 64 + lane];
-    }
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb) w.a3[kb] = p3[kb * 64 + lane];
-}
-
-// The same with the patch-ordered layer 1 of the state-correction kernel.
-__device__ __forceinline__ void load_mlp_c(const char* __restrict__ pk, int lane, MlpC& w) {
-  const bf16x8* p1 = reinterpret_cast<const bf16x8*>(pk + kPkA1c);
-  const bf16x8* p2 = reinterpret_cast<const bf16x8*>(pk + kPkA2);
-  const bf16x8* p3 = reinterpret_cast<const bf16x8*>(pk + kPkA3);
-#pragma unroll
-  for (int ot = 0; ot < 2; ++ot) {
-#pragma unroll
-    for (int kb = 0; kb < 5; ++kb) w.a1[ot][kb] = p1[(ot * 5 + kb) * 64 + lane];
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) w.a2[ot][kb] = p2[(ot * 4 + kb) * 64 + lane];
-  }
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb) w.a3[kb] = p3[kb * 64 + lane];
-}
-
-// Accumulator of one 32-row tile preset to the bias of its rows.
-__device__ __forceinline__ f32x16 bias_tile(const float* __restrict__ b, int ot, int h) {
-  f32x16 acc;
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const f32x4 v = *reinterpret_cast<const f32x4*>(b + ot * 32 + g * 8 + h * 4);
-    acc[g * 4 + 0] = v[0];
-    acc[g * 4 + 1] = v[1];
-    acc[g * 4 + 2] = v[2];
-    acc[g * 4 + 3] = v[3];
-  }
-  return acc;
-}
-
-typedef short i16x8 __attribute__((ext_vector_type(8)));
-
-// ReLU of two accumulator tiles, rounded to bfloat16, as the four B operands
-// of the next layer.  Rounding is monotonic and keeps the sign, so the ReLU
-// is taken after it, on the packed bfloat16 bit patterns read as int16
-// (negative values, -0 included, are negative int16 and become +0).  The
-// rounded values go to hout (as floats) when given.
-__device__ __forceinline__ void activate(const f32x16 acc[2], bf16x8 hb[4], float* hout) {
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb) {
-    f32x8 a;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) a[j] = acc[kb / 2][(kb % 2) * 8 + j];
-    const bf16x8 v = to_bf16x8(a);
-    const i16x8 bits = __builtin_elementwise_max(__builtin_bit_cast(i16x8, v), i16x8(0));
-    hb[kb] = __builtin_bit_cast(bf16x8, bits);
-    if (hout) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) hout[kb * 8 + j] = float(hb[kb][j]);
-    }
-  }
-}
-
-// The network on the 32 cells of a wave: zb = layer-1 B operands of this lane
-// (cell lane % 32, inputs kb*16 + (lane/32)*8 + j in layer 1's contraction
-// order).  Returns y in lanes 0..31 (components 0..3).  h1, h2 (32 floats
-// each, may be null) receive the bfloat16 activations held by this lane,
-// element kb*8 + j = hidden chained_k(kb, lane/32, j).
-// Biases: b points at b1 (64 floats), b2 (64) and b3 (4) back to back, in
-// LDS or global memory.
-template <int KB1>
-__device__ __forceinline__ f32x4 mlp_wave(const MlpW<KB1>& w, const bf16x8 zb[KB1], const float* __restrict__ b,
-                                          int lane, float* h1, float* h2) {
-  const int h = lane >> 5;
-  const float* b1 = b;
-  const float* b2 = b + 64;
-  const float* b3 = b + 128;
-  f32x16 acc[2];
-  bf16x8 hb[4];
-#pragma unroll
-  for (int ot = 0; ot < 2; ++ot) {
-    acc[ot] = bias_tile(b1, ot, h);
-#pragma unroll
-    for (int kb = 0; kb < KB1; ++kb)
-      acc[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a1[ot][kb], zb[kb], acc[ot], 0, 0, 0);
-  }
-  activate(acc, hb, h1);
-#pragma unroll
-  for (int ot = 0; ot < 2; ++ot) {
-    acc[ot] = bias_tile(b2, ot, h);
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) acc[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a2[ot][kb], hb[kb], acc[ot], 0, 0, 0);
-  }
-  activate(acc, hb, h2);
-  f32x16 out;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) out[i] = 0.0f;
-  if (h == 0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) out[i] = b3[i];
-  }
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb) out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a3[kb], hb[kb], out, 0, 0, 0);
-  f32x4 y;
-  y[0] = out[0];
-  y[1] = out[1];
-  y[2] = out[2];
-  y[3] = out[3];
-  return y;
-}
 
 // ---------------------------------------------------------------------------
 // Packing
@@ -451,22 +276,83 @@ k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float*
 }
 
 // ---------------------------------------------------------------------------
-// Training: forward on the matrix cores, backward in FP32 on the vector ALU.
-// A workgroup of two waves takes chunks of 64 batch rows; activations and
-// deltas go through LDS; each thread owns a fixed set of gradient entries
-// and accumulates them over its workgroup's chunks in a fixed order.  Per-
-// workgroup partial gradients are summed in workgroup order by the Adam
-// kernel.
+// Training: forward and backward on the matrix cores.  A workgroup of two
+// waves takes chunks of 64 batch rows (32 per wave in the forward).  With the
+// batch row r, the loss L = sum (y - t)^2 / (4 batch) and straight-through
+// gradients of the bfloat16 roundings:
+//   d3 = dL/dy,  d2 = (d3 W3^T) [h2 > 0],  d1 = (d2 W2^T) [h1 > 0],
+//   G3 = h2^T d3, G2 = h1^T d2, G1 = z^T d1, biases: column sums of d.
+// d3 and d2 are formed in FP32 on the vector ALU (contraction over the four
+// outputs).  d1^T = W2 d2^T is one matrix-core product in the transposed
+// form of the forward (hidden units x rows, d2 in the accumulator layout of
+// h2, so it is directly the B operand), and G2, G1 are products over the 64
+// rows of the chunk from feature-major LDS tiles.  A delta enters the matrix
+// cores as three bfloat16 terms, d = hi + mid + lo + O(2^-25 |d|), so the
+// products carry the FP32 delta; activations and weights are bfloat16
+// already.  (Two terms, 16 bits, left 1e-4 relative errors in G1 over 5000
+// rows, where the row sums cancel.)  Each wave owns half of every weight gradient and accumulates it
+// over its workgroup's chunks in a fixed order; per-workgroup partials are
+// summed in workgroup order by k_mlp_reduce.
 // ---------------------------------------------------------------------------
 constexpr int kTrainChunk = 64;
 constexpr int kTrainBlocksMax = 1024;
 constexpr int kGradStride = 8704;  // floats per partial (>= LBM_MLP_PARAMS, 256-byte multiple)
+constexpr int kTs = 72;            // bfloat16 per feature row of an LDS tile (64 rows + pad)
 
 struct TrainLds {
-  float z[kTrainChunk][65], h1[kTrainChunk][65], h2[kTrainChunk][65];
-  float d2[kTrainChunk][65], d1[kTrainChunk][65];
-  float d3[kTrainChunk][4];
+  __bf16 z[64][kTs], h1[64][kTs], h2[64][kTs];     // [feature][chunk row]
+  __bf16 d2h[64][kTs], d2m[64][kTs], d2l[64][kTs], d1h[64][kTs], d1m[64][kTs], d1l[64][kTs];
+  bf16x8 a2b[2][4][64];                            // A operands of d1^T = W2 d2^T
+  float d3[4][kTrainChunk];
+  float w3[64 * 4];                                // bfloat16-rounded W3
+  double loss[128];
 };
+
+// hi + mid + lo bfloat16 split of eight floats (each remainder is exact in
+// FP32, so the three terms carry 24 bits).
+__device__ __forceinline__ void split_bf16x8(const float* v, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
+  f32x8 a, b, c;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = v[j];
+  hi = to_bf16x8(a);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) b[j] = v[j] - float(hi[j]);
+  mid = to_bf16x8(b);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) c[j] = b[j] - float(mid[j]);
+  lo = to_bf16x8(c);
+}
+
+// One 32 x 32 tile of sum_r A[m][r] B[n][r] over the 64 rows of the chunk,
+// from feature-major LDS tiles (operands: 8 consecutive rows per lane); the
+// B tile is split hi + mid + lo.
+__device__ __forceinline__ f32x16 rows_product(f32x16 acc, const __bf16 (*a)[kTs], const __bf16 (*bh)[kTs],
+                                               const __bf16 (*bm)[kTs], const __bf16 (*bl)[kTs], int ma, int nb,
+                                               int lane) {
+  const int r0 = (lane >> 5) * 8, la = lane & 31;
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    const bf16x8 av = *reinterpret_cast<const bf16x8*>(&a[ma + la][kb * 16 + r0]);
+    const bf16x8 hv = *reinterpret_cast<const bf16x8*>(&bh[nb + la][kb * 16 + r0]);
+    const bf16x8 mv = *reinterpret_cast<const bf16x8*>(&bm[nb + la][kb * 16 + r0]);
+    const bf16x8 lv = *reinterpret_cast<const bf16x8*>(&bl[nb + la][kb * 16 + r0]);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, hv, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, mv, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, lv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// ReLU'd bfloat16 activations of two accumulator tiles (as activate()), stored
+// feature-major for chunk row sl; also returned as the next layer's B operands.
+__device__ __forceinline__ void activate_to_lds(const f32x16 acc[2], bf16x8 hb[4], __bf16 (*dst)[kTs], int h,
+                                                int sl) {
+  activate(acc, hb, nullptr);
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dst[chained_k(kb, h, j)][sl] = hb[kb][j];
+}
 
 __global__ void __launch_bounds__(128)
 k_mlp_train(const char* __restrict__ pk, const float* __restrict__ p, const float* __restrict__ x,
@@ -474,107 +360,190 @@ k_mlp_train(const char* __restrict__ pk, const float* __restrict__ p, const floa
             double* __restrict__ loss_part) {
   __shared__ TrainLds s;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, h = lane >> 5;
-  const int col = tid & 63, half = tid >> 6;  // owner indices of the backward
   const lbm_mlp_norm* nm = reinterpret_cast<const lbm_mlp_norm*>(pk + kPkNorm);
-  MlpA w;
-  load_mlp(pk, lane, w);
-  // bfloat16 copies of the weights the backward multiplies by
-  float w2row[64], w3row[4];
+  const float* b1 = reinterpret_cast<const float*>(pk + kPkB1);
+  const float* b2 = reinterpret_cast<const float*>(pk + kPkB2);
+  const float* b3 = reinterpret_cast<const float*>(pk + kPkB3);
+  const bf16x8* pa1 = reinterpret_cast<const bf16x8*>(pk + kPkA1);
+  const bf16x8* pa2 = reinterpret_cast<const bf16x8*>(pk + kPkA2);
+  const bf16x8* pa3 = reinterpret_cast<const bf16x8*>(pk + kPkA3);
+  // A operands of d1^T = W2 d2^T: row i = ot*32 + lane%32 of W2, contraction
+  // index j in the chained order of the accumulator layout
+  for (int e = tid; e < 2 * 4 * 64; e += 128) {
+    const int ot = e / 256, kb = (e / 64) % 4, l = e % 64;
+    bf16x8 v;
 #pragma unroll
-  for (int j = 0; j < 64; ++j) w2row[j] = bf16_round(p[LBM_MLP_OFF_W2 + col * 64 + j]);
+    for (int j = 0; j < 8; ++j)
+      v[j] = __bf16(p[LBM_MLP_OFF_W2 + (ot * 32 + (l & 31)) * 64 + chained_k(kb, l >> 5, j)]);
+    s.a2b[ot][kb][l] = v;
+  }
+  for (int e = tid; e < 256; e += 128) s.w3[e] = bf16_round(p[LBM_MLP_OFF_W3 + e]);
+  // gradient accumulators: wave wid owns rows [32 wid, 32 wid + 32) of G1 and
+  // G2 (two 32 x 32 tiles each, columns 0..31 and 32..63); thread tid owns two
+  // entries of G3 and one bias entry of b1 (tid >= 64) or b2 (tid < 64)
+  f32x16 g1[2], g2[2];
 #pragma unroll
-  for (int o = 0; o < 4; ++o) w3row[o] = bf16_round(p[LBM_MLP_OFF_W3 + col * 4 + o]);
-  float g1[32], g2[32], g3[2];
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-  for (int k = 0; k < 32; ++k) g1[k] = g2[k] = 0.0f;
-  g3[0] = g3[1] = 0.0f;
-  float gb1 = 0.0f, gb2 = 0.0f, gb3 = 0.0f;
+    for (int e = 0; e < 16; ++e) g1[c][e] = g2[c][e] = 0.0f;
+  float g3a = 0.0f, g3b = 0.0f, gb = 0.0f, gb3 = 0.0f;
   double loss = 0.0;
   const float inv = 2.0f / (float(batch) * 4.0f);
   const int chunks = (batch + kTrainChunk - 1) / kTrainChunk;
+  const int sl = wid * 32 + (lane & 31);           // chunk row of this lane
   for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
-    // forward: wave wid takes rows c*64 + wid*32 + (lane % 32)
+    const int b = c * kTrainChunk + sl;
+    const bool valid = b < batch;
+    // forward (the operations of mlp_wave), activations to LDS
     {
-      const int sl = wid * 32 + (lane & 31);
-      const int b = c * kTrainChunk + sl;
-      const bool valid = b < batch;
       const int64_t row = idx[valid ? b : batch - 1];
       bf16x8 zb[4];
-      float zf[32], h1[32], h2[32];
+      float zf[32];
       bool o;
       row_operands(x, row, nm, h, zb, &o, zf);
-      const f32x4 y = mlp_wave(w, zb, reinterpret_cast<const float*>(pk + kPkB1), lane, h1, h2);
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          s.z[sl][kb * 16 + h * 8 + j] = zf[kb * 8 + j];
-          s.h1[sl][chained_k(kb, h, j)] = h1[kb * 8 + j];
-          s.h2[sl][chained_k(kb, h, j)] = h2[kb * 8 + j];
-        }
+        for (int j = 0; j < 8; ++j) s.z[kb * 16 + h * 8 + j][sl] = zb[kb][j];
+      f32x16 acc[2];
+      bf16x8 hb[4];
+#pragma unroll
+      for (int ot = 0; ot < 2; ++ot) {
+        acc[ot] = bias_tile(b1, ot, h);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+          acc[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pa1[(ot * 4 + kb) * 64 + lane], zb[kb], acc[ot], 0, 0, 0);
+      }
+      activate_to_lds(acc, hb, s.h1, h, sl);
+#pragma unroll
+      for (int ot = 0; ot < 2; ++ot) {
+        acc[ot] = bias_tile(b2, ot, h);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+          acc[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pa2[(ot * 4 + kb) * 64 + lane], hb[kb], acc[ot], 0, 0, 0);
+      }
+      activate_to_lds(acc, hb, s.h2, h, sl);
+      f32x16 out;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) out[i] = 0.0f;
+      if (h == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = b3[i];
+      }
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+        out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pa3[kb * 64 + lane], hb[kb], out, 0, 0, 0);
       if (h == 0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float r = y[q] - t[row * 4 + q] / nm->out_scale[q];
-          s.d3[sl][q] = valid ? inv * r : 0.0f;
+          const float r = out[q] - t[row * 4 + q] / nm->out_scale[q];
+          s.d3[q][sl] = valid ? inv * r : 0.0f;
           if (valid) loss += double(r) * double(r);
         }
       }
     }
     __syncthreads();
-    // d2[s][j] = (W3 d3)_j [h2 > 0]: thread (col = j, half) takes 32 rows
-    for (int r = half * 32; r < half * 32 + 32; ++r) {
-      const float a = w3row[0] * s.d3[r][0] + w3row[1] * s.d3[r][1] + w3row[2] * s.d3[r][2] + w3row[3] * s.d3[r][3];
-      s.d2[r][col] = s.h2[r][col] > 0.0f ? a : 0.0f;
+    // d2 in the accumulator layout of h2 (element kb*8 + j: hidden
+    // chained_k(kb, h, j)), then d1^T = W2 d2^T on the matrix cores
+    {
+      float d3v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d3v[q] = s.d3[q][sl];
+      bf16x8 dh[4], dm[4], dl[4];
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        float d2[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int ck = chained_k(kb, h, j);
+          const float* w3 = &s.w3[ck * 4];
+          const float a = w3[0] * d3v[0] + w3[1] * d3v[1] + w3[2] * d3v[2] + w3[3] * d3v[3];
+          d2[j] = float(s.h2[ck][sl]) > 0.0f ? a : 0.0f;
+        }
+        split_bf16x8(d2, dh[kb], dm[kb], dl[kb]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int ck = chained_k(kb, h, j);
+          s.d2h[ck][sl] = dh[kb][j];
+          s.d2m[ck][sl] = dm[kb][j];
+          s.d2l[ck][sl] = dl[kb][j];
+        }
+      }
+#pragma unroll
+      for (int ot = 0; ot < 2; ++ot) {
+        f32x16 acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          const bf16x8 a = s.a2b[ot][kb][lane];
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, dh[kb], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, dm[kb], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, dl[kb], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          float d1[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int hid = ot * 32 + acc_row(half * 8 + j, h);
+            d1[j] = float(s.h1[hid][sl]) > 0.0f ? acc[half * 8 + j] : 0.0f;
+          }
+          bf16x8 hi, mi, lo;
+          split_bf16x8(d1, hi, mi, lo);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int hid = ot * 32 + acc_row(half * 8 + j, h);
+            s.d1h[hid][sl] = hi[j];
+            s.d1m[hid][sl] = mi[j];
+            s.d1l[hid][sl] = lo[j];
+          }
+        }
+      }
     }
     __syncthreads();
-    // d1[s][i] = (W2 d2)_i [h1 > 0]: thread (col = i, half)
-    for (int r = half * 32; r < half * 32 + 32; ++r) {
-      float a = 0.0f;
+    // weight gradients over the chunk's rows
 #pragma unroll
-      for (int j = 0; j < 64; ++j) a += w2row[j] * s.d2[r][j];
-      s.d1[r][col] = s.h1[r][col] > 0.0f ? a : 0.0f;
+    for (int cn = 0; cn < 2; ++cn) {
+      g2[cn] = rows_product(g2[cn], s.h1, s.d2h, s.d2m, s.d2l, wid * 32, cn * 32, lane);
+      g1[cn] = rows_product(g1[cn], s.z, s.d1h, s.d1m, s.d1l, wid * 32, cn * 32, lane);
     }
-    __syncthreads();
-    // gradients: g1[k][i] += z d1, g2[i][j] += h1 d2, g3[j][o] += h2 d3
-    for (int r = 0; r < kTrainChunk; ++r) {
-      const float d1v = s.d1[r][col], d2v = s.d2[r][col];
-#pragma unroll
-      for (int k = 0; k < 32; ++k) {
-        g1[k] += s.z[r][half * 32 + k] * d1v;
-        g2[k] += s.h1[r][half * 32 + k] * d2v;
+    {
+      // G3[j][o] for j = tid / 2, o = 2 (tid % 2) + {0, 1}; bias of d1 or d2
+      const int j = tid >> 1, o = (tid & 1) * 2, bh = tid & 63;
+      const __bf16(*dh)[kTs] = tid < 64 ? s.d2h : s.d1h;
+      const __bf16(*dm)[kTs] = tid < 64 ? s.d2m : s.d1m;
+      const __bf16(*dl)[kTs] = tid < 64 ? s.d2l : s.d1l;
+      for (int r = 0; r < kTrainChunk; ++r) {
+        const float hv = float(s.h2[j][r]);
+        g3a += hv * s.d3[o][r];
+        g3b += hv * s.d3[o + 1][r];
+        gb += (float(dh[bh][r]) + float(dm[bh][r])) + float(dl[bh][r]);
       }
-      const float h2v = s.h2[r][col];
-      g3[0] += h2v * s.d3[r][half * 2];
-      g3[1] += h2v * s.d3[r][half * 2 + 1];
-      if (half == 0) {
-        gb1 += d1v;
-        gb2 += d2v;
-        if (col < 4) gb3 += s.d3[r][col];
-      }
+      if (tid < 4)
+        for (int r = 0; r < kTrainChunk; ++r) gb3 += s.d3[tid][r];
     }
     __syncthreads();
   }
   float* out = partial + (int64_t)blockIdx.x * kGradStride;
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
-    out[LBM_MLP_OFF_W1 + (half * 32 + k) * 64 + col] = g1[k];
-    out[LBM_MLP_OFF_W2 + (half * 32 + k) * 64 + col] = g2[k];
-  }
-  out[LBM_MLP_OFF_W3 + col * 4 + half * 2] = g3[0];
-  out[LBM_MLP_OFF_W3 + col * 4 + half * 2 + 1] = g3[1];
-  if (half == 0) {
-    out[LBM_MLP_OFF_B1 + col] = gb1;
-    out[LBM_MLP_OFF_B2 + col] = gb2;
-    if (col < 4) out[LBM_MLP_OFF_B3 + col] = gb3;
-  }
-  // loss: fixed-order sum over the 64 lanes that hold outputs
-  __shared__ double lred[128];
-  lred[tid] = loss;
+  for (int cn = 0; cn < 2; ++cn)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int m = wid * 32 + acc_row(e, h), n = cn * 32 + (lane & 31);
+      out[LBM_MLP_OFF_W1 + m * 64 + n] = g1[cn][e];
+      out[LBM_MLP_OFF_W2 + m * 64 + n] = g2[cn][e];
+    }
+  out[LBM_MLP_OFF_W3 + (tid >> 1) * 4 + (tid & 1) * 2] = g3a;
+  out[LBM_MLP_OFF_W3 + (tid >> 1) * 4 + (tid & 1) * 2 + 1] = g3b;
+  out[(tid < 64 ? LBM_MLP_OFF_B2 : LBM_MLP_OFF_B1) + (tid & 63)] = gb;
+  if (tid < 4) out[LBM_MLP_OFF_B3 + tid] = gb3;
+  // loss: fixed-order sum over the lanes that hold outputs
+  s.loss[tid] = loss;
   __syncthreads();
   if (tid == 0) {
     double a = 0.0;
-    for (int k = 0; k < 128; ++k) a += lred[k];
+    for (int k = 0; k < 128; ++k) a += s.loss[k];
     loss_part[blockIdx.x] = a;
   }
 }
