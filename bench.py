@@ -402,13 +402,15 @@ def learned_study(args, dev, stream) -> int:
     DNS 4096^2 (FP32) of the jet at nu_DNS = F nu_LES (constant Reynolds
     number), Gaussian filter of width 4 F fine cells, subsampled every F-th
     cell to (4096 / F)^2 (Delta = 4 LES cells).  The network is trained on two seeds with the
-    library's kernels; on a held-out seed the LES (analytic closure with FP32
-    and FP16 storage, analytic plus learned correction with FP32, FP16 and
-    BF16 storage, and with the network evaluated every --corr-every steps)
-    starts from the filtered DNS initial state and runs alongside the DNS.  Reported: the relative L2 error of the total-energy spectrum
-    E_K + E_M over the bins 1 .. N_LES/4 against the filtered DNS at several
-    times, the growth rate of the streamwise k_x = 3 mode, a-priori subgrid
-    errors, and wall-clock throughput of each run.  One JSON line on stdout.
+    library's kernels; on a held-out seed the LES (no closure, analytic
+    closure and analytic plus learned correction, each with FP32 and FP16
+    storage; learned with BF16 storage; learned with the network every
+    --corr-every steps) starts from the filtered DNS initial state and runs
+    alongside the DNS.  Reported: the relative L2 error of the total-energy
+    spectrum E_K + E_M against the filtered DNS over the bins 1 .. N_LES/4 and
+    over the small-scale band N_LES/16 < k <= N_LES/4, at several times, the
+    growth rate of the streamwise k_x = 3 mode, a-priori subgrid errors, and
+    wall-clock throughput of each run.  One JSON line on stdout.
     """
     import math
 
@@ -419,16 +421,19 @@ def learned_study(args, dev, stream) -> int:
     from paper_1705_09807_amd import learned as G
     from paper_1705_09807_amd import training as TR
 
-    # nu = 1e-3, eta = 1e-2 on the LES grid (x4 for the DNS).  With the
-    # single-relaxation-time magnetic distribution, runs at eta <= 3e-3
-    # (s_m >= 1.96) overflow at roll-up on both grids (div B grows first);
-    # eta = 1e-2 keeps them finite.
+    # nu = 1e-4, eta = 1e-2 on the LES grid (x4 for the DNS), shear layers
+    # of thickness L/100 with modes at 2 % of U0: a jet whose small scales
+    # the LES without closure gets wrong by ~20 % in the band N/16 < k <= N/4
+    # while the analytic closure stays near 1 %.  With the single-relaxation-
+    # time magnetic distribution, runs at eta <= 3e-3 (s_m >= 1.96) overflow
+    # at roll-up on both grids (div B grows first); eta = 1e-2 keeps them
+    # finite.
     setup = TR.JetSetup(n_fine=4096, factor=args.study_factor, delta_fine=4.0 * args.study_factor,
                         nu_les=args.study_nu, eta_les=args.study_eta,
                         ghost=GHOST,
                         U0=KH["U0"],
-                        delta_over_L=KH["delta_over_L"], B0=KH["B0"], noise_amp=1e-4,
-                        modes=(2, 3, 4, 5, 6), mode_amp=0.01)
+                        delta_over_L=args.study_delta_over_l, B0=KH["B0"], noise_amp=1e-4,
+                        modes=(2, 3, 4, 5, 6), mode_amp=args.study_mode_amp)
     T_END = args.learned_study
     train_times = [T_END * k // 6 for k in range(1, 7)]
     t0 = time.perf_counter()
@@ -452,17 +457,22 @@ def learned_study(args, dev, stream) -> int:
     dns = TR.dns(setup, seed)
     c0 = TR.filtered(setup, dns)
     K = args.corr_every
-    runs = {"analytic_fp32": ("analytic", "fp32", 1), "learned_fp32": ("learned", "fp32", 1),
-            "learned_fp16": ("learned", "fp16", 1), "learned_bf16": ("learned", "bf16", 1),
-            "analytic_fp16": ("analytic", "fp16", 1)}
+    # no closure (Delta = 0: the filtered initial state run as a DNS of the
+    # coarse grid), the analytic closure and the analytic plus learned closure
+    runs = {"noclosure_fp32": ("none", "fp32", 1), "analytic_fp32": ("analytic", "fp32", 1),
+            "learned_fp32": ("learned", "fp32", 1), "noclosure_fp16": ("none", "fp16", 1),
+            "analytic_fp16": ("analytic", "fp16", 1), "learned_fp16": ("learned", "fp16", 1),
+            "learned_bf16": ("learned", "bf16", 1)}
     if K > 1:
         runs[f"learned_fp32_every{K}"] = ("learned", "fp32", K)
         runs[f"learned_fp16_every{K}"] = ("learned", "fp16", K)
     les = {}
     for name, (closure, dt, every_k) in runs.items():
         g = setup.ghost
-        s = Sim(nx=setup.n_les, ny=setup.n_les, nu=setup.nu_les, eta=setup.eta, delta=setup.delta_les,
-                s5=g, s6=g, s7=g, s8=g, dtype=dt, b_ref=(setup.B0, 0.0), closure=closure, device=dev, stream=stream)
+        s = Sim(nx=setup.n_les, ny=setup.n_les, nu=setup.nu_les, eta=setup.eta,
+                delta=0.0 if closure == "none" else setup.delta_les, s5=g, s6=g, s7=g, s8=g, dtype=dt,
+                b_ref=(setup.B0, 0.0), closure="analytic" if closure == "none" else closure, device=dev,
+                stream=stream)
         s.init_from_moments(c0[:5].contiguous())
         if closure == "learned":
             s.set_closure_mlp(mlp.pack())
@@ -475,6 +485,8 @@ def learned_study(args, dev, stream) -> int:
         series[name] = []
     spec_err = {name: [] for name in runs}
     spec_bin = {name: [] for name in runs}      # mean per-bin |E_les / E_fdns - 1| over bins above 1e-10 of the total
+    spec_band = {name: [] for name in runs}     # relative L2 over the small-scale band N/16 < k <= N/4
+    k_band = setup.n_les // 16
     spectra_at = {"fdns": {}}
     for name in runs:
         spectra_at[name] = {}
@@ -497,6 +509,8 @@ def learned_study(args, dev, stream) -> int:
                 spec_err[name].append((t, (torch.linalg.norm(e_l - e_f) / torch.linalg.norm(e_f)).item()))
                 keep = e_f > 1e-10 * e_f.sum()
                 spec_bin[name].append((t, (e_l[keep] / e_f[keep] - 1.0).abs().mean().item()))
+                spec_band[name].append((t, (torch.linalg.norm(e_l[k_band:] - e_f[k_band:])
+                                            / torch.linalg.norm(e_f[k_band:])).item()))
                 spectra_at[name][t] = e_l.tolist()
                 spectra_at["fdns"][t] = e_f.tolist()
         if t > 0 and t % (T_END // 8) == 0:
@@ -544,6 +558,7 @@ def learned_study(args, dev, stream) -> int:
         res[name] = {
             "spectrum_rel_l2": [(tt, round(e, 6)) for tt, e in spec_err[name]],
             "spectrum_mean_bin_rel_err": [(tt, round(e, 6)) for tt, e in spec_bin[name]],
+            "spectrum_band_rel_l2": [(tt, round(e, 6)) for tt, e in spec_band[name]],
             "growth_rate": g_l,
             "growth_rate_rel_err": (None if g_l is None or not g_f else round(g_l / g_f - 1.0, 5)),
             "finite": finite[name],
@@ -560,6 +575,7 @@ def learned_study(args, dev, stream) -> int:
                   "loss_first": losses[0].item(), "loss_last200": losses[-200:].mean().item()},
         "held_out_seed": seed,
         "spectrum_bins": [1, n_cmp],
+        "spectrum_band_bins": [k_band + 1, n_cmp],
         "growth_rate_fdns": g_f,
         "dns_fine_mlups": round(setup.n_fine ** 2 * setup.factor * T_END / (wall["dns"] * 1e-3) / 1e6, 1),
         "apriori_mse_ratio_learned_over_analytic": [(tt, round(r, 4), round(o, 5)) for tt, r, o in apriori],
@@ -612,8 +628,12 @@ def main() -> int:
     ap.add_argument("--jet-variant", default="default", choices=["default", "paper"],
                     help="paper: D2Q9 magnetic distribution and the density-gradient closure")
     ap.add_argument("--train-steps", type=int, default=4000)
-    ap.add_argument("--study-nu", type=float, default=1e-3, help="LES-grid viscosity of the study")
+    ap.add_argument("--study-nu", type=float, default=1e-4, help="LES-grid viscosity of the study")
     ap.add_argument("--study-eta", type=float, default=1e-2, help="LES-grid resistivity of the study")
+    ap.add_argument("--study-delta-over-l", type=float, default=1.0 / 100.0,
+                    help="shear-layer thickness of the learned-closure study's jet, in units of L")
+    ap.add_argument("--study-mode-amp", type=float, default=0.02,
+                    help="amplitude of each streamwise mode of the study's jet, in units of U0")
     ap.add_argument("--study-factor", type=int, default=4, choices=[2, 4, 8],
                     help="coarsening of the learned-closure study (LES grid 4096 / factor)")
     ap.add_argument("--out-dir", default="", help="folder for the jet study's per-snapshot spectra")
