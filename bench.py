@@ -395,6 +395,54 @@ def jet_study(args, dev, stream) -> int:
     return 0
 
 
+def _study_setup(args):
+    """The learned-closure study's jet and grids (training.JetSetup)."""
+    from paper_1705_09807_amd import training as TR
+
+    # nu = 1e-4, eta = 1e-2 on the LES grid (x4 for the DNS), shear layers
+    # of thickness L/100 with modes at 2 % of U0: a jet whose small scales
+    # the LES without closure gets wrong by ~20 % in the band N/16 < k <= N/4
+    # while the analytic closure stays near 1 %.  With the single-relaxation-
+    # time magnetic distribution, runs at eta <= 3e-3 (s_m >= 1.96) overflow
+    # at roll-up on both grids (div B grows first); eta = 1e-2 keeps them
+    # finite.
+    return TR.JetSetup(n_fine=4096, factor=args.study_factor, delta_fine=4.0 * args.study_factor,
+                       nu_les=args.study_nu, eta_les=args.study_eta,
+                       ghost=GHOST,
+                       U0=KH["U0"],
+                       delta_over_L=args.study_delta_over_l, B0=KH["B0"], noise_amp=1e-4,
+                       modes=(2, 3, 4, 5, 6), mode_amp=args.study_mode_amp)
+
+
+def _train_study_network(args, setup, t_end: int, dev, stream):
+    """Train the network on filtered DNS of seeds 1 and 2 at six LES times up
+    to t_end, with the library's kernels.  Returns (mlp, times, losses), or
+    (None, ...) when the DNS overflowed."""
+    import torch
+
+    from paper_1705_09807_amd import learned as G
+    from paper_1705_09807_amd import training as TR
+
+    train_times = [t_end * k // 6 for k in range(1, 7)]
+    t0 = time.perf_counter()
+    X, T = TR.samples(setup, seeds=[1, 2], les_times=train_times,
+                      progress=lambda sd, tt: log(f"samples: seed {sd} LES time {tt} ({time.perf_counter() - t0:.0f} s)"))
+    log(f"samples {tuple(X.shape)} in {time.perf_counter() - t0:.1f} s")
+    if not (bool(torch.isfinite(X).all()) and bool(torch.isfinite(T).all())):
+        log("training samples are not finite: the DNS overflowed")
+        return None, train_times, None
+    mlp = G.Mlp(G.glorot_params(0), device=dev, stream=stream)
+    mlp.fit_norm(X, T)
+    t1 = time.perf_counter()
+    losses = TR.train(mlp, X, T, steps=args.train_steps, batch=8192, lr=2e-3)
+    torch.cuda.synchronize(dev)
+    log(f"trained {args.train_steps} steps in {time.perf_counter() - t1:.1f} s: loss {losses[0].item():.3e} -> "
+        f"{losses[-200:].mean().item():.3e}")
+    del X, T
+    torch.cuda.empty_cache()
+    return mlp, train_times, losses
+
+
 def learned_study(args, dev, stream) -> int:
     """A-posteriori test of the learned closure (filtered DNS -> F x coarser
     LES, F = --study-factor, 4 by default).
@@ -421,37 +469,11 @@ def learned_study(args, dev, stream) -> int:
     from paper_1705_09807_amd import learned as G
     from paper_1705_09807_amd import training as TR
 
-    # nu = 1e-4, eta = 1e-2 on the LES grid (x4 for the DNS), shear layers
-    # of thickness L/100 with modes at 2 % of U0: a jet whose small scales
-    # the LES without closure gets wrong by ~20 % in the band N/16 < k <= N/4
-    # while the analytic closure stays near 1 %.  With the single-relaxation-
-    # time magnetic distribution, runs at eta <= 3e-3 (s_m >= 1.96) overflow
-    # at roll-up on both grids (div B grows first); eta = 1e-2 keeps them
-    # finite.
-    setup = TR.JetSetup(n_fine=4096, factor=args.study_factor, delta_fine=4.0 * args.study_factor,
-                        nu_les=args.study_nu, eta_les=args.study_eta,
-                        ghost=GHOST,
-                        U0=KH["U0"],
-                        delta_over_L=args.study_delta_over_l, B0=KH["B0"], noise_amp=1e-4,
-                        modes=(2, 3, 4, 5, 6), mode_amp=args.study_mode_amp)
+    setup = _study_setup(args)
     T_END = args.learned_study
-    train_times = [T_END * k // 6 for k in range(1, 7)]
-    t0 = time.perf_counter()
-    X, T = TR.samples(setup, seeds=[1, 2], les_times=train_times,
-                      progress=lambda sd, tt: log(f"samples: seed {sd} LES time {tt} ({time.perf_counter() - t0:.0f} s)"))
-    log(f"samples {tuple(X.shape)} in {time.perf_counter() - t0:.1f} s")
-    if not (bool(torch.isfinite(X).all()) and bool(torch.isfinite(T).all())):
-        log("training samples are not finite: the DNS overflowed")
+    mlp, train_times, losses = _train_study_network(args, setup, T_END, dev, stream)
+    if mlp is None:
         return 1
-    mlp = G.Mlp(G.glorot_params(0), device=dev, stream=stream)
-    mlp.fit_norm(X, T)
-    t1 = time.perf_counter()
-    losses = TR.train(mlp, X, T, steps=args.train_steps, batch=8192, lr=2e-3)
-    torch.cuda.synchronize(dev)
-    log(f"trained {args.train_steps} steps in {time.perf_counter() - t1:.1f} s: loss {losses[0].item():.3e} -> "
-        f"{losses[-200:].mean().item():.3e}")
-    del X, T
-    torch.cuda.empty_cache()
 
     seed = 3
     dns = TR.dns(setup, seed)
@@ -587,6 +609,126 @@ def learned_study(args, dev, stream) -> int:
     return 0
 
 
+def production_run(args, dev, stream) -> int:
+    """The production configuration run: a 16384^2 jet (268 M cells) with the
+    learned closure and FP16 population storage, nu = eta = 5e-5, Delta = 4,
+    B = (B0, 0) with B0 = --production-b0, for --production-run steps;
+    diagnostics (energies, enstrophy, integral J_z^2, div B) and the radially
+    binned kinetic and magnetic spectra with the streamwise spectrum E_x(m)
+    every --production-every steps.
+
+    The jet is the learned-closure study's (shear layers U0 = 0.05 of
+    thickness L/100, modes 2-6 at 2 % of U0 with seeded phases, noise 1e-4),
+    and so is the network: trained first, with the library's kernels, on
+    filtered DNS of that jet at the same B0 (4096^2 -> 1024^2; no filtered
+    DNS of the 16384^2 jet fits one GPU).  Each snapshot also records the
+    share of cells whose inputs lie outside the training range (the analytic
+    closure alone there) and the RMS of the four correction planes.  FP16 is the 16-bit storage that keeps the
+    growth rate within 2 % of the filtered DNS in that study; BF16 misses it
+    by 20-33 %.  Reported: the series, fitted growth rates of E_x(m), m = 1..8
+    (over the snapshots where E_x(m) lies between 1e-3 and 1e-1 of its
+    largest value, else over all snapshots before that value), and the step
+    time; with --out-dir the spectra go to
+    <out-dir>/production_spectra_B0_<B0>.npz.  One JSON line on stdout.
+    """
+    import numpy as np
+    import torch
+
+    from paper_1705_09807_amd import Sim
+    from paper_1705_09807_amd import learned as G
+    from paper_1705_09807_amd import training as TR
+
+    n, b0, T, every = 16384, args.production_b0, args.production_run, args.production_every
+    # the study's jet with this run's field: the network is trained at the
+    # same B0 (its normalised inputs would otherwise all lie outside the
+    # training range)
+    prod = TR.JetSetup(**{**_study_setup(args).__dict__, "B0": b0})
+    mlp, _, losses = _train_study_network(args, prod, 8000, dev, stream)
+    if mlp is None:
+        return 1
+    packed = mlp.pack()
+    t0 = time.perf_counter()
+    mom0 = TR.jet_fields(prod, n, seed=3, device=dev)
+    log(f"initial fields in {time.perf_counter() - t0:.1f} s")
+    sim = Sim(nx=n, ny=n, nu=5e-5, eta=5e-5, delta=LES_DELTA, dtype="fp16", schedule="fused",
+              b_ref=(b0, 0.0), closure="learned", device=dev, stream=stream,
+              s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
+    sim.init_from_moments(mom0)
+    del mom0
+    torch.cuda.empty_cache()
+    sim.set_closure_mlp(packed)
+    mom = torch.empty((5, n, n), dtype=torch.float64, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    corr = torch.empty((4, n, n), dtype=torch.float32, device=dev)
+    series = {"t": [], "e_kin": [], "e_mag": [], "enstrophy": [], "j2": [], "divb_max": [], "nonfinite": [],
+              "ex_m0_to_8": [], "out_of_range_share": [], "correction_rms": []}
+    spectra_k, spectra_m, step_ms, spec_ms = [], [], 0.0, 0.0
+    t_wall = time.perf_counter()
+    while True:
+        ev0.record(stream)
+        sim.moments(mom)
+        ek, em, ekx = G.spectra(mom, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize(dev)
+        spec_ms += ev0.elapsed_time(ev1)
+        d = sim.diagnostics()
+        series["t"].append(sim.t)
+        for k in ("e_kin", "e_mag", "enstrophy", "j2", "divb_max", "nonfinite"):
+            series[k].append(d[k])
+        series["ex_m0_to_8"].append(ekx[:9].tolist())
+        # share of cells left to the analytic closure, and the correction's size
+        sim.closure_correction(corr)
+        torch.cuda.synchronize(dev)
+        series["out_of_range_share"].append((corr == 0).all(dim=0).float().mean().item())
+        series["correction_rms"].append([torch.linalg.vector_norm(corr[i], dtype=torch.float64).item() / n
+                                         for i in range(4)])
+        spectra_k.append(ek.float().cpu().numpy())
+        spectra_m.append(em.float().cpu().numpy())
+        log(f"production B0={b0}: t = {sim.t} e_kin {d['e_kin']:.6e} e_mag {d['e_mag']:.6e} "
+            f"E_x(3) {ekx[3].item():.3e} divB_max {d['divb_max']:.2e} nonfinite {d['nonfinite']} "
+            f"out of range {series['out_of_range_share'][-1]:.3%} "
+            f"({time.perf_counter() - t_wall:.0f} s)")
+        if d["nonfinite"] or sim.t >= T:
+            break
+        ev0.record(stream)
+        sim.step(min(every, T - sim.t))
+        ev1.record(stream)
+        torch.cuda.synchronize(dev)
+        step_ms += ev0.elapsed_time(ev1)
+    tt = np.asarray(series["t"], dtype=np.float64)
+    ex = np.asarray(series["ex_m0_to_8"])
+    rates = {}
+    for m in range(1, 9):
+        v = ex[:, m]
+        peak = int(np.argmax(v))
+        sel = (v > 1e-3 * v[peak]) & (v < 1e-1 * v[peak]) & (np.arange(len(v)) <= peak)
+        if sel.sum() < 3:
+            sel = np.arange(len(v)) <= peak
+        rates[m] = (float(0.5 * np.polyfit(tt[sel], np.log(v[sel]), 1)[0]) if sel.sum() >= 2 and (v[sel] > 0).all()
+                    else None)
+    steps_done = int(series["t"][-1])
+    out = {
+        "study": "production configuration: 16384^2 jet, learned closure, FP16 storage",
+        "grid": n, "nu": 5e-5, "eta": 5e-5, "Delta": LES_DELTA, "B0": b0, "steps": steps_done,
+        "jet": prod.kh(3) | {"modes": list(prod.modes), "mode_amp_over_U0": prod.mode_amp},
+        "network": {"trained_on": "filtered DNS 4096^2 -> 1024^2 of the same jet (same B0), seeds 1 and 2",
+                    "loss_first": losses[0].item(), "loss_last200": losses[-200:].mean().item()},
+        "finite": series["nonfinite"][-1] == 0,
+        "step_ms": round(step_ms / max(steps_done, 1), 4),
+        "mlups": round(n * n * steps_done / max(step_ms, 1e-9) / 1e3, 1),
+        "spectra_ms_each": round(spec_ms / len(series["t"]), 2),
+        "growth_rate_ex_m": rates,
+        "series": series,
+    }
+    if args.out_dir:
+        os.makedirs(args.out_dir, exist_ok=True)
+        np.savez_compressed(os.path.join(args.out_dir, f"production_spectra_B0_{b0:g}.npz"), t=tt,
+                            e_kin=np.stack(spectra_k), e_mag=np.stack(spectra_m))
+    sim.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -627,6 +769,12 @@ def main() -> int:
     ap.add_argument("--jet-dtype", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--jet-variant", default="default", choices=["default", "paper"],
                     help="paper: D2Q9 magnetic distribution and the density-gradient closure")
+    ap.add_argument("--production-run", type=int, default=0, metavar="STEPS",
+                    help="run the production configuration (16384^2, learned closure, FP16 storage) for STEPS "
+                         "steps at B0 = --production-b0 and report its series; nothing else is run")
+    ap.add_argument("--production-b0", type=float, default=0.02)
+    ap.add_argument("--production-every", type=int, default=1000,
+                    help="production run: spectra and diagnostics every this many steps")
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--study-nu", type=float, default=1e-4, help="LES-grid viscosity of the study")
     ap.add_argument("--study-eta", type=float, default=1e-2, help="LES-grid resistivity of the study")
@@ -652,7 +800,7 @@ def main() -> int:
 
     # the CPU legs run first, before anything touches the GPU (their worker
     # processes start from a clean parent)
-    study = args.precision_study > 0 or args.learned_study > 0 or args.jet_study > 0
+    study = args.precision_study > 0 or args.learned_study > 0 or args.jet_study > 0 or args.production_run > 0
     cpu = None
     variant_rates = {}
     if not args.no_cpu_baseline and not study:
@@ -673,6 +821,8 @@ def main() -> int:
         return precision_study(args.precision_study, dev, stream)
     if args.learned_study > 0:
         return learned_study(args, dev, stream)
+    if args.production_run > 0:
+        return production_run(args, dev, stream)
     if args.jet_study > 0:
         return jet_study(args, dev, stream)
 
@@ -869,8 +1019,8 @@ def main() -> int:
                 "correction_every": every, "steps": nsteps,
                 "note": "fine-equivalent: a 4x coarser grid (16x fewer cells) and 4x longer steps "
                         "than the 4096^2 DNS it stands for",
-                "kernels": ("k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<..., CORR>" if every == 1
-                            else f"k_moments5f_row + k_mlp_correct every {every} steps, "
+                "kernels": ("k_cell_inputs + k_mlp_correct (bf16 MFMA) + k_fused_les<..., CORR>" if every == 1
+                            else f"k_cell_inputs + k_mlp_correct every {every} steps, "
                                  "k_fused_les<..., CORR> every step")}
             log(f"learned les 1024^2 {dt} (network every {every}): {ms * 1e3:.1f} us/step")
             del sl
@@ -936,9 +1086,9 @@ def main() -> int:
             ms = a.elapsed_time(b) / nsteps
             rec = {"mlups": round(lups16 / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 1),
                    "steps": nsteps, "correction_every": every,
-                   "kernels": (f"k_moments5f_row + k_mlp_correct (bf16 MFMA) + k_fused_les<{dt}, ..., CORR>"
+                   "kernels": (f"k_cell_inputs + k_mlp_correct (bf16 MFMA) + k_fused_les<{dt}, ..., CORR>"
                                if every == 1 else
-                               f"k_moments5f_row + k_mlp_correct every {every} steps, "
+                               f"k_cell_inputs + k_mlp_correct every {every} steps, "
                                f"k_fused_les<{dt}, ..., CORR> every step")}
             if dt == "bf16" and every == 1:
                 mom16 = torch.empty((5, n16, n16), dtype=torch.float64, device=dev)

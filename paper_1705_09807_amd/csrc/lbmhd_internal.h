@@ -42,7 +42,7 @@ struct Launch {
   int diag_blocks = 0;
   bool learned = false;           // analytic closure plus the network's correction
   bool full = false;              // closure with the filtered-density gradient terms
-  size_t off_mom5 = 0;            // 5 FP32 moment planes (network input)
+  size_t off_cellin = 0;          // network input vectors (16 bytes per cell)
   size_t off_corr = 0;            // 4 FP32 correction planes
   size_t off_mlp = 0;             // packed network
   hipStream_t stream = nullptr;
@@ -104,7 +104,9 @@ hipError_t launch_filter(const double* mom, int nx, int ny, int factor, double d
                          hipStream_t st);
 hipError_t launch_closure_samples(const double* c12, int nx, int ny, double delta, int stencil, float* x, float* t,
                                   hipStream_t st);
-hipError_t launch_mlp_correct(const float* mom5, const void* packed, float* corr, int nx, int ny, hipStream_t st);
+// The network on per-cell input vectors (16 bytes per cell, written by the
+// first stage of launch_correction).
+hipError_t launch_mlp_correct(const void* cell_in, const void* packed, float* corr, int nx, int ny, hipStream_t st);
 int spectra_bins(int n);
 size_t spectra_work_bytes(int n);
 hipError_t launch_spectra(const double* mom, int n, double* ek, double* em, double* ekx, void* work,

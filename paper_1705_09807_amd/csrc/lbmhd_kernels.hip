@@ -37,6 +37,7 @@
 #include "lbmhd_device.h"
 #include "lbmhd_internal.h"
 #include "lbmhd_learned.h"
+#include "lbmhd_mlp_device.h"
 
 namespace lbm {
 
@@ -585,14 +586,6 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
           cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0], gr[3][1], ir,
                              r.k2);
         }
-        if constexpr (MODE == kClosureCorr) {
-          const int64_t n = (int64_t)nx * ny, ci = (int64_t)y * nx + x0 + tid;
-          const C txx = C(corr[ci]), txy = C(corr[n + ci]), tyy = C(corr[2 * n + ci]), eps = C(corr[3 * n + ci]);
-          cl.tau_xy += txy;
-          cl.tau_d += txx - tyy;
-          cl.tau_s += txx + tyy;
-          cl.eps += eps;
-        }
         collide_q<QG>(cu, m, cl, r);
         const int64_t yo = int64_t(y) * int64_t(kPop<QG>) * pitch * int64_t(sizeof(S));
 #pragma unroll
@@ -610,11 +603,27 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
       row(nn, nxt, y++);
     }
   } else {
-    // the same row body written inline, rows rotated by copies
+    // the same row body written inline, rows rotated by copies.  The learned
+    // correction of row y + 1 is loaded with row y + 2's populations (its
+    // latency measured 1.0 ms of the 6.2 ms sweep at 16384^2 BF16 when loaded
+    // at its use).
+    const int64_t n = (int64_t)nx * ny;
+    float cc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, cn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    auto load_corr = [&](int y, float (&c)[4]) __attribute__((always_inline)) {
+      const int64_t ci = (int64_t)y * nx + x0 + tid;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] = corr[k * n + ci];
+    };
+    if constexpr (MODE == kClosureCorr) {
+      if (valid) load_corr(y0, cc);
+    }
     for (int y = y0; y < y1; ++y) {
       const int s = y - y0 + 1;                 // ring slot of row y is s & 3
       const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
       if (more && loader) pull_cell<S, C, QG>(src, pitch, rows_of<S, QG>(wrapy(y + 2), ny, pitch), cx, nn);
+      if constexpr (MODE == kClosureCorr) {
+        if (more && valid) load_corr(y + 1, cn);
+      }
       if (valid) {
         const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
         C gr[NF][2];
@@ -636,8 +645,7 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
                              r.k2);
         }
         if constexpr (MODE == kClosureCorr) {
-          const int64_t n = (int64_t)nx * ny, ci = (int64_t)y * nx + x0 + tid;
-          const C txx = C(corr[ci]), txy = C(corr[n + ci]), tyy = C(corr[2 * n + ci]), eps = C(corr[3 * n + ci]);
+          const C txx = C(cc[0]), txy = C(cc[1]), tyy = C(cc[2]), eps = C(cc[3]);
           cl.tau_xy += txy;
           cl.tau_d += txx - tyy;
           cl.tau_s += txx + tyy;
@@ -654,6 +662,10 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
       for (int q = 0; q < kPop<QG>; ++q) {
         cur[q] = nxt[q];
         nxt[q] = nn[q];
+      }
+      if constexpr (MODE == kClosureCorr) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cc[k] = cn[k];
       }
     }
   }
@@ -992,28 +1004,84 @@ k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int 
   out[4 * n + c0] = ref.by0 + m.dby;
 }
 
-// rho, m_x, m_y, B_x, B_y in FP32 (5 dense planes): the network's input.
-// The five FP32 moment planes of a fused-schedule state (layout kLayoutPull):
-// the gather of the fused sweep over 256-cell row segments, one cell per
-// thread.  Measured 16-29 % faster at 8192^2 and 16384^2 with 16-bit storage
-// than a 64 x 4 tile gather with 64-bit indices (four cells per thread with
-// 8-byte loads was 6-8 % slower than one).
+// Input vectors of the learned correction (first stage; the network kernel is
+// the second).  For every cell of a fused-schedule state (layout kLayoutPull):
+// rho, m, B in FP32 from the gathered populations, u = m / rho, the central-
+// difference vorticity and current, the seven fields normalised (FP32) and
+// rounded to bfloat16, and the out-of-range flag (CellIn, 16 bytes).  Each
+// wave walks its own strip of 64 columns down a segment of kCellInRows rows,
+// independently of the other waves (no workgroup barrier): each lane gathers
+// one column per row, u_x, u_y, B_x, B_y go to the wave's four-row LDS ring,
+// and the row above the newest one is finished from the ring.  The strip's
+// outer two columns and the rows just outside the segment are gathered for
+// their neighbours only: 62 output columns per strip.  Measured at 1024^2,
+// 8192^2 and 16384^2 (FP32, BF16, FP16 storage): 3-13 % faster than 256-lane
+// strips with a workgroup barrier per row; 8-row segments within 6 % of the
+// best of 4 to 64 rows at every size.
+constexpr int kCellInW = 64, kCellInRows = 8;
+
+__host__ __device__ constexpr int cell_input_strips(int nx) { return (nx + kCellInW - 3) / (kCellInW - 2); }
+
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_moments5f_row(const S* __restrict__ src, float* __restrict__ out, int nx, int ny, int64_t pitch, RestRef ref) {
+k_cell_inputs(const S* __restrict__ src, int nx, int ny, int64_t pitch, RestRef ref, int nstrips,
+              const char* __restrict__ pk, CellIn* __restrict__ out) {
   using C = typename ComputeOf<S>::type;
-  const int x = blockIdx.x * 256 + threadIdx.x;
-  const int y = blockIdx.y;
-  if (x >= nx) return;
-  C v[kQ];
-  pull_cell<S, C, 5>(src, pitch, rows_of<S>(y, ny, pitch), cols_of<S>(x, nx), v);
-  const Mom<C> m = moments19(v);
-  const int64_t n = (int64_t)nx * ny, c0 = (int64_t)y * nx + x;
-  out[c0] = float(C(ref.rho0) + m.drho);
-  out[n + c0] = float(m.mx);
-  out[2 * n + c0] = float(m.my);
-  out[3 * n + c0] = float(C(ref.bx0) + m.dbx);
-  out[4 * n + c0] = float(C(ref.by0) + m.dby);
+  __shared__ float ring_all[4][4][4][kCellInW];  // wave, row slot, field (u_x, u_y, B_x, B_y), column
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int strip = blockIdx.x * 4 + wid;
+  if (strip >= nstrips) return;
+  float(*ring)[4][kCellInW] = ring_all[wid];
+  const int xu = strip * (kCellInW - 2) - 1 + lane;  // unwrapped column, >= -1
+  const int x = xu < 0 ? nx - 1 : xu % nx;
+  const bool out_col = lane >= 1 && lane < kCellInW - 1 && xu < nx;
+  const int y0 = blockIdx.y * kCellInRows;
+  const int nrow = (y0 + kCellInRows <= ny ? kCellInRows : ny - y0);
+  const lbm_mlp_norm* nm = reinterpret_cast<const lbm_mlp_norm*>(pk + kPkNorm);
+  const Cols cl = cols_of<S>(x, nx);
+  float pr = 0.0f, pux = 0.0f, puy = 0.0f, pbx = 0.0f, pby = 0.0f;  // own column, previous row
+  for (int k = 0; k < nrow + 2; ++k) {
+    int yk = y0 - 1 + k;
+    yk = yk < 0 ? yk + ny : (yk >= ny ? yk - ny : yk);
+    C v[kQ];
+    pull_cell<S, C, 5>(src, pitch, rows_of<S>(yk, ny, pitch), cl, v);
+    const Mom<C> m = moments19(v);
+    const float r = float(C(ref.rho0) + m.drho);
+    const float ux = float(m.mx) / r, uy = float(m.my) / r;
+    const float bx = float(C(ref.bx0) + m.dbx), by = float(C(ref.by0) + m.dby);
+    const int sl = k & 3;
+    ring[sl][0][lane] = ux;
+    ring[sl][1][lane] = uy;
+    ring[sl][2][lane] = bx;
+    ring[sl][3][lane] = by;
+    // the wave's own LDS writes, visible to all its lanes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (k >= 2 && out_col) {
+      // row yk - 1 (slot k - 1), between rows yk - 2 and yk
+      const int sm = (k - 2) & 3, s0 = (k - 1) & 3;
+      const float om = 0.5f * (ring[s0][1][lane + 1] - ring[s0][1][lane - 1]) - 0.5f * (ring[sl][0][lane] - ring[sm][0][lane]);
+      const float jz = 0.5f * (ring[s0][3][lane + 1] - ring[s0][3][lane - 1]) - 0.5f * (ring[sl][2][lane] - ring[sm][2][lane]);
+      const float f[7] = {pr, pux, puy, pbx, pby, om, jz};
+      bool bad = false;
+      f32x8 z;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        z[i] = (f[i] - nm->shift[i]) * nm->scale[i];
+        bad = bad || !(fabsf(z[i]) <= kOodLimit);  // NaN counts as out of range
+      }
+      z[7] = 0.0f;
+      u32x4 w = __builtin_bit_cast(u32x4, to_bf16x8(z));
+      w[3] = (w[3] & 0xFFFFu) | (bad ? unsigned(kCellOutOfRange) << 16 : 0u);
+      out[(int64_t)(y0 + k - 2) * nx + x] = __builtin_bit_cast(CellIn, w);
+    }
+    pr = r;
+    pux = ux;
+    puy = uy;
+    pbx = bx;
+    pby = by;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1155,8 +1223,8 @@ size_t work_layout(Launch& L) {
   L.off_final = off;
   off += align256(kDiagVals * sizeof(double));
   if (L.learned) {
-    L.off_mom5 = off;
-    off += align256(5 * n * sizeof(float));
+    L.off_cellin = off;
+    off += align256(16 * n);
     L.off_corr = off;
     off += align256(4 * n * sizeof(float));
     L.off_mlp = off;
@@ -1302,24 +1370,26 @@ static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& 
 template <typename S>
 // The learned closure runs in the fused schedule only (checked at creation),
 // so the state is always in the pull layout here.
-static hipError_t mom5f_typed(const Launch& L, int64_t t, float* out) {
+static hipError_t cell_inputs_typed(const Launch& L, int64_t t, CellIn* out) {
   if (layout_at(L, t) != kLayoutPull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_moments5f_row<S>), dim3((L.nx + 255) / 256, L.ny), dim3(256), 0, L.stream,
-                     buffer_at<S>(L, t), out, L.nx, L.ny, L.pitch, rest_ref(L));
+  const int strips = cell_input_strips(L.nx);
+  const char* pk = static_cast<const char*>(L.work) + L.off_mlp;
+  hipLaunchKernelGGL((k_cell_inputs<S>), dim3((strips + 3) / 4, (L.ny + kCellInRows - 1) / kCellInRows), dim3(256),
+                     0, L.stream, buffer_at<S>(L, t), L.nx, L.ny, L.pitch, rest_ref(L), strips, pk, out);
   return hipGetLastError();
 }
 
 hipError_t launch_correction(const Launch& L, int64_t t, float* out) {
-  float* mom5 = reinterpret_cast<float*>(static_cast<char*>(L.work) + L.off_mom5);
+  CellIn* in = reinterpret_cast<CellIn*>(static_cast<char*>(L.work) + L.off_cellin);
   hipError_t e;
   switch (L.dtype) {
-    case LBM_FP64: e = mom5f_typed<double>(L, t, mom5); break;
-    case LBM_FP32: e = mom5f_typed<float>(L, t, mom5); break;
-    case LBM_FP16: e = mom5f_typed<_Float16>(L, t, mom5); break;
-    default: e = mom5f_typed<__bf16>(L, t, mom5); break;
+    case LBM_FP64: e = cell_inputs_typed<double>(L, t, in); break;
+    case LBM_FP32: e = cell_inputs_typed<float>(L, t, in); break;
+    case LBM_FP16: e = cell_inputs_typed<_Float16>(L, t, in); break;
+    default: e = cell_inputs_typed<__bf16>(L, t, in); break;
   }
   if (e != hipSuccess) return e;
-  return launch_mlp_correct(mom5, static_cast<char*>(L.work) + L.off_mlp, out, L.nx, L.ny, L.stream);
+  return launch_mlp_correct(in, static_cast<char*>(L.work) + L.off_mlp, out, L.nx, L.ny, L.stream);
 }
 
 template <typename S, typename C, int STENCIL>

@@ -60,12 +60,14 @@ k_mlp_pack(const float* __restrict__ p, const lbm_mlp_norm* __restrict__ norm, c
   } else if (e < 10240 + 64 + 32) {
     const int i = e - 10240 - 64;
     reinterpret_cast<float*>(pk + kPkNorm)[i] = reinterpret_cast<const float*>(norm)[i];
-  } else if (e < 10240 + 64 + 32 + 5120) {  // A1c: W1^T rows, patch-ordered inputs
+  } else if (e < 10240 + 64 + 32 + 4096) {  // A1n: W1^T rows, patch-ordered inputs
     const int f = e - (10240 + 64 + 32);
-    const int ot = f / 2560, kb = (f / 512) % 5, l = (f / 8) % 64, j = f % 8;
+    const int ot = f / 2048, kb = (f / 512) % 4, l = (f / 8) % 64, j = f % 8;
     const int hid = ot * 32 + l % 32, pos = kb * 2 + l / 32;
-    __bf16* c = reinterpret_cast<__bf16*>(pk + kPkA1c);
-    c[f] = __bf16(pos < 9 && j < 7 ? p[LBM_MLP_OFF_W1 + (j * 9 + pos) * 64 + hid] : 0.0f);
+    // element j < 7: field j at pos; element 7: field pos at position 8
+    const int k = j < 7 ? j * 9 + pos : (pos < 7 ? pos * 9 + 8 : -1);
+    __bf16* c = reinterpret_cast<__bf16*>(pk + kPkA1n);
+    c[f] = __bf16(k >= 0 ? p[LBM_MLP_OFF_W1 + k * 64 + hid] : 0.0f);
   }
 }
 
@@ -129,32 +131,28 @@ k_mlp_forward(const char* __restrict__ pk, const float* __restrict__ x, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// Correction of a simulation state.  Input: five FP32 planes rho, m_x, m_y,
-// B_x, B_y.  A workgroup stages a 64 x 16 tile with a two-cell halo in LDS
-// (all loads of a thread issued before any is used), forms u = m / rho, the
-// central-difference vorticity and current on the one-cell halo, normalises
-// the seven fields and flags cells with any |z| > 6 (or NaN), storing each
-// cell's seven normalised values (and a zero) as eight bfloat16 = 16 bytes,
-// then evaluates the network for its 1024 cells (each wave 8 groups of 32).
-// Layer 1 contracts over the patch positions in 16-input blocks (two
-// positions of eight values each; 5 blocks, the last half empty), so a
-// lane's B operand of a block is one 16-byte LDS read.  A cell is out of
+// Correction of a simulation state, second stage: the network on the per-cell
+// input vectors (CellIn, 16 bytes per cell) that the first stage wrote from
+// the state.  A workgroup loads the vectors of a 64 x 16 tile and its
+// one-cell halo straight into LDS (one 16-byte load per cell, no register
+// staging), then evaluates the network for its 1024 cells (each wave 8 groups
+// of 32).  Layer 1 contracts over four 16-input blocks of patch positions
+// (kPkA1n): a lane's operand of a block is one 16-byte LDS read whose last
+// element is replaced by a field of position 8.  A cell is out of
 // distribution when a flagged cell lies in its 3x3 neighbourhood (its 63
 // inputs are exactly the seven fields there).  Output: four FP32 planes
 // tau_xx, tau_xy, tau_yy, eps = out_scale * y, 0 for out-of-distribution cells
 // and cells whose output is not finite.
 // ---------------------------------------------------------------------------
 constexpr int kCorrTX = 64, kCorrTY = 16;
-constexpr int kCorrLX = kCorrTX + 4, kCorrLY = kCorrTY + 4, kCorrPL = kCorrLX * kCorrLY;
+constexpr int kCorrLX = kCorrTX + 2, kCorrLY = kCorrTY + 2, kCorrPL = kCorrLX * kCorrLY;
 
 // LDS cell offset of patch position pos (< 9: row pos / 3, column pos % 3)
-// of tile cell (ty, tx) from ty * LX + tx: the patch corner is at
-// (ty + 1, tx + 1) in the tile with its two-cell halo.
-__host__ __device__ constexpr int corr_patch_offset(int pos) {
-  return (pos / 3) * kCorrLX + pos % 3 + kCorrLX + 1;
-}
+// of tile cell (ty, tx) from ty * LX + tx: the patch corner is at (ty, tx)
+// in the tile with its one-cell halo.
+__host__ __device__ constexpr int corr_patch_offset(int pos) { return (pos / 3) * kCorrLX + pos % 3; }
 
-// Periodic wrap of v in [-2, n + kCorrLX) into [0, n).
+// Periodic wrap of v in [-1, n + kCorrLX) into [0, n).
 __device__ __forceinline__ int wrap_halo(int v, int n, bool wide) {
   if (wide) {
     v = v < 0 ? v + n : v;
@@ -164,113 +162,60 @@ __device__ __forceinline__ int wrap_halo(int v, int n, bool wide) {
   return v < 0 ? v + n : v;
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void global_void;
+
 __global__ void __launch_bounds__(256, 2)
-k_mlp_correct(const float* __restrict__ mom, const char* __restrict__ pk, float* __restrict__ corr, int nx, int ny) {
-  constexpr int LX = kCorrLX, PL = kCorrPL;
-  __shared__ float fld[7 * PL];
-  __shared__ bf16x8 zc[PL];  // normalised fields 0..6 of a cell, 0
-  __shared__ unsigned char bad[PL];
-  __shared__ unsigned char patch_bad[kCorrTX * kCorrTY];
+k_mlp_correct(const CellIn* __restrict__ in, const char* __restrict__ pk, float* __restrict__ corr, int nx, int ny) {
+  constexpr int LX = kCorrLX, PL = kCorrPL, PER = (PL + 255) / 256;
+  __shared__ CellIn zt[PER * 256];
   __shared__ __attribute__((aligned(16))) float bias[132];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, h = lane >> 5;
-  if (tid < 132) bias[tid] = reinterpret_cast<const float*>(pk + kPkB1)[tid];
   const int x0 = blockIdx.x * kCorrTX, y0 = blockIdx.y * kCorrTY;
   const int64_t n = (int64_t)nx * ny;
-  const lbm_mlp_norm* nm = reinterpret_cast<const lbm_mlp_norm*>(pk + kPkNorm);
-  // 1. primary fields on the tile and its two-cell halo
-  constexpr int PER = (PL + 255) / 256;
-  float vr[PER], vmx[PER], vmy[PER], vbx[PER], vby[PER];
+  const bool wide_x = nx >= LX, wide_y = ny >= kCorrLY;
+  // each wave fills 64 consecutive entries per pass (entry base + lane)
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int e = tid + 256 * i;
     if (e < PL) {
       const int ly = e / LX, lx = e - ly * LX;
-      const int gx = wrap_halo(x0 + lx - 2, nx, nx >= LX), gy = wrap_halo(y0 + ly - 2, ny, ny >= kCorrLY);
-      const int64_t c = (int64_t)gy * nx + gx;
-      vr[i] = mom[c];
-      vmx[i] = mom[n + c];
-      vmy[i] = mom[2 * n + c];
-      vbx[i] = mom[3 * n + c];
-      vby[i] = mom[4 * n + c];
+      const int gx = wrap_halo(x0 + lx - 1, nx, wide_x), gy = wrap_halo(y0 + ly - 1, ny, wide_y);
+      __builtin_amdgcn_global_load_lds((global_void*)(in + ((int64_t)gy * nx + gx)),
+                                       (lds_void*)(zt + 256 * i + 64 * wid), 16, 0, 0);
     }
   }
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = tid + 256 * i;
-    if (e < PL) {
-      fld[e] = vr[i];
-      fld[PL + e] = vmx[i] / vr[i];
-      fld[2 * PL + e] = vmy[i] / vr[i];
-      fld[3 * PL + e] = vbx[i];
-      fld[4 * PL + e] = vby[i];
-    }
-  }
-  __syncthreads();
-  // 2. vorticity and current on the tile and its one-cell halo
-  constexpr int RX = LX - 2, RN = RX * (kCorrLY - 2), PER2 = (RN + 255) / 256;
-#pragma unroll
-  for (int i = 0; i < PER2; ++i) {
-    const int e = tid + 256 * i;
-    if (e < RN) {
-      const int ly = e / RX + 1, p = ly * LX + (e - (ly - 1) * RX) + 1;
-      fld[5 * PL + p] = 0.5f * (fld[2 * PL + p + 1] - fld[2 * PL + p - 1]) - 0.5f * (fld[PL + p + LX] - fld[PL + p - LX]);
-      fld[6 * PL + p] = 0.5f * (fld[4 * PL + p + 1] - fld[4 * PL + p - 1]) - 0.5f * (fld[3 * PL + p + LX] - fld[3 * PL + p - LX]);
-    }
-  }
-  __syncthreads();
-  // 3. normalise the one-cell-halo region of every field; flag |z| > 6
-#pragma unroll
-  for (int i = 0; i < PER2; ++i) {
-    const int e = tid + 256 * i;
-    if (e < RN) {
-      const int ly = e / RX + 1, p = ly * LX + (e - (ly - 1) * RX) + 1;
-      bool b = false;
-      f32x8 zf;
-#pragma unroll
-      for (int f = 0; f < 7; ++f) {
-        const float z = (fld[f * PL + p] - nm->shift[f]) * nm->scale[f];
-        zf[f] = z;
-        b = b || !(fabsf(z) <= kOodLimit);  // NaN counts as out of range
-      }
-      zf[7] = 0.0f;
-      zc[p] = to_bf16x8(zf);
-      bad[p] = b ? 1 : 0;
-    }
-  }
-  __syncthreads();
-  // 3b. one flag per tile cell: any out-of-range value in its 3 x 3 patch
-  for (int e = tid; e < kCorrTX * kCorrTY; e += 256) {
-    const int ty = e / kCorrTX, base = ty * LX + (e - ty * kCorrTX);
-    int o = 0;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) o |= bad[base + (q / 3) * LX + q % 3 + LX + 1];
-    patch_bad[e] = (unsigned char)o;
-  }
-  __syncthreads();
-  // 4. the network, 32 cells per wave at a time (operands and biases held in
-  // registers for the whole loop; output scales in scalar registers)
-  MlpC w;
-  load_mlp_c(pk, lane, w);
+  if (tid < 132) bias[tid] = reinterpret_cast<const float*>(pk + kPkB1)[tid];
+  const lbm_mlp_norm* nm = reinterpret_cast<const lbm_mlp_norm*>(pk + kPkNorm);
+  MlpA w;
+  load_mlp_n(pk, lane, w);
   const float os0 = nm->out_scale[0], os1 = nm->out_scale[1], os2 = nm->out_scale[2], os3 = nm->out_scale[3];
+  __builtin_amdgcn_s_waitcnt(0);  // the loads into LDS are complete
+  __syncthreads();
   for (int g = wid; g < kCorrTX * kCorrTY / 32; g += 4) {
     const int ty = g >> 1, tx = (g & 1) * 32 + (lane & 31), base = ty * LX + tx;
-    // block kb: patch position 2 kb (lanes 0..31) or 2 kb + 1 (lanes 32..63)
-    bf16x8 zb[5];
+    CellIn v[4];
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-      zb[kb] = zc[base + (h ? corr_patch_offset(2 * kb + 1) : corr_patch_offset(2 * kb))];
-    const bf16x8 z8 = zc[base + corr_patch_offset(8)];
-    zb[4] = h ? bf16x8{} : z8;
-    const bool pb = patch_bad[ty * kCorrTX + tx] != 0;
-    const f32x4 v = mlp_wave(w, zb, bias, lane, nullptr, nullptr);
-    const bool o = pb || !(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]));
+    for (int kb = 0; kb < 4; ++kb) v[kb] = zt[base + (h ? corr_patch_offset(2 * kb + 1) : corr_patch_offset(2 * kb))];
+    const CellIn v8 = zt[base + corr_patch_offset(8)];
+    bf16x8 zb[4];
+    bool bad;
+    patch_operands(v, v8, h, zb, &bad);
+    // the two halves of a cell see complementary patch positions.  Every lane
+    // takes part in the exchange: under a short-circuit only the lanes with
+    // bad == false would run it, the value they send would be known to be 0,
+    // and the compiler drops the exchange altogether.
+    const int partner = __shfl_xor(int(bad), 32, 64);
+    const bool pb = bad || partner != 0;
+    const f32x4 y = mlp_wave(w, zb, bias, lane, nullptr, nullptr);
+    const bool o = pb || !(isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]) && isfinite(y[3]));
     const int gx = x0 + tx, gy = y0 + ty;
     if (h == 0 && gx < nx && gy < ny) {
       float* cp = corr + ((int64_t)gy * nx + gx);
-      cp[0] = o ? 0.0f : v[0] * os0;
-      cp[n] = o ? 0.0f : v[1] * os1;
-      cp[2 * n] = o ? 0.0f : v[2] * os2;
-      cp[3 * n] = o ? 0.0f : v[3] * os3;
+      cp[0] = o ? 0.0f : y[0] * os0;
+      cp[n] = o ? 0.0f : y[1] * os1;
+      cp[2 * n] = o ? 0.0f : y[2] * os2;
+      cp[3 * n] = o ? 0.0f : y[3] * os3;
     }
   }
 }
@@ -1050,7 +995,7 @@ size_t mlp_train_work_bytes(int batch) {
 }
 
 hipError_t launch_mlp_pack(const float* params, const lbm_mlp_norm* norm, void* packed, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_pack, dim3((10240 + 64 + 32 + 5120 + 255) / 256), dim3(256), 0, st, params, norm,
+  hipLaunchKernelGGL(k_mlp_pack, dim3((10240 + 64 + 32 + 4096 + 255) / 256), dim3(256), 0, st, params, norm,
                      static_cast<char*>(packed));
   return hipGetLastError();
 }
@@ -1198,9 +1143,9 @@ hipError_t launch_closure_samples(const double* c12, int nx, int ny, double delt
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_correct(const float* mom5, const void* packed, float* corr, int nx, int ny, hipStream_t st) {
+hipError_t launch_mlp_correct(const void* cell_in, const void* packed, float* corr, int nx, int ny, hipStream_t st) {
   hipLaunchKernelGGL(k_mlp_correct, dim3((nx + kCorrTX - 1) / kCorrTX, (ny + kCorrTY - 1) / kCorrTY), dim3(256), 0, st,
-                     mom5, static_cast<const char*>(packed), corr, nx, ny);
+                     static_cast<const CellIn*>(cell_in), static_cast<const char*>(packed), corr, nx, ny);
   return hipGetLastError();
 }
 

@@ -37,13 +37,15 @@ constexpr int kPkB1 = 20480;   // 64 floats
 constexpr int kPkB2 = 20736;   // 64 floats
 constexpr int kPkB3 = 20992;   // 4 floats (+ pad)
 constexpr int kPkNorm = 21248;  // lbm_mlp_norm
-// Layer 1 of the state-correction kernel, whose inputs are ordered by patch
-// position: contraction index k' = pos * 8 + field (pos = 3 row + column of
-// the 3x3 patch, field 0..6, field 7 and pos 9 zero), i.e. network input
-// field * 9 + pos.  [ot 2][kb 5][lane 64][8] bf16.
-constexpr int kPkA1c = 21504;
-static_assert(kPkNorm + (int)sizeof(lbm_mlp_norm) <= kPkA1c, "packed layout");
-static_assert(kPkA1c + 2 * 5 * 64 * 16 <= LBM_MLP_PACKED_BYTES, "packed size");
+// Layer 1 of the state-correction kernel, whose inputs come from the 3x3
+// patch of per-cell input vectors (CellIn below).  Contraction block kb of
+// lane half h holds patch position p = 2 kb + h (pos = 3 row + column):
+// element j < 7 is field j at p, element 7 is field p at position 8 (none
+// for p = 7), so the 63 inputs fill four 16-wide blocks.  [ot 2][kb 4][lane
+// 64][8] bf16.
+constexpr int kPkA1n = 21504;
+static_assert(kPkNorm + (int)sizeof(lbm_mlp_norm) <= kPkA1n, "packed layout");
+static_assert(kPkA1n + 2 * 4 * 64 * 16 <= LBM_MLP_PACKED_BYTES, "packed size");
 static_assert(sizeof(lbm_mlp_norm) == 128, "norm size");
 
 constexpr float kOodLimit = 6.0f;
@@ -68,10 +70,9 @@ struct MlpW {
   bf16x8 a1[2][KB1], a2[2][4], a3[4];
 };
 using MlpA = MlpW<4>;
-using MlpC = MlpW<5>;
 
-__device__ __forceinline__ void load_mlp(const char* __restrict__ pk, int lane, MlpA& w) {
-  const bf16x8* p1 = reinterpret_cast<const bf16x8*>(pk + kPkA1);
+__device__ __forceinline__ void load_mlp_at(const char* __restrict__ pk, int a1_off, int lane, MlpA& w) {
+  const bf16x8* p1 = reinterpret_cast<const bf16x8*>(pk + a1_off);
   const bf16x8* p2 = reinterpret_cast<const bf16x8*>(pk + kPkA2);
   const bf16x8* p3 = reinterpret_cast<const bf16x8*>(pk + kPkA3);
 #pragma unroll
@@ -85,20 +86,39 @@ __device__ __forceinline__ void load_mlp(const char* __restrict__ pk, int lane, 
   for (int kb = 0; kb < 4; ++kb) w.a3[kb] = p3[kb * 64 + lane];
 }
 
-// The same with the patch-ordered layer 1 of the state-correction kernel.
-__device__ __forceinline__ void load_mlp_c(const char* __restrict__ pk, int lane, MlpC& w) {
-  const bf16x8* p1 = reinterpret_cast<const bf16x8*>(pk + kPkA1c);
-  const bf16x8* p2 = reinterpret_cast<const bf16x8*>(pk + kPkA2);
-  const bf16x8* p3 = reinterpret_cast<const bf16x8*>(pk + kPkA3);
+// Network on feature rows (layer 1 in feature order).
+__device__ __forceinline__ void load_mlp(const char* __restrict__ pk, int lane, MlpA& w) {
+  load_mlp_at(pk, kPkA1, lane, w);
+}
+
+// Network of the state-correction kernel (layer 1 in patch order).
+__device__ __forceinline__ void load_mlp_n(const char* __restrict__ pk, int lane, MlpA& w) {
+  load_mlp_at(pk, kPkA1n, lane, w);
+}
+
+// Per-cell input vector of the state-correction kernel (16 bytes): the seven
+// normalised fields rounded to bfloat16, and in element 7 a flag, nonzero
+// when any of them is out of range (|z| > kOodLimit or not finite).
+using CellIn = bf16x8;
+constexpr unsigned short kCellOutOfRange = 0x3F80;  // bfloat16 1.0
+
+// Layer-1 B operands of lane half h from the input vectors of patch
+// positions 2 kb + h (v[kb]) and 8 (v8), in the kPkA1n order; *bad is set
+// when any of these five cells carries the out-of-range flag.
+__device__ __forceinline__ void patch_operands(const CellIn v[4], const CellIn& v8, int h, bf16x8 zb[4], bool* bad) {
+  const u32x4 w8 = __builtin_bit_cast(u32x4, v8);
+  unsigned flags = w8[3] >> 16;
 #pragma unroll
-  for (int ot = 0; ot < 2; ++ot) {
-#pragma unroll
-    for (int kb = 0; kb < 5; ++kb) w.a1[ot][kb] = p1[(ot * 5 + kb) * 64 + lane];
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) w.a2[ot][kb] = p2[(ot * 4 + kb) * 64 + lane];
+  for (int kb = 0; kb < 4; ++kb) {
+    u32x4 w = __builtin_bit_cast(u32x4, v[kb]);
+    flags |= w[3] >> 16;
+    // field 2 kb + h of position 8: low or high half of its word kb (word 3
+    // high is the flag, not a field: position 7 takes no extra input)
+    const unsigned extra = h ? (kb == 3 ? 0u : (w8[kb] & 0xFFFF0000u)) : (w8[kb] << 16);
+    w[3] = (w[3] & 0xFFFFu) | extra;
+    zb[kb] = __builtin_bit_cast(bf16x8, w);
   }
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb) w.a3[kb] = p3[kb * 64 + lane];
+  *bad = flags != 0;
 }
 
 // Accumulator of one 32-row tile preset to the bias of its rows.

@@ -145,8 +145,9 @@ def test_learned_closure_params_and_call_order(lib):
     w_learned = lib.lbm_work_bytes(ctypes.byref(p))
     p0 = _params()
     n = 64 * 48
-    # the learned closure adds 5 + 4 FP32 planes and the packed network
-    assert w_learned >= lib.lbm_work_bytes(ctypes.byref(p0)) + 9 * n * 4 + N.LBM_MLP_PACKED_BYTES
+    # the learned closure adds the 16-byte input vector of every cell, 4 FP32
+    # correction planes and the packed network
+    assert w_learned >= lib.lbm_work_bytes(ctypes.byref(p0)) + 8 * n * 4 + N.LBM_MLP_PACKED_BYTES
     # only with the fused schedule
     p_aa = _params(closure=N.LBM_CLOSURE_LEARNED, schedule=N.LBM_SCHED_AA)
     assert lib.lbm_work_bytes(ctypes.byref(p_aa)) == 0

@@ -392,11 +392,13 @@ def test_step_requires_a_network():
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("ood", [False, True])
-@pytest.mark.parametrize("nx,ny", [(96, 64), (70, 37), (67, 33)])
+@pytest.mark.parametrize("nx,ny", [(96, 64), (70, 37), (67, 33), (523, 77)])
 def test_correction_of_state_matches_oracle(nx, ny, ood, dtype):
     """The correction of a state (moments of the stored state, features,
     network, out-of-range fallback) against the oracle's on the state the GPU
-    holds, for FP64, FP32 and BF16 storage."""
+    holds, for FP64, FP32 and BF16 storage.  523 x 77 spans three strips of
+    the input-vector kernel (the last ragged), ragged row segments and
+    ragged network tiles in both directions."""
     G = _gpu()
     f, g = _smooth_state(nx, ny, 61)
     p = _params(62)
@@ -425,6 +427,49 @@ def test_correction_of_state_matches_oracle(nx, ny, ood, dtype):
         assert not oo.any()
     rows = lambda a: (a / out_scale[:, None, None]).reshape(4, -1).T[decided]
     _compare_rows(rows(corr), rows(want), f"correction {nx}x{ny} ood={ood} ({oo.mean():.0%} out of range)")
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_isolated_out_of_range_cells_zero_exactly_their_neighbourhoods(dtype):
+    """Isolated cells whose density alone leaves the training range (all nine
+    f populations scaled, so u, B and the vorticity and current around them
+    keep their values): each must zero the correction of exactly the nine
+    cells whose 3x3 patch holds it, and every other cell keeps the oracle's
+    correction.  Each neighbour sees its culprit at another patch position,
+    so all nine positions are checked on their own (inside a blob of flagged
+    cells a missed position is hidden by the others).  Culprits sit at the
+    grid's corner, at network-tile edges (every 64 columns, 16 rows) and at
+    the input-vector kernel's strip edges (every 254 columns)."""
+    G = _gpu()
+    nx, ny = 523, 77
+    f, g = _smooth_state(nx, ny, 71)
+    p = _params(72)
+    shift, scale, out_scale, s64, c64 = _state_norm(f, g)
+    culprits = [(0, 0), (5, 63), (16, 64), (31, 127), (30, 253), (45, 254), (60, 508), (76, 300), (47, 522)]
+    rho = f.sum(axis=0)
+    want_ood = np.zeros((ny, nx), dtype=bool)
+    for cy, cx in culprits:
+        f[:, cy, cx] *= (float(shift[0]) + 8.0 / float(scale[0])) / rho[cy, cx]
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                want_ood[(cy + dy) % ny, (cx + dx) % nx] = True
+    s = _learned_sim(G, nx, ny, f, g, p, shift, scale, out_scale, dtype=dtype)
+    corr = s.closure_correction().cpu().numpy().astype(np.float64)
+    st = s.get_state().cpu().numpy()
+    fo, go = st[:9], np.stack([st[9:14], st[14:19]], axis=1)
+    rho, mx, my, bx, by = O.Oracle._moments(fo, go)
+    zmax = np.abs(L.normalise(L.closure_features(rho, mx, my, bx, by), s64, c64)).max(axis=1).reshape(ny, nx)
+    assert np.array_equal(zmax > 6.0, want_ood)        # the input: only the culprits are out of range
+    assert (np.abs(zmax - 6.0) > 0.1).all()
+    got_ood = (corr == 0).all(axis=0)
+    missed = np.argwhere(want_ood & ~got_ood)
+    extra = np.argwhere(got_ood & ~want_ood)
+    print(f"{dtype}: {want_ood.sum()} cells to zero, missed {missed[:8].tolist()}, extra {extra[:8].tolist()}",
+          flush=True)
+    assert np.array_equal(got_ood, want_ood)
+    want = L.learned_correction(p, s64, c64, out_scale.astype(np.float64))(rho, mx, my, bx, by)
+    rows = lambda a: (a / out_scale[:, None, None]).reshape(4, -1).T[~want_ood.ravel()]
+    _compare_rows(rows(corr), rows(want), f"isolated out-of-range cells ({dtype})")
 
 
 @pytest.mark.parametrize("dtype,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
