@@ -610,26 +610,29 @@ def learned_study(args, dev, stream) -> int:
 
 
 def production_run(args, dev, stream) -> int:
-    """The production configuration run: a 16384^2 jet (268 M cells) with the
-    learned closure and FP16 population storage, nu = eta = 5e-5, Delta = 4,
-    B = (B0, 0) with B0 = --production-b0, for --production-run steps;
-    diagnostics (energies, enstrophy, integral J_z^2, div B) and the radially
-    binned kinetic and magnetic spectra with the streamwise spectrum E_x(m)
-    every --production-every steps.
+    """The production configuration run: a 16384^2 jet (268 M cells), nu =
+    5e-5, Delta = 4, B = (B0, 0) with B0 = --production-b0, for
+    --production-run steps; by default the learned closure, FP16 population
+    storage and eta = 5e-5 (--production-closure, --production-dtype,
+    --production-eta).  Diagnostics (energies, enstrophy, integral J_z^2,
+    div B) and the radially binned kinetic and magnetic spectra with the
+    streamwise spectrum E_x(m) every --production-every steps; the run stops
+    at the first snapshot with a non-finite value.
 
     The jet is the learned-closure study's (shear layers U0 = 0.05 of
     thickness L/100, modes 2-6 at 2 % of U0 with seeded phases, noise 1e-4),
     and so is the network: trained first, with the library's kernels, on
     filtered DNS of that jet at the same B0 (4096^2 -> 1024^2; no filtered
-    DNS of the 16384^2 jet fits one GPU).  Each snapshot also records the
-    share of cells whose inputs lie outside the training range (the analytic
-    closure alone there) and the RMS of the four correction planes.  FP16 is the 16-bit storage that keeps the
-    growth rate within 2 % of the filtered DNS in that study; BF16 misses it
-    by 20-33 %.  Reported: the series, fitted growth rates of E_x(m), m = 1..8
-    (over the snapshots where E_x(m) lies between 1e-3 and 1e-1 of its
-    largest value, else over all snapshots before that value), and the step
-    time; with --out-dir the spectra go to
-    <out-dir>/production_spectra_B0_<B0>.npz.  One JSON line on stdout.
+    DNS of the 16384^2 jet fits one GPU).  Each snapshot of a learned run
+    also records the share of cells whose inputs lie outside the training
+    range (the analytic closure alone there) and the RMS of the four
+    correction planes.  FP16 is the 16-bit storage that keeps the growth rate
+    within 2 % of the filtered DNS in that study; BF16 misses it by 20-33 %.
+    Reported: the series, fitted growth rates of E_x(m), m = 1..8, over the
+    finite snapshots (where E_x(m) lies between 1e-3 and 1e-1 of its largest
+    value, else all snapshots up to that value), and the step time; with
+    --out-dir the spectra go to <out-dir>/production_spectra_B0_<B0>_eta_
+    <eta>_<closure>_<dtype>.npz.  One JSON line on stdout.
     """
     import numpy as np
     import torch
@@ -643,20 +646,25 @@ def production_run(args, dev, stream) -> int:
     # same B0 (its normalised inputs would otherwise all lie outside the
     # training range)
     prod = TR.JetSetup(**{**_study_setup(args).__dict__, "B0": b0})
-    mlp, _, losses = _train_study_network(args, prod, 8000, dev, stream)
-    if mlp is None:
-        return 1
-    packed = mlp.pack()
+    mlp, losses, packed = None, None, None
+    if args.production_closure == "learned":
+        mlp, _, losses = _train_study_network(args, prod, 8000, dev, stream)
+        if mlp is None:
+            return 1
+        packed = mlp.pack()
     t0 = time.perf_counter()
     mom0 = TR.jet_fields(prod, n, seed=3, device=dev)
     log(f"initial fields in {time.perf_counter() - t0:.1f} s")
-    sim = Sim(nx=n, ny=n, nu=5e-5, eta=5e-5, delta=LES_DELTA, dtype="fp16", schedule="fused",
-              b_ref=(b0, 0.0), closure="learned", device=dev, stream=stream,
+    eta, closure, dtype = args.production_eta, args.production_closure, args.production_dtype
+    sim = Sim(nx=n, ny=n, nu=5e-5, eta=eta, delta=LES_DELTA, dtype=dtype, schedule="fused",
+              b_ref=(b0, 0.0), closure=closure, device=dev, stream=stream,
               s5=GHOST, s6=GHOST, s7=GHOST, s8=GHOST)
     sim.init_from_moments(mom0)
     del mom0
     torch.cuda.empty_cache()
-    sim.set_closure_mlp(packed)
+    learned = closure == "learned"
+    if learned:
+        sim.set_closure_mlp(packed)
     mom = torch.empty((5, n, n), dtype=torch.float64, device=dev)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     corr = torch.empty((4, n, n), dtype=torch.float32, device=dev)
@@ -677,17 +685,18 @@ def production_run(args, dev, stream) -> int:
             series[k].append(d[k])
         series["ex_m0_to_8"].append(ekx[:9].tolist())
         # share of cells left to the analytic closure, and the correction's size
-        sim.closure_correction(corr)
-        torch.cuda.synchronize(dev)
-        series["out_of_range_share"].append((corr == 0).all(dim=0).float().mean().item())
-        series["correction_rms"].append([torch.linalg.vector_norm(corr[i], dtype=torch.float64).item() / n
-                                         for i in range(4)])
+        if learned:
+            sim.closure_correction(corr)
+            torch.cuda.synchronize(dev)
+            series["out_of_range_share"].append((corr == 0).all(dim=0).float().mean().item())
+            series["correction_rms"].append([torch.linalg.vector_norm(corr[i], dtype=torch.float64).item() / n
+                                             for i in range(4)])
         spectra_k.append(ek.float().cpu().numpy())
         spectra_m.append(em.float().cpu().numpy())
         log(f"production B0={b0}: t = {sim.t} e_kin {d['e_kin']:.6e} e_mag {d['e_mag']:.6e} "
             f"E_x(3) {ekx[3].item():.3e} divB_max {d['divb_max']:.2e} nonfinite {d['nonfinite']} "
-            f"out of range {series['out_of_range_share'][-1]:.3%} "
-            f"({time.perf_counter() - t_wall:.0f} s)")
+            + (f"out of range {series['out_of_range_share'][-1]:.3%} " if learned else "")
+            + f"({time.perf_counter() - t_wall:.0f} s)")
         if d["nonfinite"] or sim.t >= T:
             break
         ev0.record(stream)
@@ -695,8 +704,9 @@ def production_run(args, dev, stream) -> int:
         ev1.record(stream)
         torch.cuda.synchronize(dev)
         step_ms += ev0.elapsed_time(ev1)
-    tt = np.asarray(series["t"], dtype=np.float64)
-    ex = np.asarray(series["ex_m0_to_8"])
+    fin = np.asarray(series["nonfinite"]) == 0
+    tt = np.asarray(series["t"], dtype=np.float64)[fin]
+    ex = np.asarray(series["ex_m0_to_8"])[fin]
     rates = {}
     for m in range(1, 9):
         v = ex[:, m]
@@ -708,11 +718,12 @@ def production_run(args, dev, stream) -> int:
                     else None)
     steps_done = int(series["t"][-1])
     out = {
-        "study": "production configuration: 16384^2 jet, learned closure, FP16 storage",
-        "grid": n, "nu": 5e-5, "eta": 5e-5, "Delta": LES_DELTA, "B0": b0, "steps": steps_done,
+        "study": f"production configuration: 16384^2 jet, {closure} closure, {dtype} storage",
+        "grid": n, "nu": 5e-5, "eta": eta, "Delta": LES_DELTA, "B0": b0, "steps": steps_done,
         "jet": prod.kh(3) | {"modes": list(prod.modes), "mode_amp_over_U0": prod.mode_amp},
-        "network": {"trained_on": "filtered DNS 4096^2 -> 1024^2 of the same jet (same B0), seeds 1 and 2",
-                    "loss_first": losses[0].item(), "loss_last200": losses[-200:].mean().item()},
+        "network": ({"trained_on": "filtered DNS 4096^2 -> 1024^2 of the same jet (same B0), seeds 1 and 2",
+                     "loss_first": losses[0].item(), "loss_last200": losses[-200:].mean().item()}
+                    if learned else None),
         "finite": series["nonfinite"][-1] == 0,
         "step_ms": round(step_ms / max(steps_done, 1), 4),
         "mlups": round(n * n * steps_done / max(step_ms, 1e-9) / 1e3, 1),
@@ -722,7 +733,8 @@ def production_run(args, dev, stream) -> int:
     }
     if args.out_dir:
         os.makedirs(args.out_dir, exist_ok=True)
-        np.savez_compressed(os.path.join(args.out_dir, f"production_spectra_B0_{b0:g}.npz"), t=tt,
+        np.savez_compressed(os.path.join(args.out_dir, f"production_spectra_B0_{b0:g}_eta_{eta:g}_{closure}_{dtype}.npz"),
+                            t=np.asarray(series["t"], dtype=np.float64),
                             e_kin=np.stack(spectra_k), e_mag=np.stack(spectra_m))
     sim.close()
     print(json.dumps(out), flush=True)
@@ -773,6 +785,11 @@ def main() -> int:
                     help="run the production configuration (16384^2, learned closure, FP16 storage) for STEPS "
                          "steps at B0 = --production-b0 and report its series; nothing else is run")
     ap.add_argument("--production-b0", type=float, default=0.02)
+    ap.add_argument("--production-eta", type=float, default=5e-5,
+                    help="production run: resistivity (5e-5 as configured; the single-relaxation-time magnetic "
+                         "collision is then at s_m = 1.9994)")
+    ap.add_argument("--production-closure", default="learned", choices=["learned", "analytic"])
+    ap.add_argument("--production-dtype", default="fp16", choices=["fp16", "bf16", "fp32"])
     ap.add_argument("--production-every", type=int, default=1000,
                     help="production run: spectra and diagnostics every this many steps")
     ap.add_argument("--train-steps", type=int, default=4000)
