@@ -1041,7 +1041,30 @@ def main() -> int:
                                  "k_fused_les<..., CORR> every step")}
             log(f"learned les 1024^2 {dt} (network every {every}): {ms * 1e3:.1f} us/step")
             del sl
-        del mlp, packed
+        # one Adam step of the network on 8192 rows (forward, matrix-core
+        # backward, fixed-order reduction, Adam), synthetic seeded rows
+        gen = torch.Generator(device=dev).manual_seed(5)
+        Xt = torch.randn((1 << 16, 64), device=dev, generator=gen) * 0.5
+        Xt[:, 63] = 0.0
+        Tt = torch.randn((1 << 16, 4), device=dev, generator=gen)
+        mlp.fit_norm(Xt, Tt)
+        from paper_1705_09807_amd import training as TR
+        TR.train(mlp, Xt, Tt, steps=20, batch=8192)
+        torch.cuda.synchronize(dev)
+        a, b = ev(), ev()
+        a.record(stream)
+        TR.train(mlp, Xt, Tt, steps=200, batch=8192)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ms = a.elapsed_time(b) / 200
+        # flops per row: forward 2 * (63 * 64 + 64 * 64 + 64 * 4) = 16 768; backward
+        # d1 = W2 d2 (2 * 64 * 64) and the three weight gradients (16 768 again)
+        tflop = 8192 * (16768 + 2 * 64 * 64 + 16768) / (ms * 1e-3) / 1e12
+        extra["mlp_train_step_8192"] = {"avg_step_us": round(ms * 1e3, 1), "rows": 8192,
+                                        "tflops_fwd_bwd": round(tflop, 2),
+                                        "kernels": "k_mlp_train (matrix cores) + k_mlp_reduce + k_mlp_adam"}
+        log(f"mlp train step (8192 rows): {ms * 1e3:.1f} us")
+        del mlp, packed, Xt, Tt
 
     if args.lowprec_steps > 0:
         # 8192^2 jet, nu = eta = 1e-4: storage precision FP32 vs 16-bit deviations

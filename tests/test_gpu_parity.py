@@ -346,7 +346,10 @@ def test_full_size_sampled(case):
     d = s.diagnostics()
     assert d["nonfinite"] == 0
     # periodic domain: mass, momentum and B are conserved to storage round-off
-    ctol = 1e-13 if dtype == "fp64" else 1e-9
+    drift = {k: abs(d[k] - d0[k]) / d0["mass"] for k in ("mass", "mom_x", "mom_y", "bsum_x", "bsum_y")}
+    _say(f"conservation drift per unit mass after {steps} steps: " + ", ".join(f"{k} {v:.1e}" for k, v in drift.items()))
+    # (measured on MI355X: FP32 <= 1.3e-12 of the mass for every sum, FP64 <= 4e-18)
+    ctol = 1e-13 if dtype == "fp64" else 2e-10
     assert abs(d["mass"] - d0["mass"]) <= ctol * d0["mass"]
     for key in ("mom_x", "mom_y", "bsum_x", "bsum_y"):
         assert abs(d[key] - d0[key]) <= ctol * d0["mass"] * 0.05, key
@@ -384,8 +387,11 @@ def test_full_size_dns_jet_sampled():
         assert np.abs(mom[:, k] - mo).max() <= 2e-6, (x, y)
     d = s.diagnostics()
     assert d["nonfinite"] == 0
-    assert abs(d["mass"] - d0["mass"]) <= 1e-9 * d0["mass"]
-    assert abs(d0["mass"] - n * n) <= 1e-9 * n * n
+    _say(f"dns mass drift per unit mass after {steps} steps: {abs(d['mass'] - d0['mass']) / d0['mass']:.1e}, "
+         f"initial mass offset {abs(d0['mass'] - n * n) / (n * n):.1e}")
+    # FP32 deviations of the jet: measured drift 3.7e-11, initial offset 6e-13
+    assert abs(d["mass"] - d0["mass"]) <= 3e-10 * d0["mass"]
+    assert abs(d0["mass"] - n * n) <= 1e-11 * n * n
 
 
 def test_benchmark_workload_stays_finite():
