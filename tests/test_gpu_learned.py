@@ -390,15 +390,21 @@ def test_step_requires_a_network():
         s.step(1)
 
 
+_CORR_CASES = [(nx, ny, ood) for nx, ny in [(96, 64), (70, 37), (67, 33), (523, 77)] for ood in (False, True)]
+# on a grid this small every 3x3 patch reaches the density extremes, so the
+# out-of-range case would flag every cell: the in-range case only
+_CORR_CASES.append((24, 18, False))
+
+
 @pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
-@pytest.mark.parametrize("ood", [False, True])
-@pytest.mark.parametrize("nx,ny", [(96, 64), (70, 37), (67, 33), (523, 77)])
+@pytest.mark.parametrize("nx,ny,ood", _CORR_CASES)
 def test_correction_of_state_matches_oracle(nx, ny, ood, dtype):
     """The correction of a state (moments of the stored state, features,
     network, out-of-range fallback) against the oracle's on the state the GPU
     holds, for FP64, FP32 and BF16 storage.  523 x 77 spans three strips of
     the input-vector kernel (the last ragged), ragged row segments and
-    ragged network tiles in both directions."""
+    ragged network tiles in both directions; 24 x 18 is narrower than a
+    strip and a tile in both directions, so every halo wraps around."""
     G = _gpu()
     f, g = _smooth_state(nx, ny, 61)
     p = _params(62)
