@@ -166,13 +166,14 @@ typedef struct {
 
 /* Bytes of the caller-owned device buffers for these parameters (0 if the
  * parameters are invalid).  The state holds the populations in the storage
- * precision, one buffer (AA) or two (fused), each ny lattice rows of P
+ * precision, one buffer (AA) or two (fused, the second starting 4 KB past
+ * the 64 KB boundary that follows the first), each ny lattice rows of P
  * population rows (P = 19, or 27 with D2Q9 g) padded to a multiple of 64
  * elements, rounded up to 256 elements: the populations of a lattice row
  * are stored together (an internal layout: state IO uses the natural layout
- * above).  The work buffer holds moment
- * planes and reduction partials (and, with the learned closure, the network
- * and its input and output planes). */
+ * above).  The work buffer holds moment planes and reduction partials (and,
+ * with the learned closure, the packed network, a 16-byte input vector per
+ * cell and the 4 FP32 correction planes). */
 size_t lbm_state_bytes(const lbm_params* p);
 size_t lbm_work_bytes(const lbm_params* p);
 
