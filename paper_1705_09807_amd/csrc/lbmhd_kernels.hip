@@ -671,6 +671,218 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
   }
 }
 
+// A cell's populations as stored (16-bit values decoded where they are used).
+template <typename S, int QG>
+struct RawCell {
+  S v[kPop<QG>];
+};
+template <typename S, typename C, int QG>
+__device__ __forceinline__ void decode_raw(const RawCell<S, QG>& c, C* v) {
+#pragma unroll
+  for (int q = 0; q < kPop<QG>; ++q) v[q] = decode<C>(c.v[q]);
+}
+
+// Buffer addressing of the wave-strip sweep: a buffer resource per lattice
+// row (its base held in scalar registers), the population's row offset as
+// the scalar offset and the column's byte offset as the per-lane offset, so a
+// load or store costs no per-lane address arithmetic.  Raw resources
+// (stride 0) of num_records = the lattice row's bytes; every access of a row
+// lies inside it, except the stores of lanes that own no output column,
+// which take an offset past num_records: the hardware's range check drops
+// them, so the row body has no branch around its stores.
+constexpr uint32_t kDropOffset = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
+}
+template <typename S>
+__device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(S) == 2)
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, int(voff), int(soff), 0));
+  else
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+}
+template <typename S, bool NT>
+__device__ __forceinline__ void buf_store(S v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  constexpr int aux = NT ? 2 : 0;  // non-temporal
+  if constexpr (sizeof(S) == 2)
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, int(voff), int(soff), aux);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff), int(soff), aux);
+}
+
+// f_q(x, y) = src[q][x - c_q][y - c_q] of one cell, as stored; ys, yc, yn
+// are the (periodic) rows y - 1, y, y + 1, pq the bytes between population
+// rows.
+template <typename S, int QG>
+__device__ __forceinline__ void pull_raw(const S* __restrict__ src, uint32_t pq, int ys, int yc, int yn,
+                                         const Cols& cl, RawCell<S, QG>& c) {
+  const uint32_t rowb = uint32_t(kPop<QG>) * pq;
+  const char* b = reinterpret_cast<const char*>(src);
+  const __amdgpu_buffer_rsrc_t rs = row_rsrc(b + int64_t(ys) * rowb, rowb);
+  const __amdgpu_buffer_rsrc_t rc = row_rsrc(b + int64_t(yc) * rowb, rowb);
+  const __amdgpu_buffer_rsrc_t rn = row_rsrc(b + int64_t(yn) * rowb, rowb);
+#pragma unroll
+  for (int q = 0; q < kPop<QG>; ++q) {
+    const uint32_t xo = qcx<QG>(q) > 0 ? cl.w : (qcx<QG>(q) < 0 ? cl.e : cl.c);
+    const __amdgpu_buffer_rsrc_t rr = qcy<QG>(q) > 0 ? rs : (qcy<QG>(q) < 0 ? rn : rc);
+    c.v[q] = buf_load<S>(rr, xo, uint32_t(q) * pq);
+  }
+}
+
+// Closure on, FP32 compute (FP32, FP16 and BF16 storage): the schedule of
+// k_fused_les, written for the buffer addressing above.  A workgroup of W + 64
+// lanes owns the columns x0 .. x0+W-1 (W a multiple of 64, so every wave
+// stores whole aligned cache lines) and marches up the rows y0 .. y1-1; the
+// moment fields of rows y-1 .. y+2 live in a 4-slot LDS ring indexed by
+// column - x0 + 1.  Per row a collision lane issues the loads of row y + 2,
+// collides and stores row y from the ring, puts row y + 2's moments into the
+// ring and meets the others at the row's barrier (which waits for LDS only).
+// The row body has no branch around a memory operation: a lane past the last
+// column loads the last column, drops its stores (kDropOffset) and puts its
+// moments into a spare ring column (W + 2), so the compiler waits on each
+// batch of loads alone; three register sets rotate the rows without copies.
+// The last wave gathers the two halo columns (x0 - 1 and the column after the
+// strip's last cell) two rows ahead, in a loop of its own with the same
+// barrier per row.  Results are those of k_fused_les (same expressions).
+template <typename S, int W, int STENCIL, bool NT, int MODE, int QG>
+__global__ void __launch_bounds__(W + 64)
+k_fused_les_f(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t pitch, int ry, Rates<float> r,
+              const float* __restrict__ corr) {
+  using C = float;
+  constexpr int NF = MODE == kClosureFull ? 5 : 4;
+  constexpr int NP = kPop<QG>;
+  __shared__ C ring[4][NF][W + 3];
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * W;
+  const int last = min(x0 + W, nx) - 1;  // last column of this strip
+  const int y0 = blockIdx.y * ry;
+  const int y1 = min(y0 + ry, ny);
+  const uint32_t pq = uint32_t(pitch) * uint32_t(sizeof(S));  // bytes between population rows
+  const uint32_t rowb = uint32_t(NP) * pq;                    // bytes of a lattice row
+  auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
+  auto slot = [&](int y) { return (y - y0 + 1) & 3; };  // ring slot of row y
+  auto pull = [&](int y, const Cols& cx, RawCell<S, QG>& c) __attribute__((always_inline)) {
+    pull_raw<S, QG>(src, pq, wrapy(y - 1), y, wrapy(y + 1), cx, c);
+  };
+  auto put = [&](int sl, int widx, const RawCell<S, QG>& c) __attribute__((always_inline)) {
+    C v[NP];
+    decode_raw<S, C, QG>(c, v);
+    const Mom<C> m = moments_of<QG>(v);
+    ring[sl][0][widx] = m.mx;
+    ring[sl][1][widx] = m.my;
+    ring[sl][2][widx] = m.dbx;
+    ring[sl][3][widx] = m.dby;
+    if constexpr (NF == 5) ring[sl][4][widx] = m.drho;
+  };
+
+  if (tid >= W) {
+    // halo wave: lane 0 gathers the column left of the strip, the others the
+    // column right of it (only lanes 0 and 1 put theirs into the ring)
+    const int hl = tid - W;
+    const int xc = hl == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (last + 1 == nx ? 0 : last + 1);
+    const int widx = hl == 0 ? 0 : (hl == 1 ? last - x0 + 2 : W + 2);
+    const Cols cx = cols_of<S>(xc, nx);
+    auto ahead = [&](int y) { return wrapy(y <= y1 ? y : y1); };  // rows past y1 are not needed
+    RawCell<S, QG> ca, cb;
+    pull(wrapy(y0 - 1), cx, ca);
+    put(0, widx, ca);
+    pull(y0, cx, ca);
+    put(1, widx, ca);
+    pull(wrapy(y0 + 1), cx, ca);
+    put(2, widx, ca);
+    pull(ahead(y0 + 2), cx, ca);
+    __syncthreads();
+    int y = y0;
+    for (; y + 2 <= y1; y += 2) {  // rows y, y + 1: put rows y + 2 and y + 3
+      pull(ahead(y + 3), cx, cb);
+      put(slot(y + 2), widx, ca);
+      __syncthreads();
+      pull(ahead(y + 4), cx, ca);
+      if (y + 3 <= y1) put(slot(y + 3), widx, cb);
+      __syncthreads();
+    }
+    if (y < y1) __syncthreads();  // row y1 - 1 needs no further row
+    return;
+  }
+
+  const bool valid = x0 + tid <= last;
+  const int xc = valid ? x0 + tid : last;  // idle lanes address a valid cell, never stored
+  const Cols cx = cols_of<S>(xc, nx);
+  const int widx = valid ? tid + 1 : W + 2;
+  const uint32_t xo_store = valid ? cx.c : kDropOffset;
+  const int64_t n = (int64_t)nx * ny;
+  float cc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, cn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  auto load_corr = [&](int y, float (&c)[4]) __attribute__((always_inline)) {
+    const int64_t ci = (int64_t)y * nx + xc;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = corr[k * n + ci];
+  };
+
+  // Row y: rcur holds it as stored, rt receives row y + 2 (row y + 1 again
+  // for the segment's last row, whose ring slot is then never read).
+  auto row = [&](const RawCell<S, QG>& rcur, RawCell<S, QG>& rt, int y) __attribute__((always_inline)) {
+    const bool more = y + 1 < y1;
+    pull(wrapy(more ? y + 2 : y + 1), cx, rt);
+    if constexpr (MODE == kClosureCorr) load_corr(more ? y + 1 : y, cn);
+    // the loads stay ahead of the collision (the scheduler would otherwise
+    // sink them to their use to save registers)
+    __builtin_amdgcn_sched_barrier(0);
+    const int sc = slot(y), sn = slot(y + 1), ss = slot(y - 1), l = tid + 1;
+    C gr[NF][2];
+#pragma unroll
+    for (int k = 0; k < NF; ++k)
+      grad3x3<C, STENCIL>(ring[sc][k][l + 1], ring[sc][k][l - 1], ring[sn][k][l], ring[ss][k][l], ring[sn][k][l + 1],
+                          ring[sn][k][l - 1], ring[ss][k][l + 1], ring[ss][k][l - 1], gr[k][0], gr[k][1]);
+    C cur[NP];
+    decode_raw<S, C, QG>(rcur, cur);
+    const Mom<C> m = moments_of<QG>(cur);
+    const C ir = C(1) / (r.rho0 + m.drho);
+    Closure<C> cl;
+    if constexpr (MODE == kClosureFull) {
+      cl = closure_terms_full(gr, m.mx, m.my, r.bx0 + m.dbx, r.by0 + m.dby, ir, r.k2);
+    } else {
+      if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9 && QG == 5)
+        local_gradients(cur, m, r, gr[1][0] - gr[0][1], gr);
+      cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0], gr[3][1], ir, r.k2);
+    }
+    if constexpr (MODE == kClosureCorr) {
+      cl.tau_xy += cc[1];
+      cl.tau_d += cc[0] - cc[2];
+      cl.tau_s += cc[0] + cc[2];
+      cl.eps += cc[3];
+    }
+    collide_q<QG>(cur, m, cl, r);
+    const __amdgpu_buffer_rsrc_t d = row_rsrc(reinterpret_cast<char*>(dst) + int64_t(y) * rowb, rowb);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) buf_store<S, NT>(encode<S>(cur[q]), d, xo_store, uint32_t(q) * pq);
+    __builtin_amdgcn_sched_barrier(0);
+    put(slot(y + 2), widx, rt);
+    if constexpr (MODE == kClosureCorr) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cc[k] = cn[k];
+    }
+    __syncthreads();
+  };
+
+  RawCell<S, QG> ra, rb, rc;
+  pull(wrapy(y0 - 1), cx, ra);
+  put(0, widx, ra);
+  pull(y0, cx, rb);
+  put(1, widx, rb);
+  pull(wrapy(y0 + 1), cx, rc);
+  put(2, widx, rc);
+  if constexpr (MODE == kClosureCorr) load_corr(y0, cc);
+  __syncthreads();
+  int y = y0;
+  for (; y + 3 <= y1; y += 3) {  // one straight-line block of three rows
+    row(rb, ra, y);
+    row(rc, rb, y + 1);
+    row(ra, rc, y + 2);
+  }
+  if (y < y1) row(rb, ra, y);
+  if (y + 1 < y1) row(rc, rb, y + 1);
+}
+
 // ---------------------------------------------------------------------------
 // AA schedule (one buffer, in place).
 //  even t: load A[q][x],             store f*_q to A[opp q][x]
@@ -1293,30 +1505,37 @@ static bool streaming_stores(const Launch& L) {
   return 2.0 * double(9 + 2 * L.qg) * double(L.nx) * double(L.ny) * double(storage_bytes(L.dtype)) > 256.0e6;
 }
 
-template <typename S, typename C, int W, bool NT, int MODE, int QG>
-static void launch_les_k(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
+// FP32 compute runs k_fused_les_f, FP64 k_fused_les.
+template <typename S, typename C, int W, bool NT, int MODE, int QG, int STENCIL>
+static void launch_les_s(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
   const int ry = fused_rows(L.nx, L.ny, W, L.cus, sizeof(C) == 4 ? 128 : 64);
   const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
+  if constexpr (sizeof(C) == 4)
+    hipLaunchKernelGGL((k_fused_les_f<S, W, STENCIL, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream, src, dst, L.nx,
+                       L.ny, L.pitch, ry, r, corr);
+  else
+    hipLaunchKernelGGL((k_fused_les<S, C, W, STENCIL, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream, src, dst, L.nx,
+                       L.ny, L.pitch, ry, r, corr);
+}
+
+template <typename S, typename C, int W, bool NT, int MODE, int QG>
+static void launch_les_k(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
   // the density-gradient closure and the D2Q9 vector distribution take
   // stencil gradients only
   if constexpr (MODE != kClosureFull && QG == 5) {
     if (L.stencil == LBM_STENCIL_LOCAL_ISO9) {
-      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_ISO9, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream,
-                         src, dst, L.nx, L.ny, L.pitch, ry, r, corr);
+      launch_les_s<S, C, W, NT, MODE, QG, LBM_STENCIL_LOCAL_ISO9>(L, src, dst, r, corr);
       return;
     }
     if (L.stencil == LBM_STENCIL_LOCAL_CENTRAL5) {
-      hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_LOCAL_CENTRAL5, NT, MODE, QG>), g, dim3(W + 64), 0,
-                         L.stream, src, dst, L.nx, L.ny, L.pitch, ry, r, corr);
+      launch_les_s<S, C, W, NT, MODE, QG, LBM_STENCIL_LOCAL_CENTRAL5>(L, src, dst, r, corr);
       return;
     }
   }
   if (L.stencil == LBM_STENCIL_CENTRAL5)
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_CENTRAL5, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream, src,
-                       dst, L.nx, L.ny, L.pitch, ry, r, corr);
+    launch_les_s<S, C, W, NT, MODE, QG, LBM_STENCIL_CENTRAL5>(L, src, dst, r, corr);
   else
-    hipLaunchKernelGGL((k_fused_les<S, C, W, LBM_STENCIL_ISO9, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream, src,
-                       dst, L.nx, L.ny, L.pitch, ry, r, corr);
+    launch_les_s<S, C, W, NT, MODE, QG, LBM_STENCIL_ISO9>(L, src, dst, r, corr);
 }
 
 template <typename S, typename C, int W, bool NT, int QG>
