@@ -924,14 +924,14 @@ def main() -> int:
         # values per update: fused 19 + 19; in place synchronous 19 + 4 then
         # 19 + 4 + 19; in place lagged 19 + 4 + 19 + 4.
         variants = [
-            ("les4096", "fused", {}, 38, "k_fused_les<float> (plain closure, Delta=4)"),
-            ("les4096_full", "fused", dict(closure="full"), 38, "k_fused_les<float, ..., full> (density-gradient terms)"),
+            ("les4096", "fused", {}, 38, "k_fused_les_f<float> (plain closure, Delta=4)"),
+            ("les4096_full", "fused", dict(closure="full"), 38, "k_fused_les_f<float, ..., full> (density-gradient terms)"),
             ("les4096_local_iso9", "fused", dict(grad_stencil="local_iso9"), 38,
-             "k_fused_les<float, LOCAL_ISO9> (gradients from non-equilibrium moments)"),
+             "k_fused_les_f<float, LOCAL_ISO9> (gradients from non-equilibrium moments)"),
             ("les4096_aa", "aa", {}, 65, "k_aa_moments + k_aa_les (in place, synchronous)"),
             ("les4096_aa_lagged", "aa_lagged", {}, 46, "k_aa_les_lagged (in place, lagged gradients)"),
             # D2Q9 vector distribution (27 populations): compared with the D2Q5 run
-            ("les4096_d2q9", "fused", dict(mag_lattice="d2q9"), 54, "k_fused_les<float, ..., QG=9> (D2Q9 g)"),
+            ("les4096_d2q9", "fused", dict(mag_lattice="d2q9"), 54, "k_fused_les_f<float, ..., QG=9> (D2Q9 g)"),
             ("dns4096_d2q9", "fused", dict(mag_lattice="d2q9", delta=0.0), 54,
              "k_fused_dns_pair<float, QG=9> (D2Q9 g, closure off)"),
         ]
@@ -977,10 +977,10 @@ def main() -> int:
                 del mom
             extra[key] = rec
             if key == "les4096":
-                # the plain closure beyond the caches: one k_fused_les launch per step
+                # the plain closure beyond the caches: one k_fused_les_f launch per step
                 roofline_plain = {
                     "bound": "hbm",
-                    "kernel": "k_fused_les<float, float, 512, 0, true, 0, 5> (4096^2 LES sweep, plain closure)",
+                    "kernel": "k_fused_les_f<float, 512, 0, true, 0, 5> (4096^2 LES sweep, plain closure)",
                     "achieved": round(bw, 1),
                     "peak": HBM_PEAK_GBS,
                     "unit": "GB/s",
@@ -1036,9 +1036,9 @@ def main() -> int:
                 "correction_every": every, "steps": nsteps,
                 "note": "fine-equivalent: a 4x coarser grid (16x fewer cells) and 4x longer steps "
                         "than the 4096^2 DNS it stands for",
-                "kernels": ("k_cell_inputs + k_mlp_correct (bf16 MFMA) + k_fused_les<..., CORR>" if every == 1
+                "kernels": ("k_cell_inputs + k_mlp_correct (bf16 MFMA) + k_fused_les_f<..., CORR>" if every == 1
                             else f"k_cell_inputs + k_mlp_correct every {every} steps, "
-                                 "k_fused_les<..., CORR> every step")}
+                                 "k_fused_les_f<..., CORR> every step")}
             log(f"learned les 1024^2 {dt} (network every {every}): {ms * 1e3:.1f} us/step")
             del sl
         # one Adam step of the network on 8192 rows (forward, matrix-core
@@ -1126,10 +1126,10 @@ def main() -> int:
             ms = a.elapsed_time(b) / nsteps
             rec = {"mlups": round(lups16 / (ms * 1e-3) / 1e6, 1), "avg_step_us": round(ms * 1e3, 1),
                    "steps": nsteps, "correction_every": every,
-                   "kernels": (f"k_cell_inputs + k_mlp_correct (bf16 MFMA) + k_fused_les<{dt}, ..., CORR>"
+                   "kernels": (f"k_cell_inputs + k_mlp_correct (bf16 MFMA) + k_fused_les_f<{dt}, ..., CORR>"
                                if every == 1 else
                                f"k_cell_inputs + k_mlp_correct every {every} steps, "
-                               f"k_fused_les<{dt}, ..., CORR> every step")}
+                               f"k_fused_les_f<{dt}, ..., CORR> every step")}
             if dt == "bf16" and every == 1:
                 mom16 = torch.empty((5, n16, n16), dtype=torch.float64, device=dev)
                 sp.moments(mom16)

@@ -494,7 +494,8 @@ k_fused_dns(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
   for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * pitch, rw.c, cl.c), encode<S>(v[q]));
 }
 
-// Closure on.  A workgroup of W + 64 lanes owns the column strip
+// Closure on, FP64 (FP32 compute runs k_fused_les_f, the same schedule with
+// buffer addressing).  A workgroup of W + 64 lanes owns the column strip
 // x0 .. x0+W-1 and marches up rows y0 .. y0+ry-1.  The moments (m_x, m_y,
 // B_x - B_ref, B_y - B_ref) of the rows y-1 .. y+2 live in a 4-slot LDS ring
 // indexed by column - x0 + 1.  Lanes 0..W-1 gather, collide and store their
@@ -554,59 +555,9 @@ k_fused_les(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int6
     if (writer) put(2, nxt);
   }
   __syncthreads();
-  if constexpr (std::is_same<S, _Float16>::value && MODE == kClosurePlain) {
-    // FP16 storage, plain closure: the row loop unrolled three times so that
-    // the three rows rotate through fixed registers (8192^2 and 16384^2: 3-7 %
-    // faster than rotating them by copies; with BF16 storage it measured 5-6 %
-    // slower, with FP32 up to 2 % slower, and with the correction or density
-    // terms it needs registers that cost a wave per SIMD).  row(): loads of
-    // row y + 2 into fr, the collision of cu (row y), the ring write of row
-    // y + 2 and the barrier.
-    auto row = [&](C (&cu)[kPop<QG>], C (&fr)[kPop<QG>], int y) __attribute__((always_inline)) {
-      const int s = y - y0 + 1;                 // ring slot of row y is s & 3
-      const bool more = y + 1 < y1;             // row y + 2 is needed for row y + 1
-      if (more && loader) pull_cell<S, C, QG>(src, pitch, rows_of<S, QG>(wrapy(y + 2), ny, pitch), cx, fr);
-      if (valid) {
-        const int sn = (s + 1) & 3, sc = s & 3, ss = (s - 1) & 3, l = tid + 1;
-        C gr[NF][2];
-#pragma unroll
-        for (int k = 0; k < NF; ++k) {
-          grad3x3<C, STENCIL>(ring[sc][k][l + 1], ring[sc][k][l - 1], ring[sn][k][l], ring[ss][k][l],
-                              ring[sn][k][l + 1], ring[sn][k][l - 1], ring[ss][k][l + 1], ring[ss][k][l - 1], gr[k][0],
-                              gr[k][1]);
-        }
-        const Mom<C> m = moments_of<QG>(cu);
-        const C ir = C(1) / (r.rho0 + m.drho);
-        Closure<C> cl;
-        if constexpr (MODE == kClosureFull) {
-          cl = closure_terms_full(gr, m.mx, m.my, r.bx0 + m.dbx, r.by0 + m.dby, ir, r.k2);
-        } else {
-          if constexpr (STENCIL >= LBM_STENCIL_LOCAL_ISO9 && QG == 5)
-            local_gradients(cu, m, r, gr[1][0] - gr[0][1], gr);
-          cl = closure_terms(gr[0][0], gr[0][1], gr[1][0], gr[1][1], gr[2][0], gr[2][1], gr[3][0], gr[3][1], ir,
-                             r.k2);
-        }
-        collide_q<QG>(cu, m, cl, r);
-        const int64_t yo = int64_t(y) * int64_t(kPop<QG>) * pitch * int64_t(sizeof(S));
-#pragma unroll
-        for (int q = 0; q < kPop<QG>; ++q) store<NT>(at(dst + q * pitch, yo, cx.c), encode<S>(cu[q]));
-      }
-      if (more && writer) put((s + 2) & 3, fr);
-      __syncthreads();
-    };
-    for (int y = y0;;) {
-      if (y >= y1) break;
-      row(cur, nn, y++);
-      if (y >= y1) break;
-      row(nxt, cur, y++);
-      if (y >= y1) break;
-      row(nn, nxt, y++);
-    }
-  } else {
-    // the same row body written inline, rows rotated by copies.  The learned
-    // correction of row y + 1 is loaded with row y + 2's populations (its
-    // latency measured 1.0 ms of the 6.2 ms sweep at 16384^2 BF16 when loaded
-    // at its use).
+  {
+    // Rows rotated by copies.  The learned correction of row y + 1 is loaded
+    // with row y + 2's populations, a row ahead of its use.
     const int64_t n = (int64_t)nx * ny;
     float cc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, cn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     auto load_corr = [&](int y, float (&c)[4]) __attribute__((always_inline)) {
