@@ -170,6 +170,53 @@ def test_random_state_steps_fp64(case, schedule, t0):
     assert s.t == t0 + 2
 
 
+# Closure sweep with FP32 arithmetic (FP32, FP16, BF16 storage): strips whose last
+# one is partial (lanes past the last column drop their stores) together with row
+# segments of 2, 3, 4 and 5 rows, so the three-row rotation ends in each phase.
+# Strip width and segment height on a 256-CU device: 1100 columns -> three
+# 512-lane strips (76 columns in the last), 85 segments per strip column; 700 ->
+# three 256-lane strips (188 in the last); 200 -> four 64-lane strips (8 in the last).
+TAIL_SHAPES = [(1100, 425), (1100, 340), (1100, 255), (700, 99), (200, 300)]  # rows 5, 4, 3, 2 (+1), 5
+TAIL_UNIT = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("shape", TAIL_SHAPES, ids=[f"{a}x{b}" for a, b in TAIL_SHAPES])
+def test_closure_sweep_strip_and_segment_tails(dtype, shape):
+    """One step from a random near-rest state (15 % population noise: large
+    closure gradients, Delta = 6) against the oracle started from the rounded
+    state the GPU holds: every population within one rounding of the output
+    (u * max|deviation|) plus FP32 arithmetic noise (1e-7 with FP32 storage,
+    1e-6 with 16-bit storage), while the same step
+    without the closure misses the oracle by at least 10x that bound."""
+    nx, ny = shape
+    _say("tails", dtype, shape)
+    f = perturbed(O.W9, (9, ny, nx), 21, 0.15)
+    g = offset_noise(np.zeros(10), (10, ny, nx), 22, 0.01).reshape(5, 2, ny, nx)
+    s = _sim(nx=nx, ny=ny, nu=0.02, eta=0.03, delta=6.0, dtype=dtype)
+    s.set_state(torch.from_numpy(pack(f, g)), 0)
+    st0 = s.get_state().cpu().numpy()
+    s.step(1)
+    got = s.get_state().cpu().numpy()
+    refs = {}
+    for delta in (6.0, 0.0):
+        o = O.Oracle(nx, ny, 0.02, 0.03, delta=delta)
+        o.set_state(st0[:9], np.stack([st0[9:14], st0[14:19]], axis=1))
+        o.step(1)
+        refs[delta] = pack(*o.state()[:2])
+    ref = refs[6.0]
+    dev = ref.copy()
+    dev[:9] -= O.W9[:, None, None]
+    # FP32 arithmetic noise: measured below 2e-8 on MI355X
+    bound = TAIL_UNIT[dtype] * np.abs(dev).max() + (1e-7 if dtype == "fp32" else 1e-6)
+    err = np.abs(got - ref).max()
+    gap = np.abs(refs[0.0] - ref).max()
+    _say(f"  max error {err:.2e}, bound {bound:.2e}, no-closure gap {gap:.2e}")
+    assert err <= bound
+    assert gap >= 10.0 * bound
+    s.close()
+
+
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
 @pytest.mark.parametrize("schedule", ["fused", "aa"])
 @pytest.mark.parametrize("t0", [0, 3])
