@@ -314,7 +314,7 @@ def jet_study(args, dev, stream) -> int:
     storage rounds the sub-ulp differences between the four periods away,
     so the vortex-pairing modes are never seeded and the L/4 street never
     merges; in FP64 they grow from round-off.  Reported per run at T/4, T/2 and T (DNS 2048^2: twice those
-    steps): kinetic and magnetic energy, enstrophy, max |div B|, and the
+    steps), and every --jet-every steps when given: kinetic and magnetic energy, enstrophy, max |div B|, and the
     exponent of a power-law fit of the total-energy spectrum E_K + E_M over
     two wavenumber ranges; the paper quotes -1.66 for the 1024^2 runs and
     -1.71 for DNS 2048^2 at the final time (its fit range is not stated).
@@ -350,7 +350,10 @@ def jet_study(args, dev, stream) -> int:
         sim = Sim(nx=n, ny=n, nu=nu, eta=nu, delta=delta, dtype=dtype, b_ref=(0.0, B0), device=dev, stream=stream,
                   **variant)
         sim.init_sech2_jet(U0=U0, B0=B0, pert=0.01, k=4)
-        marks = sorted({steps // 4, steps // 2, steps})
+        marks = {steps // 4, steps // 2, steps}
+        if args.jet_every > 0:  # and every jet_every LES steps (scaled like the run's time)
+            marks |= set(range(args.jet_every * mult, steps + 1, args.jet_every * mult))
+        marks = sorted(marks)
         rec = {"grid": n, "delta": delta, "nu": nu, "eta": nu, "steps": steps, "snapshots": {}}
         chunk = max(1, min(20000 * mult, steps // 8))
         t0 = time.perf_counter()
@@ -778,6 +781,8 @@ def main() -> int:
                          "steps (the paper's T is 780000) and DNS 2048^2 of 2T (one JSON line)")
     ap.add_argument("--jet-runs", default="dns1024,les1024_d1,les1024_d2,dns2048",
                     help="comma-separated subset of the jet study's runs")
+    ap.add_argument("--jet-every", type=int, default=0, metavar="STEPS",
+                    help="jet study: also take spectra every STEPS LES steps (twice that for DNS 2048^2)")
     ap.add_argument("--jet-dtype", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--jet-variant", default="default", choices=["default", "paper"],
                     help="paper: D2Q9 magnetic distribution and the density-gradient closure")
