@@ -1177,10 +1177,10 @@ k_moments_out(const S* __restrict__ base, double* __restrict__ out, int nx, int 
 // one column per row, u_x, u_y, B_x, B_y go to the wave's four-row LDS ring,
 // and the row above the newest one is finished from the ring.  The strip's
 // outer two columns and the rows just outside the segment are gathered for
-// their neighbours only: 62 output columns per strip.  Measured at 1024^2,
-// 8192^2 and 16384^2 (FP32, BF16, FP16 storage): 3-13 % faster than 256-lane
-// strips with a workgroup barrier per row; 8-row segments within 6 % of the
-// best of 4 to 64 rows at every size.
+// their neighbours only: 62 output columns per strip.  FP64 storage runs this
+// kernel; FP32 compute runs k_cell_inputs_f below, whose aligned strips store
+// whole lines (16384^2 BF16: 2.73 ms against 2.94 ms for this form, whose
+// 62-column strips split the lines they store with their neighbours).
 constexpr int kCellInW = 64, kCellInRows = 8;
 
 __host__ __device__ constexpr int cell_input_strips(int nx) { return (nx + kCellInW - 3) / (kCellInW - 2); }
@@ -1245,6 +1245,116 @@ k_cell_inputs(const S* __restrict__ src, int nx, int ny, int64_t pitch, RestRef 
     pbx = bx;
     pby = by;
   }
+}
+
+// Input vectors with FP32 compute (FP32, FP16, BF16 storage): the strip
+// schedule of k_fused_les_f.  A workgroup of W + 64 lanes owns the columns
+// x0 .. x0+W-1 (so each row's input vectors are whole aligned lines) and walks
+// the rows y0 .. y1-1.  A lane keeps rho, u, B of the rows y-1, y, y+1 of its
+// own column in registers and reads u_y, B_y of its two neighbour columns from
+// an LDS row (two slots by row parity, one barrier per row); the last wave
+// gathers the two halo columns.  Rows are gathered two ahead of their use with
+// buffer loads, three register sets rotate through a three-times unrolled
+// loop, and lanes past the strip's last column drop their stores through
+// kDropOffset, so the row body has no branch around a memory operation.  The
+// arithmetic is k_cell_inputs' (same expressions, same results).
+struct CellFields {
+  float r, ux, uy, bx, by;
+};
+
+template <typename S, int W>
+__global__ void __launch_bounds__(W + 64)
+k_cell_inputs_f(const S* __restrict__ src, int nx, int ny, int64_t pitch, int ry, RestRef ref,
+                const char* __restrict__ pk, CellIn* __restrict__ out) {
+  using C = float;
+  constexpr int NP = kPop<5>;
+  __shared__ float rowbuf[2][2][W + 3];  // row parity, field (u_y, B_y), column - x0 + 1 (W + 2: spare)
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * W;
+  const int last = min(x0 + W, nx) - 1;
+  const int y0 = blockIdx.y * ry;
+  const int y1 = min(y0 + ry, ny);
+  const uint32_t pq = uint32_t(pitch) * uint32_t(sizeof(S));
+  const lbm_mlp_norm* nm = reinterpret_cast<const lbm_mlp_norm*>(pk + kPkNorm);
+  auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
+  auto ahead = [&](int y) { return wrapy(y <= y1 ? y : y1); };  // rows past y1 are not needed
+
+  const bool halo = tid >= W;
+  const int hl = tid - W;
+  const bool valid = !halo && x0 + tid <= last;
+  const int xc = halo ? (hl == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (last + 1 == nx ? 0 : last + 1))
+                      : (valid ? x0 + tid : last);
+  const int widx = halo ? (hl == 0 ? 0 : (hl == 1 ? last - x0 + 2 : W + 2)) : (valid ? tid + 1 : W + 2);
+  const Cols cx = cols_of<S>(xc, nx);
+  const uint32_t xo_store = valid ? uint32_t(x0 + tid) * uint32_t(sizeof(CellIn)) : kDropOffset;
+  const uint32_t orow = uint32_t(nx) * uint32_t(sizeof(CellIn));
+
+  auto pull = [&](int y, RawCell<S, 5>& c) __attribute__((always_inline)) {
+    pull_raw<S, 5>(src, pq, wrapy(y - 1), y, wrapy(y + 1), cx, c);
+  };
+  auto fields = [&](const RawCell<S, 5>& c, CellFields& f) __attribute__((always_inline)) {
+    C v[NP];
+    decode_raw<S, C, 5>(c, v);
+    const Mom<C> m = moments19(v);
+    f.r = float(C(ref.rho0) + m.drho);
+    f.ux = float(m.mx) / f.r;
+    f.uy = float(m.my) / f.r;
+    f.bx = float(C(ref.bx0) + m.dbx);
+    f.by = float(C(ref.by0) + m.dby);
+  };
+  auto share = [&](int y, const CellFields& f) __attribute__((always_inline)) {
+    rowbuf[y & 1][0][widx] = f.uy;
+    rowbuf[y & 1][1][widx] = f.by;
+  };
+
+  // Row y: fm, fc hold rows y - 1 and y, fn receives row y + 1 from rn (loaded
+  // two rows ago); rt receives row y + 3.
+  auto row = [&](const CellFields& fm, const CellFields& fc, CellFields& fn, const RawCell<S, 5>& rn,
+                 RawCell<S, 5>& rt, int y) __attribute__((always_inline)) {
+    pull(ahead(y + 3), rt);
+    __builtin_amdgcn_sched_barrier(0);
+    fields(rn, fn);
+    share(y + 1, fn);
+    {
+      // the halo wave runs the same body on column 1 and drops its stores
+      const int l = halo ? 1 : tid + 1;
+      const float om = 0.5f * (rowbuf[y & 1][0][l + 1] - rowbuf[y & 1][0][l - 1]) - 0.5f * (fn.ux - fm.ux);
+      const float jz = 0.5f * (rowbuf[y & 1][1][l + 1] - rowbuf[y & 1][1][l - 1]) - 0.5f * (fn.bx - fm.bx);
+      const float f[7] = {fc.r, fc.ux, fc.uy, fc.bx, fc.by, om, jz};
+      bool bad = false;
+      f32x8 z;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        z[i] = (f[i] - nm->shift[i]) * nm->scale[i];
+        bad = bad || !(fabsf(z[i]) <= kOodLimit);  // NaN counts as out of range
+      }
+      z[7] = 0.0f;
+      u32x4 w = __builtin_bit_cast(u32x4, to_bf16x8(z));
+      w[3] = (w[3] & 0xFFFFu) | (bad ? unsigned(kCellOutOfRange) << 16 : 0u);
+      const __amdgpu_buffer_rsrc_t d = row_rsrc(reinterpret_cast<char*>(out) + int64_t(y) * orow, orow);
+      __builtin_amdgcn_raw_buffer_store_b128(w, d, int(xo_store), 0, 0);
+    }
+    __syncthreads();
+  };
+
+  CellFields fa, fb, fc;
+  RawCell<S, 5> ra, rb, rc;
+  pull(wrapy(y0 - 1), ra);
+  fields(ra, fa);
+  pull(y0, rb);
+  fields(rb, fb);
+  share(y0, fb);
+  pull(ahead(y0 + 1), ra);
+  pull(ahead(y0 + 2), rb);
+  __syncthreads();
+  int y = y0;
+  for (; y + 3 <= y1; y += 3) {  // one straight-line block of three rows
+    row(fa, fb, fc, ra, rc, y);
+    row(fb, fc, fa, rb, ra, y + 1);
+    row(fc, fa, fb, rc, rb, y + 2);
+  }
+  if (y < y1) row(fa, fb, fc, ra, rc, y);
+  if (y + 1 < y1) row(fb, fc, fa, rb, ra, y + 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1542,10 +1652,25 @@ template <typename S>
 // so the state is always in the pull layout here.
 static hipError_t cell_inputs_typed(const Launch& L, int64_t t, CellIn* out) {
   if (layout_at(L, t) != kLayoutPull) return hipErrorInvalidValue;
-  const int strips = cell_input_strips(L.nx);
   const char* pk = static_cast<const char*>(L.work) + L.off_mlp;
-  hipLaunchKernelGGL((k_cell_inputs<S>), dim3((strips + 3) / 4, (L.ny + kCellInRows - 1) / kCellInRows), dim3(256),
-                     0, L.stream, buffer_at<S>(L, t), L.nx, L.ny, L.pitch, rest_ref(L), strips, pk, out);
+  if constexpr (sizeof(typename ComputeOf<S>::type) == 4) {
+    const int W = L.nx >= 1024 ? 512 : (L.nx >= 256 ? 256 : 64);
+    const int ry = fused_rows(L.nx, L.ny, W, L.cus, 128);
+    const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
+    if (W == 512)
+      hipLaunchKernelGGL((k_cell_inputs_f<S, 512>), g, dim3(512 + 64), 0, L.stream, buffer_at<S>(L, t), L.nx, L.ny,
+                         L.pitch, ry, rest_ref(L), pk, out);
+    else if (W == 256)
+      hipLaunchKernelGGL((k_cell_inputs_f<S, 256>), g, dim3(256 + 64), 0, L.stream, buffer_at<S>(L, t), L.nx, L.ny,
+                         L.pitch, ry, rest_ref(L), pk, out);
+    else
+      hipLaunchKernelGGL((k_cell_inputs_f<S, 64>), g, dim3(64 + 64), 0, L.stream, buffer_at<S>(L, t), L.nx, L.ny,
+                         L.pitch, ry, rest_ref(L), pk, out);
+  } else {
+    const int strips = cell_input_strips(L.nx);
+    hipLaunchKernelGGL((k_cell_inputs<S>), dim3((strips + 3) / 4, (L.ny + kCellInRows - 1) / kCellInRows),
+                       dim3(256), 0, L.stream, buffer_at<S>(L, t), L.nx, L.ny, L.pitch, rest_ref(L), strips, pk, out);
+  }
   return hipGetLastError();
 }
 
