@@ -251,6 +251,9 @@ __device__ __forceinline__ void collide19(C v[kQ], const Mom<C>& m, const Closur
 template <typename C>
 __device__ __forceinline__ void local_gradients(const C v[kQ], const Mom<C>& m, const Rates<C>& r, C wm,
                                                 C gr[4][2]) {
+  // evaluated as written (no contraction into FMAs), so every copy of an
+  // unrolled row body gives the same bits
+#pragma clang fp contract(off)
   const C rho = r.rho0 + m.drho;
   const C ir = C(1) / rho;
   const C bx = r.bx0 + m.dbx, by = r.by0 + m.dby;
@@ -1569,7 +1572,12 @@ static bool streaming_stores(const Launch& L) {
 // FP32 compute runs k_fused_les_f, FP64 k_fused_les.
 template <typename S, typename C, int W, bool NT, int MODE, int QG, int STENCIL>
 static void launch_les_s(const Launch& L, const S* src, S* dst, const Rates<C>& r, const float* corr) {
-  const int ry = fused_rows(L.nx, L.ny, W, L.cus, sizeof(C) == 4 ? 128 : 64);
+  // Segments sized for one workgroup per compute unit, two for k_fused_les_f
+  // beyond the Infinity Cache (two fit a compute unit; measured 4096^2 FP32
+  // 448 against 466 us, 8192^2 within 1 % either way, while the cache-resident
+  // 1024^2 sweep prefers one: 28.7 against 31.4 us).
+  const int per_cu = (sizeof(C) == 4 && NT) ? 2 : 1;
+  const int ry = fused_rows(L.nx, L.ny, W, L.cus * per_cu, sizeof(C) == 4 ? 128 : 64);
   const dim3 g((L.nx + W - 1) / W, (L.ny + ry - 1) / ry);
   if constexpr (sizeof(C) == 4)
     hipLaunchKernelGGL((k_fused_les_f<S, W, STENCIL, NT, MODE, QG>), g, dim3(W + 64), 0, L.stream, src, dst, L.nx,
