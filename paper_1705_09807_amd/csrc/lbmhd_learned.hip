@@ -237,7 +237,7 @@ k_mlp_correct(const CellIn* __restrict__ in, const char* __restrict__ pk, float*
 // already.  (Two terms, 16 bits, left 1e-4 relative errors in G1 over 5000
 // rows, where the row sums cancel.)  Each wave owns half of every weight gradient and accumulates it
 // over its workgroup's chunks in a fixed order; per-workgroup partials are
-// summed in workgroup order by k_mlp_reduce.
+// summed in a fixed order by k_mlp_reduce_groups and k_mlp_reduce.
 // ---------------------------------------------------------------------------
 constexpr int kTrainChunk = 64;
 constexpr int kTrainBlocksMax = 1024;
@@ -493,19 +493,48 @@ k_mlp_train(const char* __restrict__ pk, const float* __restrict__ p, const floa
   }
 }
 
-// Sum of the partial gradients in workgroup order (and of the loss partials).
+// Sum of the partial gradients (and of the loss partials) in a fixed order,
+// in two launches so that the loads of many partials are in flight at once:
+// each run of kReduceGroup consecutive partials is summed in order into its
+// first partial (k_mlp_reduce_groups), then those group sums in order
+// (k_mlp_reduce).  (One thread summing all partials in order, one launch,
+// waited on each batch of loads: 34 us for 128 partials.)
+constexpr int kReduceGroup = 16;
+
+__global__ void __launch_bounds__(256)
+k_mlp_reduce_groups(float* __restrict__ partial, int nparts, double* __restrict__ loss_part) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int b0 = blockIdx.y * kReduceGroup;
+  const int nb = min(kReduceGroup, nparts - b0);
+  if (i < LBM_MLP_PARAMS) {
+    float v[kReduceGroup];
+#pragma unroll
+    for (int k = 0; k < kReduceGroup; ++k) v[k] = k < nb ? partial[(int64_t)(b0 + k) * kGradStride + i] : 0.0f;
+    float g = v[0];
+#pragma unroll
+    for (int k = 1; k < kReduceGroup; ++k)
+      if (k < nb) g += v[k];
+    partial[(int64_t)b0 * kGradStride + i] = g;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && loss_part) {
+    double a = loss_part[b0];
+    for (int k = 1; k < nb; ++k) a += loss_part[b0 + k];
+    loss_part[b0] = a;
+  }
+}
+
 __global__ void __launch_bounds__(256)
 k_mlp_reduce(const float* __restrict__ partial, int nparts, float* __restrict__ grad,
              const double* __restrict__ loss_part, float* __restrict__ loss_out, float loss_norm) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < LBM_MLP_PARAMS) {
     float g = 0.0f;
-    for (int b = 0; b < nparts; ++b) g += partial[(int64_t)b * kGradStride + i];
+    for (int b = 0; b < nparts; b += kReduceGroup) g += partial[(int64_t)b * kGradStride + i];
     grad[i] = g;
   }
   if (i == 0 && loss_out) {
     double a = 0.0;
-    for (int b = 0; b < nparts; ++b) a += loss_part[b];
+    for (int b = 0; b < nparts; b += kReduceGroup) a += loss_part[b];
     *loss_out = float(a * double(loss_norm));
   }
 }
@@ -1019,6 +1048,9 @@ hipError_t launch_mlp_gradient(const float* params, const lbm_mlp_norm* norm, co
   hipError_t e = launch_mlp_pack(params, norm, w, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(128), 0, st, w, params, x, t, idx, batch, partial, lpart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_reduce_groups, dim3((LBM_MLP_PARAMS + 255) / 256, (blocks + kReduceGroup - 1) / kReduceGroup),
+                     dim3(256), 0, st, partial, blocks, lpart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_mlp_reduce, dim3((LBM_MLP_PARAMS + 255) / 256), dim3(256), 0, st, partial, blocks, grad, lpart,
                      loss, float(1.0 / (double(batch) * 4.0)));
