@@ -394,6 +394,10 @@ _CORR_CASES = [(nx, ny, ood) for nx, ny in [(96, 64), (70, 37), (67, 33), (523, 
 # on a grid this small every 3x3 patch reaches the density extremes, so the
 # out-of-range case would flag every cell: the in-range case only
 _CORR_CASES.append((24, 18, False))
+# taller grids whose last strip of the FP32-compute input-vector kernel is partial
+# (512-, 256- and 64-lane strips) while its row segments run the three-row loop and
+# end with one or two rows (segments of 5, 4, 2 and 5 rows on a 256-CU device)
+_CORR_CASES += [(1100, 425, False), (1100, 340, False), (700, 99, False), (200, 300, False)]
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
@@ -445,13 +449,14 @@ def test_isolated_out_of_range_cells_zero_exactly_their_neighbourhoods(dtype):
     so all nine positions are checked on their own (inside a blob of flagged
     cells a missed position is hidden by the others).  Culprits sit at the
     grid's corner, at network-tile edges (every 64 columns, 16 rows) and at
-    the input-vector kernel's strip edges (every 254 columns)."""
+    the FP32-compute input-vector kernel's strip edges (255/256, 511/512)."""
     G = _gpu()
     nx, ny = 523, 77
     f, g = _smooth_state(nx, ny, 71)
     p = _params(72)
     shift, scale, out_scale, s64, c64 = _state_norm(f, g)
-    culprits = [(0, 0), (5, 63), (16, 64), (31, 127), (30, 253), (45, 254), (60, 508), (76, 300), (47, 522)]
+    culprits = [(0, 0), (5, 63), (16, 64), (31, 127), (30, 253), (45, 254), (60, 508), (76, 300), (47, 522),
+                (20, 255), (38, 256), (68, 511), (10, 512)]
     rho = f.sum(axis=0)
     want_ood = np.zeros((ny, nx), dtype=bool)
     for cy, cx in culprits:
