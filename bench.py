@@ -1200,6 +1200,31 @@ def main() -> int:
     }
     del dns
     torch.cuda.empty_cache()
+    if args.copy_bytes == 0:
+        # what this GPU sustains for a plain stream: a device-to-device copy (torch
+        # copy_, the runtime's copy kernel) of the bytes one 4096^2 FP32 sweep moves,
+        # 1.275 GB read and 1.275 GB written.  Skipped in counter runs, whose
+        # calibration copy (--copy-bytes) must be the only large copy.
+        nb = 19 * 4 * DNS_N * DNS_N
+        ca = torch.empty(nb, dtype=torch.uint8, device=dev)
+        cb = torch.empty_like(ca)
+        cb.copy_(ca)
+        torch.cuda.synchronize(dev)
+        e0, e1 = ev(), ev()
+        reps = 20
+        e0.record(stream)
+        for _ in range(reps):
+            cb.copy_(ca)
+        e1.record(stream)
+        torch.cuda.synchronize(dev)
+        ms = e0.elapsed_time(e1) / reps
+        gbps = 2 * nb / (ms * 1e-3) / 1e9
+        extra["copy_d2d_4096sq_fp32_bytes"] = {
+            "avg_us": round(ms * 1e3, 1), "GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBS, 4),
+            "note": "device-to-device copy of 1.275 GB (torch copy_): the bytes of one 4096^2 FP32 sweep"}
+        log(f"copy of {nb / 1e9:.3f} GB: {ms * 1e3:.1f} us, {gbps:.0f} GB/s")
+        del ca, cb
+        torch.cuda.empty_cache()
     if args.copy_bytes > 0:
         a = torch.empty(args.copy_bytes, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
