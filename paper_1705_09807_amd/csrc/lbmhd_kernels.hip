@@ -643,7 +643,9 @@ __device__ __forceinline__ void decode_raw(const RawCell<S, QG>& c, C* v) {
 // (stride 0) of num_records = the lattice row's bytes; every access of a row
 // lies inside it, except the stores of lanes that own no output column,
 // which take an offset past num_records: the hardware's range check drops
-// them, so the row body has no branch around its stores.
+// them, so the row body has no branch around its stores.  (nx <= 32768, as
+// lbm_create requires, keeps a lattice row below 27 * 32768 * 4 B = 3.5 MB
+// and a row of input vectors at 512 KB, far below kDropOffset.)
 constexpr uint32_t kDropOffset = 0x80000000u;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
