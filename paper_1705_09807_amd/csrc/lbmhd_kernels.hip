@@ -285,6 +285,8 @@ __device__ __forceinline__ void local_gradients(const C v[kQ], const Mom<C>& m, 
 
 // Two consecutive stored values (one aligned load or store).
 template <typename S> using Vec2 = S __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
 // Addressing.  A buffer is ny lattice rows, each holding the NPOP population
 // rows of that lattice row one after another, `pitch` elements apart:
@@ -410,74 +412,6 @@ k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
 }
 
 template <typename S> using Vec4 = S __attribute__((ext_vector_type(4)));
-
-// Four horizontally adjacent cells x .. x + 3 (x a multiple of 4, nx too):
-// every population in one aligned four-element load, plus one load of the
-// neighbour column for the populations that stream along x.
-template <typename S, typename C>
-__device__ __forceinline__ void pull_quad(const S* __restrict__ src, int64_t pitch, int nx, const Rows& rw, int x,
-                                          C (&v)[4][kQ]) {
-  using V4 = Vec4<S>;
-  const uint32_t es = uint32_t(sizeof(S));
-  const uint32_t x0 = uint32_t(x) * es;
-  const uint32_t xw = uint32_t(x == 0 ? nx - 1 : x - 1) * es;
-  const uint32_t x4 = uint32_t(x + 4 == nx ? 0 : x + 4) * es;
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int64_t yo = qcy(q) > 0 ? rw.s : (qcy(q) < 0 ? rw.n : rw.c);
-    const S* pq = src + q * pitch;
-    const V4 t = *reinterpret_cast<const V4*>(at(pq, yo, x0));
-    if (qcx(q) == 0) {
-      v[0][q] = decode<C>(t.x);
-      v[1][q] = decode<C>(t.y);
-      v[2][q] = decode<C>(t.z);
-      v[3][q] = decode<C>(t.w);
-    } else if (qcx(q) > 0) {  // the cells pull from x - 1
-      v[0][q] = decode<C>(*at(pq, yo, xw));
-      v[1][q] = decode<C>(t.x);
-      v[2][q] = decode<C>(t.y);
-      v[3][q] = decode<C>(t.z);
-    } else {  // from x + 1
-      v[0][q] = decode<C>(t.y);
-      v[1][q] = decode<C>(t.z);
-      v[2][q] = decode<C>(t.w);
-      v[3][q] = decode<C>(*at(pq, yo, x4));
-    }
-  }
-}
-
-// Closure off, 16-bit storage, nx a multiple of 4: four cells per thread, so
-// every population moves in one aligned 8-byte load and store per thread (plus
-// one 2-byte load of the neighbour column for those that stream along x).
-// Measured 7-9 % faster than the pair kernel at 8192^2 with FP16 and BF16
-// storage (slower with FP32, whose pair loads are already 8 bytes).
-template <typename S, typename C, bool NT>
-__global__ void __launch_bounds__(64)
-k_fused_dns_quad(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t pitch, Rates<C> r) {
-  using V4 = Vec4<S>;
-  const int x = (blockIdx.x * 64 + threadIdx.x) * 4;
-  const int y = blockIdx.y;
-  if (x >= nx) return;
-  const Rows rw = rows_of<S>(y, ny, pitch);
-  const uint32_t x0 = uint32_t(x) * uint32_t(sizeof(S));
-  C v[4][kQ];
-  pull_quad<S, C>(src, pitch, nx, rw, x, v);
-  const Closure<C> cl = {C(0), C(0), C(0), C(0)};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const Mom<C> m = moments19(v[k]);
-    collide19(v[k], m, cl, r);
-  }
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    V4 t;
-    t.x = encode<S>(v[0][q]);
-    t.y = encode<S>(v[1][q]);
-    t.z = encode<S>(v[2][q]);
-    t.w = encode<S>(v[3][q]);
-    store<NT>(reinterpret_cast<V4*>(at(dst + q * pitch, rw.c, x0)), t);
-  }
-}
 
 // Closure off, any nx: one cell per thread, row segments of 256 cells.
 template <typename S, typename C, bool NT, int QG>
@@ -666,6 +600,27 @@ __device__ __forceinline__ void buf_store(S v, __amdgpu_buffer_rsrc_t r, uint32_
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff), int(soff), aux);
 }
 
+// Buffer loads and stores of T (4, 8 or 16 bytes: one, two or four stored values).
+template <typename T>
+__device__ __forceinline__ T buf_load_v(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+  else if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), int(soff), 0));
+}
+template <typename T, bool NT>
+__device__ __forceinline__ void buf_store_v(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  constexpr int aux = NT ? 2 : 0;
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff), int(soff), aux);
+  else if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, int(voff), int(soff), aux);
+  else
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, int(voff), int(soff), aux);
+}
+
 // f_q(x, y) = src[q][x - c_q][y - c_q] of one cell, as stored; ys, yc, yn
 // are the (periodic) rows y - 1, y, y + 1, pq the bytes between population
 // rows.
@@ -682,6 +637,71 @@ __device__ __forceinline__ void pull_raw(const S* __restrict__ src, uint32_t pq,
     const uint32_t xo = qcx<QG>(q) > 0 ? cl.w : (qcx<QG>(q) < 0 ? cl.e : cl.c);
     const __amdgpu_buffer_rsrc_t rr = qcy<QG>(q) > 0 ? rs : (qcy<QG>(q) < 0 ? rn : rc);
     c.v[q] = buf_load<S>(rr, xo, uint32_t(q) * pq);
+  }
+}
+
+// Closure off, 16-bit storage, nx a multiple of 4: four cells per thread, so
+// every population moves in one aligned 8-byte load and store per thread (plus
+// one 2-byte load of the neighbour column for those that stream along x),
+// addressed through a resource per lattice row.  Measured 7-9 % faster than
+// two cells per thread at 8192^2 with FP16 and BF16 storage (slower with FP32,
+// whose pair loads are already 8 bytes), and the buffer form 0-4 % faster
+// than per-lane addresses (BF16 8192^2 884-893 against 901-916 us; for the
+// FP32 pair kernel it measured up to 3 % slower, so that one keeps them).
+template <typename S, typename C, bool NT>
+__global__ void __launch_bounds__(64)
+k_fused_dns_quad(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t pitch, Rates<C> r) {
+  using V4 = Vec4<S>;
+  const int x = (blockIdx.x * 64 + threadIdx.x) * 4;
+  const int y = blockIdx.y;
+  if (x >= nx) return;
+  const uint32_t es = uint32_t(sizeof(S)), pq = uint32_t(pitch) * es, rowb = uint32_t(kQ) * pq;
+  const char* b = reinterpret_cast<const char*>(src);
+  const int ys = y == 0 ? ny - 1 : y - 1, yn = y + 1 == ny ? 0 : y + 1;
+  const __amdgpu_buffer_rsrc_t rs = row_rsrc(b + int64_t(ys) * rowb, rowb);
+  const __amdgpu_buffer_rsrc_t rc = row_rsrc(b + int64_t(y) * rowb, rowb);
+  const __amdgpu_buffer_rsrc_t rn = row_rsrc(b + int64_t(yn) * rowb, rowb);
+  const uint32_t x0 = uint32_t(x) * es;
+  const uint32_t xw = uint32_t(x == 0 ? nx - 1 : x - 1) * es;
+  const uint32_t x4 = uint32_t(x + 4 == nx ? 0 : x + 4) * es;
+  C v[4][kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const __amdgpu_buffer_rsrc_t rr = qcy(q) > 0 ? rs : (qcy(q) < 0 ? rn : rc);
+    const uint32_t so = uint32_t(q) * pq;
+    const V4 t = buf_load_v<V4>(rr, x0, so);
+    if (qcx(q) == 0) {
+      v[0][q] = decode<C>(t.x);
+      v[1][q] = decode<C>(t.y);
+      v[2][q] = decode<C>(t.z);
+      v[3][q] = decode<C>(t.w);
+    } else if (qcx(q) > 0) {
+      v[0][q] = decode<C>(buf_load<S>(rr, xw, so));
+      v[1][q] = decode<C>(t.x);
+      v[2][q] = decode<C>(t.y);
+      v[3][q] = decode<C>(t.z);
+    } else {
+      v[0][q] = decode<C>(t.y);
+      v[1][q] = decode<C>(t.z);
+      v[2][q] = decode<C>(t.w);
+      v[3][q] = decode<C>(buf_load<S>(rr, x4, so));
+    }
+  }
+  const Closure<C> cl = {C(0), C(0), C(0), C(0)};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const Mom<C> m = moments19(v[k]);
+    collide19(v[k], m, cl, r);
+  }
+  const __amdgpu_buffer_rsrc_t d = row_rsrc(reinterpret_cast<char*>(dst) + int64_t(y) * rowb, rowb);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    V4 t;
+    t.x = encode<S>(v[0][q]);
+    t.y = encode<S>(v[1][q]);
+    t.z = encode<S>(v[2][q]);
+    t.w = encode<S>(v[3][q]);
+    buf_store_v<V4, NT>(t, d, x0, uint32_t(q) * pq);
   }
 }
 
