@@ -1074,7 +1074,7 @@ def main() -> int:
         tflop = 8192 * (16768 + 2 * 64 * 64 + 16768) / (ms * 1e-3) / 1e12
         extra["mlp_train_step_8192"] = {"avg_step_us": round(ms * 1e3, 1), "rows": 8192,
                                         "tflops_fwd_bwd": round(tflop, 2),
-                                        "kernels": "k_mlp_train (matrix cores) + k_mlp_reduce + k_mlp_adam"}
+                                        "kernels": "k_mlp_pack + k_mlp_train (matrix cores) + k_mlp_reduce_groups + k_mlp_reduce + k_mlp_adam"}
         log(f"mlp train step (8192 rows): {ms * 1e3:.1f} us")
         del mlp, packed, Xt, Tt
 
