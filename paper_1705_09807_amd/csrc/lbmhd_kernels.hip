@@ -1698,8 +1698,10 @@ static void launch_fused(const Launch& L, const S* src, S* dst, const Rates<C>& 
   }
   // Strip width: 512 lanes for wide grids with FP32 compute, 256 otherwise (the
   // LDS ring of a 512-lane FP64 strip would exceed 64 KB), 64 for narrow
-  // grids.  Measured with the lattice-row layout at 4096^2 .. 16384^2: 512
-  // lanes beat 256 by 2-4 % with FP32 storage and by up to 1.6x with FP16.
+  // grids.  Measured with the lattice-row layout and XCD-contiguous numbering:
+  // 256-lane strips (two or four workgroups per compute unit) against 512 take
+  // 0-10 % longer with FP32 storage at 4096^2 and 8192^2 and 16-18 % longer
+  // with FP16 at 8192^2 (with the earlier two-dimensional grids: up to 1.6x).
   if constexpr (sizeof(C) == 4) {
     if (L.nx >= 1024) {
       launch_les<S, C, 512, NT, QG>(L, src, dst, r, corr);
