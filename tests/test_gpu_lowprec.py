@@ -69,10 +69,13 @@ def test_initial_state(dtype):
 @pytest.mark.parametrize("dtype", ["fp16", "bf16"])
 @pytest.mark.parametrize("schedule", ["fused", "aa"])
 @pytest.mark.parametrize("delta", [0.0, 2.0])
-@pytest.mark.parametrize("shape", [(33, 17), (68, 12), (258, 5)])
+@pytest.mark.parametrize("shape", [(33, 17), (68, 12), (258, 5), (300, 7)])
 def test_one_step_from_random_state(dtype, schedule, delta, shape):
     """Odd widths (one cell per thread), widths divisible by 4 (the four-cell
-    closure-off sweep), a width of two mod 4 (the two-cell one)."""
+    closure-off sweep), a width of two mod 4 (the two-cell one).  300 x 7:
+    two row segments per row, the second ragged, and 14 workgroups in the
+    one-dimensional grids (not a multiple of the 8 XCDs the workgroups are
+    numbered over); likewise two closure-sweep strips, the second ragged."""
     nx, ny = shape
     f = perturbed(O.W9, (9, ny, nx), 5, 0.15)
     g = offset_noise(np.zeros(10), (10, ny, nx), 6, 0.01).reshape(5, 2, ny, nx)
