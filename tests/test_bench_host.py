@@ -40,6 +40,22 @@ def test_traffic_summaries_parse(tmp_path, monkeypatch):
     assert bench.measured_traffic("old", 100) is None
 
 
+def test_source_hash_ignores_comments_only(tmp_path, monkeypatch):
+    """Editing comments or blank space keeps a counter summary valid; any
+    change of code invalidates it."""
+    def h(text):
+        f = tmp_path / "k.hip"
+        f.write_text(text)
+        monkeypatch.setattr(bench, "KERNEL_SRC", str(f))
+        return bench.kernel_source_hash()
+
+    base = h("int f(int a) {\n  return a + 1;  // one\n}\n")
+    assert h("/* about f */\nint f(int a) {\n\n    return a + 1;  // two\n}") == base
+    assert h("int f(int a) {\n  return a + 2;  // one\n}\n") != base
+    # spacing inside a line counts (conservative: a reformatting invalidates too)
+    assert h("int f(int a) {\n  return a+1;\n}\n") != base
+
+
 def test_correction_interval_must_be_positive():
     """--corr-every below 1 is an argument error (exit 2) before touching a GPU."""
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--corr-every", "0"], capture_output=True,
