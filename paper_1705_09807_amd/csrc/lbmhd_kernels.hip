@@ -647,7 +647,8 @@ __device__ __forceinline__ void pull_raw(const S* __restrict__ src, uint32_t pq,
 // XCD takes one contiguous range of work items, so neighbouring row segments
 // (or strips) run side by side on one XCD and the cache lines at their common
 // edge, which both read, come from that XCD's L2 instead of two.  A bijection
-// of 0 .. nb-1 for any nb.  Measured with the same results: the closure sweep
+// of 0 .. nb-1 for any nb, so results do not depend on the XCD count of the
+// device or partition; only the cache benefit assumes eight.  Measured with the same results: the closure sweep
 // at 8192^2 FP32 1701-1750 against 1761-1782 us (its reads 1.03x instead of
 // 1.12x the algorithmic bytes at 4096^2), the 16-bit DNS sweep at 8192^2
 // 844-862 against 916-918 us (FP16); the FP32 pair kernel was 3 % slower with
