@@ -17,12 +17,12 @@ from oracle import lbmhd_oracle as O
 from seeded_inputs import assemble_rough
 
 
-def window(x: int, y: int, n: int, steps: int):
-    """Column and row indices of the periodic window around (x, y), and the
-    window position of (x, y)."""
+def window(x: int, y: int, n: int, steps: int, ny: int | None = None):
+    """Column and row indices of the periodic window around (x, y) on an
+    n x ny grid (ny = n if not given), and the window position of (x, y)."""
     half = 2 * steps + 1
     idx = np.arange(2 * half + 1) - half
-    return (x + idx) % n, (y + idx) % n, half
+    return (x + idx) % n, (y + idx) % (n if ny is None else ny), half
 
 
 def pack(f, g):
@@ -40,9 +40,11 @@ def oracle_cell(mom, steps: int, lattice: str = "d2q5", **oracle_kw) -> np.ndarr
     return pack(*o.state()[:2])[:, half, half]
 
 
-def check_rough_sampled(got, pts, n, steps, factors, tol, gaps=(), lattice="d2q5", say=print, **oracle_kw):
+def check_rough_sampled(got, pts, n, steps, factors, tol, gaps=(), lattice="d2q5", say=print, ny=None,
+                        **oracle_kw):
     """got [npop, npts]: the GPU's populations at the sampled cells pts after
-    `steps` steps from the equilibria of the rough fields `factors`.  Each
+    `steps` steps from the equilibria of the rough fields `factors` on an
+    n x ny grid (ny = n if not given).  Each
     cell must be within `tol` (max abs) of the oracle with `oracle_kw`; for
     each (label, kw, factor) in `gaps`, the oracle with those keyword changes
     must sit at least factor * tol away at every sampled cell.  Returns the
@@ -51,7 +53,7 @@ def check_rough_sampled(got, pts, n, steps, factors, tol, gaps=(), lattice="d2q5
     smallest = {label: np.inf for label, _, _ in gaps}
     need = {label: factor * tol for label, _, factor in gaps}
     for k, (x, y) in enumerate(pts):
-        xs, ys, _ = window(x, y, n, steps)
+        xs, ys, _ = window(x, y, n, steps, ny)
         mom = assemble_rough(factors, xs, ys)
         ref = oracle_cell(mom, steps, lattice, **oracle_kw)
         err = float(np.abs(got[:, k] - ref).max())

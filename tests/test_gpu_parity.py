@@ -403,6 +403,34 @@ def test_full_size_sampled(case):
     s.close()
 
 
+def test_ragged_wide_fp32_sampled():
+    """The FP32 closure sweep with streaming stores on a grid whose strips,
+    segments and workgroup count are all ragged: 5000 x 1700 (1.3 GB of
+    state; ten 512-lane strips, the last 392 columns wide; with 256 compute
+    units 50 segments of 34 rows, 500 workgroups, which the XCD-contiguous
+    numbering splits 63 / 62 over the 8 XCDs).  Sampled cells at the corners,
+    at strip and segment edges and at random."""
+    nx, ny, nu, ghost, steps = 5000, 1700, 2e-4, 1.6, 3
+    _say("ragged wide fp32", nx, ny)
+    g4 = dict(s5=ghost, s6=ghost, s7=ghost, s8=ghost)
+    s = _sim(nx=nx, ny=ny, nu=nu, eta=nu, delta=4.0, dtype="fp32", b_ref=(ROUGH_MEAN[3], ROUGH_MEAN[4]), **g4)
+    factors = rough_factors(nx, ny, 13)
+    s.init_from_moments(assemble_rough_torch(factors, torch, s.device))
+    s._keep = None
+    rng = np.random.default_rng(14)
+    pts = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1), (511, 33), (512, 34), (4607, 67), (4608, 68),
+           (4999, 1666), (1023, 1665), (1024, 1699)]
+    pts += [(int(rng.integers(0, nx)), int(rng.integers(0, ny))) for _ in range(14)]
+    xs = torch.tensor([p[0] for p in pts], device=s.device)
+    ys = torch.tensor([p[1] for p in pts], device=s.device)
+    s.step(steps)
+    got = s.get_state()[:, ys, xs].cpu().numpy()
+    okw = dict(nu=nu, eta=nu, delta=4.0, **g4)
+    check_rough_sampled(got, pts, nx, steps, factors, FULL_TOL["fp32"], gaps=FULL_GAPS, say=_say, ny=ny, **okw)
+    assert s.diagnostics()["nonfinite"] == 0
+    s.close()
+
+
 def test_full_size_dns_jet_sampled():
     """The benchmark's closure-off sweep: 4096^2 DNS from the jet (initial
     state written on the device), 3 steps, 32 sampled cells."""
