@@ -142,6 +142,54 @@ def test_kh_64_fields(dtype, steps):
 
 @pytest.mark.parametrize("dtype", ["fp16", "bf16"])
 @pytest.mark.parametrize("delta", [0.0, 4.0])
+def test_ragged_wide_sampled(dtype, delta):
+    """Streaming stores on a ragged 5000 x 1701 grid (650 MB of 16-bit state):
+    the closure-off sweep's 256-cell row segments end with one of 136 cells
+    and its grid has 34 020 workgroups; the closure sweep's ten 512-lane
+    strips end with one of 392 columns, in 51 segments of 34 rows (510
+    workgroups).  Neither count is a multiple of the 8 XCDs over which the
+    workgroups are numbered.  The jet (B0 = 0.01, nu = eta = 1e-4) after 3
+    steps at cells on segment, strip and grid edges and at random, against
+    the oracle on a window around each; bound: 3 roundings of u * |deviation|."""
+    nx, ny, steps, nu, B0 = 5000, 1701, 3, 1e-4, 0.01
+    kh = dict(U0=0.05, delta_over_L=1 / 40, B0=B0, rho0=1.0, pert_amp_over_U0=1e-3, noise_amp=1e-5)
+    g4 = dict(s5=1.6, s6=1.6, s7=1.6, s8=1.6)
+    s = _sim(nx=nx, ny=ny, nu=nu, eta=nu, delta=delta, dtype=dtype, b_ref=(B0, 0.0), **g4)
+    s.init_kh_jet(seed=15, **kh)
+    d0 = s.diagnostics()
+    s.step(steps)
+    rng = np.random.default_rng(16)
+    pts = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1), (4863, 850), (4864, 851), (511, 33), (512, 34),
+           (4607, 1666), (4608, 1700), (255, 1699), (256, 425)]
+    pts += [(int(rng.integers(0, nx)), int(rng.integers(0, ny))) for _ in range(12)]
+    xs = torch.tensor([p[0] for p in pts], device=s.device)
+    ys = torch.tensor([p[1] for p in pts], device=s.device)
+    st = s.get_state()
+    got = st[:, ys, xs].cpu().numpy()
+    del st
+    win = 2 * (2 * steps + 1) + 1
+    half = win // 2
+    worst = 0.0
+    for k, (x, y) in enumerate(pts):
+        X, Y = np.meshgrid((x - half + np.arange(win)) % nx, (y - half + np.arange(win)) % ny)
+        f, g = O.kh_jet_populations(X, Y, nx, ny, seed=15, **kh)
+        o = O.Oracle(win, win, nu, nu, delta=delta, **g4)
+        o.set_state(f, g)
+        o.step(steps)
+        ref = pack(*o.state()[:2])[:, half, half]
+        dev = deviation(ref[:, None, None], B0)[:, 0, 0]
+        err = np.abs(got[:, k] - ref).max()
+        worst = max(worst, err / np.abs(dev).max())
+        assert err <= (steps + 1) * UNIT[dtype] * np.abs(dev).max() + 1e-6, (x, y, err)
+    print(f"{dtype} delta={delta} {nx}x{ny}: worst sampled error / max|deviation| = {worst:.2e}", flush=True)
+    d = s.diagnostics()
+    assert d["nonfinite"] == 0
+    assert abs(d["mass"] - d0["mass"]) <= steps * UNIT[dtype] * 0.05 * nx * ny
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["fp16", "bf16"])
+@pytest.mark.parametrize("delta", [0.0, 4.0])
 def test_full_size_8192_sampled(dtype, delta):
     """The 8192^2 jet (B0 = 0.01, nu = eta = 1e-4, MRT ghost rates 1.6) in the
     benchmark's launch configuration: 3 steps, 24 sampled cells against the
