@@ -140,3 +140,35 @@ def test_full_size_variants_sampled(variant):
     check_rough_sampled(got, pts, n, steps, factors, 1e-7, gaps=gaps, say=print,
                         nu=nu, eta=nu, delta=delta, grad_stencil=stencil, closure_time=ctime, **g4)
     s.close()
+
+
+RAGGED_VARIANTS = VARIANTS + [("stencil_aa", "aa", "iso9", "sync")]
+
+
+@pytest.mark.parametrize("variant", RAGGED_VARIANTS, ids=[v[0] for v in RAGGED_VARIANTS])
+def test_ragged_variants_sampled(variant):
+    """The same variants, and the in-place schedule with the stencil closure,
+    on a ragged 5000 x 1701 grid: the in-place kernels' 256-cell row segments
+    end with one of 136 cells and their grid has 34 020 workgroups (not a
+    multiple of the 8 XCDs they are numbered over).  3 steps from rough
+    fields, cells at segment and grid edges and at random."""
+    label, schedule, stencil, ctime = variant
+    nx, ny, nu, steps, delta = 5000, 1701, 2e-4, 3, 4.0
+    g4 = dict(s5=1.6, s6=1.6, s7=1.6, s8=1.6)
+    s = _sim(nx=nx, ny=ny, nu=nu, eta=nu, delta=delta, dtype="fp32", schedule=schedule, grad_stencil=stencil,
+             b_ref=(ROUGH_MEAN[3], ROUGH_MEAN[4]), **g4)
+    factors = rough_factors(nx, ny, 23)
+    s.init_from_moments(assemble_rough_torch(factors, torch, s.device))
+    s._keep = None
+    s.step(steps)
+    rng = np.random.default_rng(37)
+    pts = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1), (255, 850), (256, 851), (4863, 1700),
+           (4864, 33), (511, 34), (512, 1666)]
+    pts += [(int(rng.integers(0, nx)), int(rng.integers(0, ny))) for _ in range(10)]
+    xs = torch.tensor([q[0] for q in pts], device=s.device)
+    ys = torch.tensor([q[1] for q in pts], device=s.device)
+    got = s.get_state()[:, ys, xs].cpu().numpy()
+    gaps = [("no closure", dict(delta=0.0, grad_stencil="iso9", closure_time="sync"), 100.0)]
+    check_rough_sampled(got, pts, nx, steps, factors, 1e-7, gaps=gaps, say=print, ny=ny,
+                        nu=nu, eta=nu, delta=delta, grad_stencil=stencil, closure_time=ctime, **g4)
+    s.close()
