@@ -1174,7 +1174,7 @@ def main() -> int:
 
     last_dns, last_les = diag_log[-1] if diag_log else ({}, {})
     out = {
-        "metric": "MLUPS + % HBM roofline",
+        "metric": "MLUPS + % HBM roofline; learned vs plain closure at \u22642% spectrum error",
         "value": round(value, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
