@@ -126,6 +126,35 @@ def test_random_states_two_steps(shape, delta):
         assert e <= 1e-14, (t0, e)
 
 
+@pytest.mark.parametrize("shape", [(32767, 5), (32768, 4)])
+@pytest.mark.parametrize("delta", [0.0, 3.0])
+def test_widest_rows_fp32(shape, delta):
+    """FP32 storage at the widest rows the ABI accepts: with D2Q9 g a lattice
+    row holds 27 planes of 32768 floats (3.5 MB), the largest range one row's
+    buffer resource covers in the closure sweep (64 strips of 512 lanes, the
+    last one column short at 32767).  One step from a random state against
+    the oracle started from the state the GPU holds: within one rounding of
+    each output (2^-24 max|f|) plus FP32 arithmetic noise (1e-7)."""
+    nx, ny = shape
+    _say("d2q9 widest fp32", shape, delta)
+    f = perturbed(O.W9, (9, ny, nx), 23, 0.15)
+    g = offset_noise(np.zeros(18), (18, ny, nx), 24, 0.01).reshape(9, 2, ny, nx)
+    s = _sim(nx=nx, ny=ny, nu=0.02, eta=0.03, delta=delta, dtype="fp32", s5=1.3, s6=0.9, s7=1.7, s8=1.1)
+    s.set_state(pack(f, g), 0)
+    st0 = s.get_state().cpu().numpy()
+    s.step(1)
+    got = s.get_state().cpu().numpy()
+    o = O.Oracle(nx, ny, 0.02, 0.03, delta=delta, s5=1.3, s6=0.9, s7=1.7, s8=1.1, mag_lattice="d2q9")
+    o.set_state(st0[:9], np.stack([st0[9:18], st0[18:27]], axis=1))
+    o.step(1)
+    ref = pack(*o.state()[:2])
+    err = np.abs(got - ref).max()
+    bound = 2.0 ** -24 * np.abs(ref).max() + 1e-7
+    _say(f"  max error {err:.2e}, bound {bound:.2e}")
+    assert err <= bound
+    s.close()
+
+
 def test_density_gradient_closure_on_d2q9():
     nx, ny = 80, 36
     _say("d2q9 full closure")

@@ -176,7 +176,8 @@ def test_random_state_steps_fp64(case, schedule, t0):
 # Strip width and segment height on a 256-CU device: 1100 columns -> three
 # 512-lane strips (76 columns in the last), 85 segments per strip column; 700 ->
 # three 256-lane strips (188 in the last); 200 -> four 64-lane strips (8 in the last).
-TAIL_SHAPES = [(1100, 425), (1100, 340), (1100, 255), (700, 99), (200, 300)]  # rows 5, 4, 3, 2 (+1), 5
+TAIL_SHAPES = [(1100, 425), (1100, 340), (1100, 255), (700, 99), (200, 300),  # rows 5, 4, 3, 2 (+1), 5
+               (32768, 4), (32767, 5)]  # the widest rows: 64 strips, 2.5 MB per FP32 row; last strip 511
 TAIL_UNIT = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
 
 
