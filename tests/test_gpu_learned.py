@@ -398,6 +398,10 @@ _CORR_CASES.append((24, 18, False))
 # (512-, 256- and 64-lane strips) while its row segments run the three-row loop and
 # end with one or two rows (segments of 5, 4, 2 and 5 rows on a 256-CU device)
 _CORR_CASES += [(1100, 425, False), (1100, 340, False), (700, 99, False), (200, 300, False)]
+# the widest rows the ABI accepts: 64 input-vector strips per row (the last one
+# column short at 32767), network tiles shorter than the grid is wide, and a
+# grid fewer rows tall than a tile, so every tile's vertical halo wraps
+_CORR_CASES += [(32768, 4, False), (32767, 5, False)]
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32", "bf16"])
