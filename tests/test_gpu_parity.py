@@ -177,7 +177,8 @@ def test_random_state_steps_fp64(case, schedule, t0):
 # 512-lane strips (76 columns in the last), 85 segments per strip column; 700 ->
 # three 256-lane strips (188 in the last); 200 -> four 64-lane strips (8 in the last).
 TAIL_SHAPES = [(1100, 425), (1100, 340), (1100, 255), (700, 99), (200, 300),  # rows 5, 4, 3, 2 (+1), 5
-               (32768, 4), (32767, 5)]  # the widest rows: 64 strips, 2.5 MB per FP32 row; last strip 511
+               (32768, 4), (32767, 5),  # the widest rows: 64 strips, 2.5 MB per FP32 row; last strip 511
+               (4, 600), (5, 37)]  # the narrowest: one 64-lane strip, 4 or 5 valid lanes, both halos wrap
 TAIL_UNIT = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
 
 
