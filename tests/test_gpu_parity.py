@@ -219,6 +219,41 @@ def test_closure_sweep_strip_and_segment_tails(dtype, shape):
     s.close()
 
 
+UNIFORM_UNIT = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("schedule", ["fused", "aa", "aa_lagged"])
+@pytest.mark.parametrize("delta", [0.0, 4.0])
+def test_uniform_state_is_a_fixed_point(dtype, schedule, delta):
+    """A uniform state (rho = 1.02, u = (0.03, -0.02), B = (0.01, 0.005)) is a
+    fixed point of streaming and collision (Sec. 2: the equilibria of its
+    own moments), and the closure adds nothing (every gradient vanishes).
+    After 50 steps every cell's moments must equal the initial ones up to the
+    rounding of the stored values: at most one rounding (unit u) of each of
+    the 19 stored values per step, of size at most max|f| (FP64, FP32) or
+    max|deviation| (16-bit storage), accumulated linearly: 50 * 19 * u * that."""
+    nx, ny, steps = 67, 45, 50
+    rho, u, B = 1.02, (0.03, -0.02), (0.01, 0.005)
+    mom = np.empty((5, ny, nx))
+    mom[0], mom[1], mom[2], mom[3], mom[4] = rho, rho * u[0], rho * u[1], B[0], B[1]
+    s = _sim(nx=nx, ny=ny, nu=0.02, eta=0.03, delta=delta, dtype=dtype, schedule=schedule, b_ref=B)
+    s.init_from_moments(torch.from_numpy(mom))
+    m0 = s.moments().cpu().numpy()
+    st0 = s.get_state().cpu().numpy()
+    s.step(steps)
+    m1 = s.moments().cpu().numpy()
+    assert s.diagnostics()["nonfinite"] == 0
+    ref = np.concatenate([O.W9, O.W5 * B[0], O.W5 * B[1]])[:, None, None]  # what 16-bit storage subtracts
+    size = np.abs(st0).max() if dtype in ("fp64", "fp32") else np.abs(st0 - ref).max()
+    bound = steps * 19 * UNIFORM_UNIT[dtype] * size
+    drift = np.abs(m1 - m0).max()
+    spread = (m1.max(axis=(1, 2)) - m1.min(axis=(1, 2))).max()
+    _say(f"uniform {dtype} {schedule} delta={delta}: drift {drift:.2e}, spread {spread:.2e}, bound {bound:.2e}")
+    assert drift <= bound and spread <= bound
+    s.close()
+
+
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
 @pytest.mark.parametrize("schedule", ["fused", "aa"])
 @pytest.mark.parametrize("t0", [0, 3])
