@@ -1394,7 +1394,9 @@ k_cell_inputs_f(const S* __restrict__ src, int nx, int ny, int64_t pitch, int ry
       u32x4 w = __builtin_bit_cast(u32x4, to_bf16x8(z));
       w[3] = (w[3] & 0xFFFFu) | (bad ? unsigned(kCellOutOfRange) << 16 : 0u);
       const __amdgpu_buffer_rsrc_t d = row_rsrc(reinterpret_cast<char*>(out) + int64_t(y) * orow, orow);
-      __builtin_amdgcn_raw_buffer_store_b128(w, d, int(xo_store), 0, 0);
+      // non-temporal: the network kernel reads the vectors back after the
+      // whole grid is written (16384^2 learned step 0.5-1 % faster, 1024^2 no slower)
+      __builtin_amdgcn_raw_buffer_store_b128(w, d, int(xo_store), 0, 2);
     }
     __syncthreads();
   };

@@ -212,10 +212,13 @@ k_mlp_correct(const CellIn* __restrict__ in, const char* __restrict__ pk, float*
     const int gx = x0 + tx, gy = y0 + ty;
     if (h == 0 && gx < nx && gy < ny) {
       float* cp = corr + ((int64_t)gy * nx + gx);
-      cp[0] = o ? 0.0f : y[0] * os0;
-      cp[n] = o ? 0.0f : y[1] * os1;
-      cp[2 * n] = o ? 0.0f : y[2] * os2;
-      cp[3 * n] = o ? 0.0f : y[3] * os3;
+      // non-temporal stores: the planes are read by the next sweep, after the
+      // whole grid is written (measured together with the input vectors'
+      // non-temporal stores: the 16384^2 learned step 0.5-1 % faster)
+      __builtin_nontemporal_store(o ? 0.0f : y[0] * os0, cp);
+      __builtin_nontemporal_store(o ? 0.0f : y[1] * os1, cp + n);
+      __builtin_nontemporal_store(o ? 0.0f : y[2] * os2, cp + 2 * n);
+      __builtin_nontemporal_store(o ? 0.0f : y[3] * os3, cp + 3 * n);
     }
   }
 }
